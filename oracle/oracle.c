@@ -1,0 +1,840 @@
+/*
+ * oracle.c -- plain FP64 CPU reference of the hash-grid secondary-ray renderer.
+ *
+ * TEST INFRASTRUCTURE.  Only the tests, the smoke check and the benchmark's
+ * CPU-baseline leg may load this library.  It shares no code, header, table
+ * or constant generator with the HIP path; both receive the same seeded
+ * inputs (FP32 masters) and each implements the counter-based generator
+ * Philox4x32-10 from its published definition.
+ *
+ * What is computed (paper: "Baking Relightable NeRF for Real-time
+ * Direct/Indirect Illumination Rendering", arXiv 2409.10327):
+ *   - hash-grid encoder f = H(x), multi-level tables as InstantNGP
+ *     (Sec. 3.2 "Indirect Illumination Renderer", Sec. 4.1 settings);
+ *   - BRDF decoder B(f) -> albedo, roughness (0.09 + 0.91 sigmoid), metallic
+ *     (Sec. 3.2; output mapping in Sec. 3.3);
+ *   - implicit ray tracer I(f, w) -> visibility (sigmoid) and depth
+ *     min-max normalised to [near, far] with outputs clamped to 1
+ *     (Sec. 3.2 items 1-2; near/far from the supplementary training details);
+ *   - one recursive bounce at x' = x + t w with 8 secondary rays
+ *     (Sec. 3.1, Sec. 3.2 "Overview", supplementary "Rendering Details");
+ *   - incoming radiance of Eq. (2) and the Monte Carlo rendering equation
+ *     Eq. (1) over environment-map light (Sec. 2.2);
+ *   - microfacet BRDF: Lambert diffuse + GGX (alpha = r^2), Schlick Fresnel,
+ *     height-correlated Smith visibility (Sec. 4.1, Sec. 4.2, supplementary
+ *     roughness-remapping ablation);
+ *   - L2 distillation loss, its analytic gradient and Adam.
+ * Readings where the paper is silent are stated next to each function.
+ *
+ * Everything is evaluated in double precision from FP32 inputs, in the
+ * plainest order, with OpenMP only over independent points.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+#define OR_MAXF 64      /* max L*F */
+#define OR_MAXIN 67     /* max L*F + 3 */
+#define OR_MAXH 64      /* hidden width */
+#define OR_MAXOUT 8
+#define OR_MAXL 32
+#define OR_MAXN2 64     /* max secondary directions */
+
+#define OR_DIFFUSE_ONLY 1u
+
+typedef struct {
+    int32_t L, F, log2_T;
+    int32_t res[OR_MAXL];
+    double lo, extent;
+    const float *table; /* [L][T][F] */
+} or_grid;
+
+typedef struct {
+    int32_t n_in, n_hidden, n_out;
+    const float *W0, *b0, *W1, *b1, *W2, *b2; /* W[k]: [out][in] */
+} or_mlp;
+
+typedef struct {
+    or_grid grid;
+    or_mlp brdf, irt;
+    double t_near, t_far, f0;
+} or_model;
+
+typedef struct {
+    int32_t H, W;
+    const float *rgb; /* [H][W][3] */
+} or_env;
+
+typedef struct {
+    int32_t n_dirs, n_dirs2;
+    uint64_t seed;
+    uint32_t flags;
+} or_sampling;
+
+typedef struct {
+    int64_t n;
+    const float *pos, *nrm, *wo, *dir; /* [n][3]; dir != NULL selects query mode */
+} or_points;
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw: "Parallel random numbers: as   */
+/* easy as 1, 2, 3", SC'11).  Ten rounds; each round multiplies counter     */
+/* words 0 and 2 by the round multipliers, mixes the high halves with the   */
+/* other two words and the key, and the key is bumped by the Weyl constants */
+/* between rounds.                                                          */
+/* ------------------------------------------------------------------------ */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Stratified cosine-weighted direction about a unit normal n.              */
+/* Reading: the paper samples light directions with stratified sampling     */
+/* (supplementary training and rendering details) and evaluates Eq. (1)     */
+/* with the sampling pdf.  Directions are drawn from a cosine-weighted      */
+/* hemisphere (pdf = cos/pi) with N = n_a x n_b strata, n_a = 2^floor(log2  */
+/* N / 2).  Sample k lies in stratum (k / n_b, k % n_b).                     */
+/* The uniforms come from Philox4x32-10 with key = seed and counter         */
+/* (pid, q, k >> 2, tag); word k & 3 is split into two 16-bit halves and    */
+/* each is mapped to the centre of its 2^-16 bin.                           */
+/* Disk-to-hemisphere mapping (Malley's method); orthonormal basis of       */
+/* Duff et al., "Building an Orthonormal Basis, Revisited", JCGT 2017.      */
+/* ------------------------------------------------------------------------ */
+static void onb(const double n[3], double t[3], double b[3])
+{
+    double sgn = copysign(1.0, n[2]);
+    double a = -1.0 / (sgn + n[2]);
+    double bb = n[0] * n[1] * a;
+    t[0] = 1.0 + sgn * n[0] * n[0] * a;
+    t[1] = sgn * bb;
+    t[2] = -sgn * n[0];
+    b[0] = bb;
+    b[1] = sgn + n[1] * n[1] * a;
+    b[2] = -n[1];
+}
+
+static int ilog2(int n)
+{
+    int l = 0;
+    while ((1 << (l + 1)) <= n) ++l;
+    return l;
+}
+
+static void uniforms(uint64_t seed, uint32_t pid, uint32_t q, uint32_t k, uint32_t tag,
+                     double *u1, double *u2)
+{
+    uint32_t ctr[4] = {pid, q, k >> 2, tag};
+    uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+    uint32_t o[4];
+    or_philox4x32_10(ctr, key, o);
+    uint32_t w = o[k & 3u];
+    *u1 = ((double)(w & 0xffffu) + 0.5) / 65536.0;
+    *u2 = ((double)(w >> 16) + 0.5) / 65536.0;
+}
+
+static void sample_dir(uint64_t seed, uint32_t pid, uint32_t q, uint32_t k, uint32_t tag,
+                       int nstrata, const double n[3], double w[3])
+{
+    double u1, u2;
+    uniforms(seed, pid, q, k, tag, &u1, &u2);
+    int na = 1 << (ilog2(nstrata) / 2);
+    int nb = nstrata / na;
+    int a = (int)k / nb, b = (int)k % nb;
+    double s1 = (a + u1) / na;
+    double s2 = (b + u2) / nb;
+    double r = sqrt(s1), ph = 2.0 * M_PI * s2;
+    double lx = r * cos(ph), ly = r * sin(ph), lz = sqrt(1.0 - s1);
+    double t[3], bt[3];
+    onb(n, t, bt);
+    for (int d = 0; d < 3; ++d) w[d] = lx * t[d] + ly * bt[d] + lz * n[d];
+}
+
+void or_sample_dirs(uint64_t seed, const double *nrm, const uint32_t *pid, const uint32_t *q,
+                    const uint32_t *k, uint32_t tag, int32_t nstrata, int64_t n, double *out)
+{
+    for (int64_t i = 0; i < n; ++i)
+        sample_dir(seed, pid[i], q[i], k[i], tag, nstrata, nrm + 3 * i, out + 3 * i);
+}
+
+void or_uniforms(uint64_t seed, const uint32_t *pid, const uint32_t *q, const uint32_t *k,
+                 uint32_t tag, int64_t n, double *out)
+{
+    for (int64_t i = 0; i < n; ++i) uniforms(seed, pid[i], q[i], k[i], tag, out + 2 * i, out + 2 * i + 1);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Hash-grid encoder H (InstantNGP multi-resolution tables, Sec. 3.2).      */
+/* Reading: positions in the cube [lo, lo+extent]^3 map to u in [0,1]^3,    */
+/* clamped.  For FP32 positions the subtraction x - lo is rounded to FP32   */
+/* (the extent is a power of two, so the division is exact); positions     */
+/* computed here in FP64 (bounce points) use u in FP64.  At level l with    */
+/* resolution N_l: p = u N_l, cell c = min(floor(p), N_l - 1), w = p - c.   */
+/* Vertex index: dense row-major when (N_l+1)^3 <= T, otherwise the spatial */
+/* hash of Mueller et al. 2022 (Eq. 4): xor of coordinates times primes     */
+/* (1, 2654435761, 805459861) modulo 2^32, masked to T.  Trilinear blend;   */
+/* features concatenated level-major.                                       */
+/* ------------------------------------------------------------------------ */
+static uint32_t vertex_index(int N, uint32_t T, uint32_t vx, uint32_t vy, uint32_t vz)
+{
+    uint64_t s = (uint64_t)(N + 1);
+    if (s * s * s <= (uint64_t)T)
+        return (uint32_t)(vx + s * (vy + s * vz));
+    uint32_t h = (vx * 1u) ^ (vy * 2654435761u) ^ (vz * 805459861u);
+    return h & (T - 1u);
+}
+
+typedef struct {
+    uint32_t idx[OR_MAXL][8];
+    double w[OR_MAXL][3];     /* fractional position inside the cell */
+    int inside[3];            /* 1 if u was not clamped (gradient passes) */
+} enc_rec;
+
+static void encode_u(const or_grid *g, const double u_raw[3], double *f, enc_rec *rec)
+{
+    const uint32_t T = 1u << g->log2_T;
+    double u[3];
+    for (int d = 0; d < 3; ++d) {
+        u[d] = u_raw[d] < 0.0 ? 0.0 : (u_raw[d] > 1.0 ? 1.0 : u_raw[d]);
+        if (rec) rec->inside[d] = (u_raw[d] > 0.0 && u_raw[d] < 1.0);
+    }
+    for (int l = 0; l < g->L; ++l) {
+        int N = g->res[l];
+        uint32_t c[3];
+        double w[3];
+        for (int d = 0; d < 3; ++d) {
+            double p = u[d] * N;
+            double cf = floor(p);
+            if (cf > N - 1) cf = N - 1;
+            c[d] = (uint32_t)cf;
+            w[d] = p - cf;
+        }
+        for (int k = 0; k < g->F; ++k) f[l * g->F + k] = 0.0;
+        for (int corner = 0; corner < 8; ++corner) {
+            int dx = corner & 1, dy = (corner >> 1) & 1, dz = (corner >> 2) & 1;
+            uint32_t idx = vertex_index(N, T, c[0] + dx, c[1] + dy, c[2] + dz);
+            double wt = (dx ? w[0] : 1.0 - w[0]) * (dy ? w[1] : 1.0 - w[1]) * (dz ? w[2] : 1.0 - w[2]);
+            const float *e = g->table + ((size_t)l * T + idx) * g->F;
+            for (int k = 0; k < g->F; ++k) f[l * g->F + k] += wt * (double)e[k];
+            if (rec) rec->idx[l][corner] = idx;
+        }
+        if (rec)
+            for (int d = 0; d < 3; ++d) rec->w[l][d] = w[d];
+    }
+}
+
+static void pos_to_u_f32(const or_grid *g, const float x[3], double u[3])
+{
+    float lo = (float)g->lo;
+    for (int d = 0; d < 3; ++d) {
+        float s = x[d] - lo; /* rounded to FP32 */
+        u[d] = (double)s / g->extent;
+    }
+}
+
+static void pos_to_u_f64(const or_grid *g, const double x[3], double u[3])
+{
+    for (int d = 0; d < 3; ++d) u[d] = (x[d] - g->lo) / g->extent;
+}
+
+void or_encode(const or_grid *g, const float *pos, int64_t n, double *feat)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double u[3];
+        pos_to_u_f32(g, pos + 3 * i, u);
+        encode_u(g, u, feat + (size_t)i * g->L * g->F, NULL);
+    }
+}
+
+/* Encode at FP64 positions (used to pin bounce-point encodes). */
+void or_encode_f64(const or_grid *g, const double *pos, int64_t n, double *feat)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double u[3];
+        pos_to_u_f64(g, pos + 3 * i, u);
+        encode_u(g, u, feat + (size_t)i * g->L * g->F, NULL);
+    }
+}
+
+/* Vertex indices [n][L][8] (corner bit 0 = +x, bit 1 = +y, bit 2 = +z) and
+ * in-cell weights [n][L][3] for FP32 positions. */
+void or_encode_index(const or_grid *g, const float *pos, int64_t n, uint32_t *idx, double *wts)
+{
+    double f[OR_MAXF];
+#pragma omp parallel for schedule(static) private(f)
+    for (int64_t i = 0; i < n; ++i) {
+        double u[3];
+        enc_rec rec;
+        pos_to_u_f32(g, pos + 3 * i, u);
+        encode_u(g, u, f, &rec);
+        for (int l = 0; l < g->L; ++l) {
+            for (int c = 0; c < 8; ++c) idx[((size_t)i * g->L + l) * 8 + c] = rec.idx[l][c];
+            if (wts)
+                for (int d = 0; d < 3; ++d) wts[((size_t)i * g->L + l) * 3 + d] = rec.w[l][d];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Three-layer MLP with ReLU hidden activations (Sec. 4.1: 3 layers, width  */
+/* 64).  W[k] is stored [out][in].                                          */
+/* ------------------------------------------------------------------------ */
+static void linear(const float *W, const float *b, int n_out, int n_in, const double *x, double *y)
+{
+    for (int o = 0; o < n_out; ++o) {
+        double acc = (double)b[o];
+        for (int i = 0; i < n_in; ++i) acc += (double)W[(size_t)o * n_in + i] * x[i];
+        y[o] = acc;
+    }
+}
+
+static void mlp_fwd(const or_mlp *m, const double *in, double *h1, double *h2, double *out)
+{
+    linear(m->W0, m->b0, m->n_hidden, m->n_in, in, h1);
+    for (int k = 0; k < m->n_hidden; ++k) h1[k] = h1[k] > 0.0 ? h1[k] : 0.0;
+    linear(m->W1, m->b1, m->n_hidden, m->n_hidden, h1, h2);
+    for (int k = 0; k < m->n_hidden; ++k) h2[k] = h2[k] > 0.0 ? h2[k] : 0.0;
+    linear(m->W2, m->b2, m->n_out, m->n_hidden, h2, out);
+}
+
+void or_mlp_forward(const or_mlp *m, const double *in, int64_t n, double *out)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double h1[OR_MAXH], h2[OR_MAXH];
+        mlp_fwd(m, in + (size_t)i * m->n_in, h1, h2, out + (size_t)i * m->n_out);
+    }
+}
+
+/* Gradient of one MLP evaluation: accumulates parameter gradients into
+ * g (packed W0,b0,W1,b1,W2,b2) and returns d/d(input) in gin. */
+static void mlp_bwd(const or_mlp *m, const double *in, const double *h1, const double *h2,
+                    const double *gout, double *g, double *gin)
+{
+    const int ni = m->n_in, nh = m->n_hidden, no = m->n_out;
+    double *gW0 = g, *gb0 = gW0 + nh * ni, *gW1 = gb0 + nh, *gb1 = gW1 + nh * nh;
+    double *gW2 = gb1 + nh, *gb2 = gW2 + no * nh;
+    double gp2[OR_MAXH], gp1[OR_MAXH];
+    for (int o = 0; o < no; ++o) {
+        gb2[o] += gout[o];
+        for (int k = 0; k < nh; ++k) gW2[o * nh + k] += gout[o] * h2[k];
+    }
+    for (int k = 0; k < nh; ++k) {
+        double s = 0.0;
+        for (int o = 0; o < no; ++o) s += (double)m->W2[o * nh + k] * gout[o];
+        gp2[k] = h2[k] > 0.0 ? s : 0.0;
+    }
+    for (int k = 0; k < nh; ++k) {
+        gb1[k] += gp2[k];
+        for (int j = 0; j < nh; ++j) gW1[k * nh + j] += gp2[k] * h1[j];
+    }
+    for (int j = 0; j < nh; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < nh; ++k) s += (double)m->W1[k * nh + j] * gp2[k];
+        gp1[j] = h1[j] > 0.0 ? s : 0.0;
+    }
+    for (int j = 0; j < nh; ++j) {
+        gb0[j] += gp1[j];
+        for (int i = 0; i < ni; ++i) gW0[j * ni + i] += gp1[j] * in[i];
+    }
+    for (int i = 0; i < ni; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < nh; ++j) s += (double)m->W0[j * ni + i] * gp1[j];
+        gin[i] = s;
+    }
+}
+
+static int64_t mlp_nparams(const or_mlp *m)
+{
+    return (int64_t)m->n_hidden * m->n_in + m->n_hidden + (int64_t)m->n_hidden * m->n_hidden +
+           m->n_hidden + (int64_t)m->n_out * m->n_hidden + m->n_out;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Output heads.                                                            */
+/* B: albedo = sigmoid, roughness = 0.09 + 0.91 sigmoid (Sec. 3.3),         */
+/*    metallic = sigmoid.                                                   */
+/* I: V = sigmoid(o0) (Sec. 3.3: sigmoid maps visibility to [0,1]);         */
+/*    depth d = min(softplus(o1), 1) -- min-max normalised depth clamped to */
+/*    1 = far (Sec. 3.2 item 2); t = near + (far - near) d.                 */
+/* ------------------------------------------------------------------------ */
+static double sigmoid(double z) { return 1.0 / (1.0 + exp(-z)); }
+static double softplus(double z) { return (z > 0.0 ? z : 0.0) + log1p(exp(-fabs(z))); }
+
+/* ------------------------------------------------------------------------ */
+/* Environment lookup (image-based lighting, Sec. 2.2: the incoming        */
+/* radiance is interpolated from the equirectangular map).  Reading: y is   */
+/* up; azimuth phi = atan2(w_z, w_x), polar angle theta from +y computed as */
+/* atan2(sqrt(w_x^2 + w_z^2), w_y); texel centres at +1/2; bilinear,        */
+/* columns wrap, rows clamp.                                                */
+/* ------------------------------------------------------------------------ */
+static void env_lookup(const or_env *e, const double w[3], double out[3])
+{
+    const int H = e->H, W = e->W;
+    double phi = atan2(w[2], w[0]);
+    double th = atan2(sqrt(w[0] * w[0] + w[2] * w[2]), w[1]);
+    double s = (phi + M_PI) / (2.0 * M_PI) * W - 0.5;
+    double q = th / M_PI * H - 0.5;
+    double xf = floor(s), yf = floor(q);
+    double fx = s - xf, fy = q - yf;
+    long x0 = (long)xf;
+    x0 = ((x0 % W) + W) % W;
+    long x1 = (x0 + 1) % W;
+    long y0 = (long)yf, y1 = y0 + 1;
+    if (y0 < 0) y0 = 0;
+    if (y0 > H - 1) y0 = H - 1;
+    if (y1 < 0) y1 = 0;
+    if (y1 > H - 1) y1 = H - 1;
+    for (int c = 0; c < 3; ++c) {
+        double e00 = e->rgb[(y0 * W + x0) * 3 + c], e01 = e->rgb[(y0 * W + x1) * 3 + c];
+        double e10 = e->rgb[(y1 * W + x0) * 3 + c], e11 = e->rgb[(y1 * W + x1) * 3 + c];
+        out[c] = (1.0 - fy) * ((1.0 - fx) * e00 + fx * e01) + fy * ((1.0 - fx) * e10 + fx * e11);
+    }
+}
+
+void or_env_lookup(const or_env *e, const double *dirs, int64_t n, double *out)
+{
+    for (int64_t i = 0; i < n; ++i) env_lookup(e, dirs + 3 * i, out + 3 * i);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Microfacet BRDF f_r(n, v, l; a, r, m).                                   */
+/* Diffuse: Lambert (1-m) a / pi ("simplified Disney" albedo term).         */
+/* Specular: GGX D with alpha = r^2, Schlick Fresnel with F0 = mix(f0, a,   */
+/* m) (f0 = 0.04, Sec. 5), height-correlated Smith visibility (Sec. 4.2 and */
+/* the supplementary roughness-remapping ablation).  NdotL <= 0 returns 0;  */
+/* NdotV is clamped below at 1e-4.  With the diffuse-only flag the value is */
+/* a / pi.  Also returns d f / d a (per channel), d f / d r, d f / d m.      */
+/* ------------------------------------------------------------------------ */
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+static void brdf_eval(const double n[3], const double v[3], const double l[3], const double a[3],
+                      double r, double m, double f0, int diffuse_only, double f[3],
+                      double dfa[3], double dfr[3], double dfm[3])
+{
+    double NdotL = dot3(n, l);
+    if (NdotL <= 0.0) {
+        for (int c = 0; c < 3; ++c) f[c] = dfa[c] = dfr[c] = dfm[c] = 0.0;
+        return;
+    }
+    if (diffuse_only) {
+        for (int c = 0; c < 3; ++c) {
+            f[c] = a[c] / M_PI;
+            dfa[c] = 1.0 / M_PI;
+            dfr[c] = dfm[c] = 0.0;
+        }
+        return;
+    }
+    double NdotV = dot3(n, v);
+    if (NdotV < 1e-4) NdotV = 1e-4;
+    double h[3] = {l[0] + v[0], l[1] + v[1], l[2] + v[2]};
+    double hn = sqrt(dot3(h, h));
+    if (hn > 0.0) {
+        for (int d = 0; d < 3; ++d) h[d] /= hn;
+    } else {
+        for (int d = 0; d < 3; ++d) h[d] = n[d];
+    }
+    double NdotH = dot3(n, h);
+    if (NdotH < 0.0) NdotH = 0.0;
+    double VdotH = dot3(v, h);
+    if (VdotH < 0.0) VdotH = 0.0;
+    double alpha = r * r, a2 = alpha * alpha;
+    double Q = NdotH * NdotH * (a2 - 1.0) + 1.0;
+    double D = a2 / (M_PI * Q * Q);
+    double sv = sqrt(NdotV * NdotV * (1.0 - a2) + a2);
+    double sl = sqrt(NdotL * NdotL * (1.0 - a2) + a2);
+    double A = NdotL * sv, B = NdotV * sl;
+    double Vis = 0.5 / (A + B);
+    double P = pow(1.0 - VdotH, 5.0);
+    /* derivatives with respect to a2 = r^4 */
+    double dD_da2 = (Q - 2.0 * a2 * NdotH * NdotH) / (M_PI * Q * Q * Q);
+    double dA_da2 = NdotL * (1.0 - NdotV * NdotV) / (2.0 * sv);
+    double dB_da2 = NdotV * (1.0 - NdotL * NdotL) / (2.0 * sl);
+    double dVis_da2 = -0.5 * (dA_da2 + dB_da2) / ((A + B) * (A + B));
+    double da2_dr = 4.0 * r * r * r;
+    for (int c = 0; c < 3; ++c) {
+        double F0 = f0 * (1.0 - m) + a[c] * m;
+        double F = F0 + (1.0 - F0) * P;
+        f[c] = (1.0 - m) * a[c] / M_PI + D * F * Vis;
+        dfa[c] = (1.0 - m) / M_PI + D * Vis * (1.0 - P) * m;
+        dfm[c] = -a[c] / M_PI + D * Vis * (1.0 - P) * (a[c] - f0);
+        dfr[c] = F * (dD_da2 * Vis + D * dVis_da2) * da2_dr;
+    }
+}
+
+void or_brdf(const double *n, const double *v, const double *l, const double *a, const double *r,
+             const double *m, double f0, int32_t diffuse_only, int64_t cnt, double *f, double *dfa,
+             double *dfr, double *dfm)
+{
+    for (int64_t i = 0; i < cnt; ++i) {
+        double t1[3], t2[3], t3[3];
+        brdf_eval(n + 3 * i, v + 3 * i, l + 3 * i, a + 3 * i, r[i], m[i], f0, diffuse_only,
+                  f + 3 * i, dfa ? dfa + 3 * i : t1, dfr ? dfr + 3 * i : t2, dfm ? dfm + 3 * i : t3);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Incoming radiance along (x, w): Eq. (2).                                 */
+/*   V, d from I(f(x), w); x' = x + t w (Sec. 3.1).                          */
+/*   Bounce (Sec. 3.2 "Overview"): f' = H(x'), (a', r', m') = B(f'), N'     */
+/*   new directions about n' with visibility V'_j = sigmoid(I(f', w'_j)_0); */
+/*   L'_o = 1/N' sum_j pi f_r(n', v', w'_j) V'_j L_env(w'_j).               */
+/*   Reading: the decoder has no normal head, so the secondary surface      */
+/*   faces the tracer, n' = v' = -w; visibility is used soft (sigmoid) in    */
+/*   Eq. (2) and the bounce is evaluated for every direction, weighted by   */
+/*   (1 - V).                                                               */
+/*   L_in = V L_env(w) + (1 - V) L'_o; direct-only: L_in = V L_env(w).       */
+/* ------------------------------------------------------------------------ */
+static void incoming(const or_model *M, const or_env *E, const or_sampling *S, int indirect,
+                     const double *f, const float *x, const double w[3], uint32_t pid, uint32_t q,
+                     double Lin[3], double *V, double *dep)
+{
+    const or_grid *g = &M->grid;
+    const int nf = g->L * g->F;
+    double z[OR_MAXIN], h1[OR_MAXH], h2[OR_MAXH], o[OR_MAXOUT];
+    for (int i = 0; i < nf; ++i) z[i] = f[i];
+    z[nf] = w[0]; z[nf + 1] = w[1]; z[nf + 2] = w[2];
+    mlp_fwd(&M->irt, z, h1, h2, o);
+    double vis = sigmoid(o[0]);
+    double sp = softplus(o[1]);
+    double d = sp < 1.0 ? sp : 1.0;
+    double t = M->t_near + (M->t_far - M->t_near) * d;
+    double Le[3];
+    env_lookup(E, w, Le);
+    *V = vis;
+    *dep = d;
+    if (!indirect) {
+        for (int c = 0; c < 3; ++c) Lin[c] = vis * Le[c];
+        return;
+    }
+    double xb[3], u[3], fb[OR_MAXF], ob[OR_MAXOUT];
+    for (int k = 0; k < 3; ++k) xb[k] = (double)x[k] + t * w[k];
+    pos_to_u_f64(g, xb, u);
+    encode_u(g, u, fb, NULL);
+    mlp_fwd(&M->brdf, fb, h1, h2, ob);
+    double ab[3] = {sigmoid(ob[0]), sigmoid(ob[1]), sigmoid(ob[2])};
+    double rb = 0.09 + 0.91 * sigmoid(ob[3]);
+    double mb = sigmoid(ob[4]);
+    double nb[3] = {-w[0], -w[1], -w[2]};
+    double Lo[3] = {0, 0, 0};
+    const int N2 = S->n_dirs2;
+    for (int j = 0; j < N2; ++j) {
+        double wj[3], Ej[3], fr[3], t1[3], t2[3], t3[3];
+        sample_dir(S->seed, pid, q, (uint32_t)j, 1u, N2, nb, wj);
+        for (int i = 0; i < nf; ++i) z[i] = fb[i];
+        z[nf] = wj[0]; z[nf + 1] = wj[1]; z[nf + 2] = wj[2];
+        mlp_fwd(&M->irt, z, h1, h2, o);
+        double vj = sigmoid(o[0]);
+        env_lookup(E, wj, Ej);
+        brdf_eval(nb, nb, wj, ab, rb, mb, M->f0, (S->flags & OR_DIFFUSE_ONLY) != 0, fr, t1, t2, t3);
+        for (int c = 0; c < 3; ++c) Lo[c] += M_PI * fr[c] * vj * Ej[c];
+    }
+    for (int c = 0; c < 3; ++c) {
+        Lo[c] /= N2;
+        Lin[c] = vis * Le[c] + (1.0 - vis) * Lo[c];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Rendering.                                                               */
+/* Shade mode (P->dir == NULL): Eq. (1) at each primary point with N        */
+/* cosine-distributed directions; with pdf = cos/pi every sample carries    */
+/* the weight pi f_r.  (a, r, m) = B(H(x)), normal and view from the input. */
+/*   rgb[p] = 1/N sum_i pi f_r(n, w_o, w_i) L_in(x, w_i);                    */
+/*   vis/depth (optional) [p][N] hold V and d of each direction.            */
+/* Query mode (P->dir != NULL): rgb[p] = L_in(x_p, dir_p), vis[p] = V,       */
+/*   depth[p] = d (the distillation outputs, Sec. 3.3).                      */
+/* ------------------------------------------------------------------------ */
+void or_render(const or_model *M, const or_env *E, const or_sampling *S, const or_points *P,
+               int32_t indirect, double *rgb, double *vis, double *depth)
+{
+    const or_grid *g = &M->grid;
+    const int nf = g->L * g->F;
+    const int query = P->dir != NULL;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t p = 0; p < P->n; ++p) {
+        double f[OR_MAXF], u[3];
+        const float *x = P->pos + 3 * p;
+        pos_to_u_f32(g, x, u);
+        encode_u(g, u, f, NULL);
+        if (query) {
+            double w[3] = {P->dir[3 * p], P->dir[3 * p + 1], P->dir[3 * p + 2]};
+            double Lin[3], V, d;
+            incoming(M, E, S, indirect, f, x, w, (uint32_t)p, 0u, Lin, &V, &d);
+            for (int c = 0; c < 3; ++c) rgb[3 * p + c] = Lin[c];
+            if (vis) vis[p] = V;
+            if (depth) depth[p] = d;
+            continue;
+        }
+        double h1[OR_MAXH], h2[OR_MAXH], ob[OR_MAXOUT];
+        mlp_fwd(&M->brdf, f, h1, h2, ob);
+        double a[3] = {sigmoid(ob[0]), sigmoid(ob[1]), sigmoid(ob[2])};
+        double r = 0.09 + 0.91 * sigmoid(ob[3]);
+        double m = sigmoid(ob[4]);
+        double n[3] = {P->nrm[3 * p], P->nrm[3 * p + 1], P->nrm[3 * p + 2]};
+        double v[3] = {P->wo[3 * p], P->wo[3 * p + 1], P->wo[3 * p + 2]};
+        double Lo[3] = {0, 0, 0};
+        const int N = S->n_dirs;
+        for (int i = 0; i < N; ++i) {
+            double w[3], Lin[3], V, d, fr[3], t1[3], t2[3], t3[3];
+            sample_dir(S->seed, (uint32_t)p, 0u, (uint32_t)i, 0u, N, n, w);
+            incoming(M, E, S, indirect, f, x, w, (uint32_t)p, (uint32_t)i, Lin, &V, &d);
+            brdf_eval(n, v, w, a, r, m, M->f0, (S->flags & OR_DIFFUSE_ONLY) != 0, fr, t1, t2, t3);
+            for (int c = 0; c < 3; ++c) Lo[c] += M_PI * fr[c] * Lin[c];
+            if (vis) vis[p * N + i] = V;
+            if (depth) depth[p * N + i] = d;
+        }
+        for (int c = 0; c < 3; ++c) rgb[3 * p + c] = Lo[c] / N;
+    }
+    (void)nf;
+}
+
+/* ------------------------------------------------------------------------ */
+/* L2 distillation loss (reading of Sec. 3.3 with squared errors):          */
+/*   loss = 1/n sum_p [ sum_c (rgb - t_c)^2 + (vis - t_3)^2 + (d - t_4)^2 ]  */
+/* Returns the loss; writes its gradient with respect to each prediction.   */
+/* ------------------------------------------------------------------------ */
+double or_l2_loss(const float *rgb, const float *vis, const float *dep, const float *tgt, int64_t n,
+                  double *g_rgb, double *g_vis, double *g_dep)
+{
+    double loss = 0.0;
+    for (int64_t p = 0; p < n; ++p) {
+        for (int c = 0; c < 3; ++c) {
+            double e = (double)rgb[3 * p + c] - tgt[5 * p + c];
+            loss += e * e;
+            if (g_rgb) g_rgb[3 * p + c] = 2.0 * e / n;
+        }
+        double ev = (double)vis[p] - tgt[5 * p + 3];
+        double ed = (double)dep[p] - tgt[5 * p + 4];
+        loss += ev * ev + ed * ed;
+        if (g_vis) g_vis[p] = 2.0 * ev / n;
+        if (g_dep) g_dep[p] = 2.0 * ed / n;
+    }
+    return loss / n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Analytic backward of query mode (the distillation forward).              */
+/* Given upstream gradients of rgb (L_in), vis (V) and depth (d), adds the  */
+/* gradients with respect to the tables g_table [L][T][F], the decoder      */
+/* g_brdf and the tracer g_irt (each packed W0,b0,W1,b1,W2,b2) and,          */
+/* optionally, writes d/dx into g_pos [n][3].                               */
+/* Chain: L_in = V Le + (1-V) L'_o; L'_o depends on (a',r',m') = B(H(x')),   */
+/* on V'_j = sigmoid(I(H(x'), w'_j)_0) and, through x' = x + t w with       */
+/* t = near + (far-near) min(softplus(o1), 1), on o1 of I(H(x), w).          */
+/* The clamps pass no gradient where active (softplus >= 1, u outside       */
+/* (0,1)); the bounce directions depend only on w, which is an input.       */
+/* ------------------------------------------------------------------------ */
+static void scatter_table(const or_grid *g, const enc_rec *rec, const double *gf, double *g_table)
+{
+    const uint32_t T = 1u << g->log2_T;
+    for (int l = 0; l < g->L; ++l) {
+        const double *w = rec->w[l];
+        for (int corner = 0; corner < 8; ++corner) {
+            int dx = corner & 1, dy = (corner >> 1) & 1, dz = (corner >> 2) & 1;
+            double wt = (dx ? w[0] : 1.0 - w[0]) * (dy ? w[1] : 1.0 - w[1]) * (dz ? w[2] : 1.0 - w[2]);
+            size_t base = ((size_t)l * T + rec->idx[l][corner]) * g->F;
+            for (int k = 0; k < g->F; ++k) {
+                double v = wt * gf[l * g->F + k];
+#pragma omp atomic
+                g_table[base + k] += v;
+            }
+        }
+    }
+}
+
+/* d/dx of the encoding contracted with gf (position gradient). */
+static void encode_dx(const or_grid *g, const enc_rec *rec, const double *gf, double gx[3])
+{
+    const uint32_t T = 1u << g->log2_T;
+    gx[0] = gx[1] = gx[2] = 0.0;
+    for (int l = 0; l < g->L; ++l) {
+        const double *w = rec->w[l];
+        double scale = g->res[l] / g->extent;
+        for (int corner = 0; corner < 8; ++corner) {
+            int dl[3] = {corner & 1, (corner >> 1) & 1, (corner >> 2) & 1};
+            double fac[3], dfac[3];
+            for (int d = 0; d < 3; ++d) {
+                fac[d] = dl[d] ? w[d] : 1.0 - w[d];
+                dfac[d] = dl[d] ? 1.0 : -1.0;
+            }
+            const float *e = g->table + ((size_t)l * T + rec->idx[l][corner]) * g->F;
+            double ge = 0.0;
+            for (int k = 0; k < g->F; ++k) ge += gf[l * g->F + k] * (double)e[k];
+            gx[0] += ge * dfac[0] * fac[1] * fac[2] * scale;
+            gx[1] += ge * fac[0] * dfac[1] * fac[2] * scale;
+            gx[2] += ge * fac[0] * fac[1] * dfac[2] * scale;
+        }
+    }
+    for (int d = 0; d < 3; ++d)
+        if (!rec->inside[d]) gx[d] = 0.0;
+}
+
+void or_backward(const or_model *M, const or_env *E, const or_sampling *S, const or_points *P,
+                 int32_t indirect, const float *g_rgb, const float *g_vis, const float *g_dep,
+                 double *g_table, double *g_brdf, double *g_irt, double *g_pos)
+{
+    const or_grid *g = &M->grid;
+    const int nf = g->L * g->F;
+    const int64_t nb_par = mlp_nparams(&M->brdf), ni_par = mlp_nparams(&M->irt);
+    const double span = M->t_far - M->t_near;
+    const int diffuse = (S->flags & OR_DIFFUSE_ONLY) != 0;
+#pragma omp parallel
+    {
+        double *lb = (double *)calloc((size_t)nb_par, sizeof(double));
+        double *li = (double *)calloc((size_t)ni_par, sizeof(double));
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t p = 0; p < P->n; ++p) {
+            const float *x = P->pos + 3 * p;
+            double w[3] = {P->dir[3 * p], P->dir[3 * p + 1], P->dir[3 * p + 2]};
+            double u[3], f[OR_MAXF], z[OR_MAXIN], h1[OR_MAXH], h2[OR_MAXH], o[OR_MAXOUT];
+            enc_rec rx, rb;
+            pos_to_u_f32(g, x, u);
+            encode_u(g, u, f, &rx);
+            for (int i = 0; i < nf; ++i) z[i] = f[i];
+            z[nf] = w[0]; z[nf + 1] = w[1]; z[nf + 2] = w[2];
+            mlp_fwd(&M->irt, z, h1, h2, o);
+            double V = sigmoid(o[0]);
+            double sp = softplus(o[1]);
+            double d = sp < 1.0 ? sp : 1.0;
+            double t = M->t_near + span * d;
+            double Le[3];
+            env_lookup(E, w, Le);
+            double G[3] = {g_rgb[3 * p], g_rgb[3 * p + 1], g_rgb[3 * p + 2]};
+            double gV = g_vis[p], gd = g_dep[p];
+            double gxb[3] = {0, 0, 0};
+            if (indirect) {
+                double xb[3], ub[3], fb[OR_MAXF], hb1[OR_MAXH], hb2[OR_MAXH], ob[OR_MAXOUT];
+                for (int k = 0; k < 3; ++k) xb[k] = (double)x[k] + t * w[k];
+                pos_to_u_f64(g, xb, ub);
+                encode_u(g, ub, fb, &rb);
+                mlp_fwd(&M->brdf, fb, hb1, hb2, ob);
+                double ab[3] = {sigmoid(ob[0]), sigmoid(ob[1]), sigmoid(ob[2])};
+                double s3 = sigmoid(ob[3]);
+                double rr = 0.09 + 0.91 * s3;
+                double mb = sigmoid(ob[4]);
+                double nbv[3] = {-w[0], -w[1], -w[2]};
+                const int N2 = S->n_dirs2;
+                double wj[OR_MAXN2][3], Ej[OR_MAXN2][3], cj[OR_MAXN2][3], Vj[OR_MAXN2];
+                double dca[OR_MAXN2][3], dcr[OR_MAXN2][3], dcm[OR_MAXN2][3];
+                double Lo[3] = {0, 0, 0};
+                for (int j = 0; j < N2; ++j) {
+                    sample_dir(S->seed, (uint32_t)p, 0u, (uint32_t)j, 1u, N2, nbv, wj[j]);
+                    for (int i = 0; i < nf; ++i) z[i] = fb[i];
+                    z[nf] = wj[j][0]; z[nf + 1] = wj[j][1]; z[nf + 2] = wj[j][2];
+                    mlp_fwd(&M->irt, z, h1, h2, o);
+                    Vj[j] = sigmoid(o[0]);
+                    env_lookup(E, wj[j], Ej[j]);
+                    double fr[3];
+                    brdf_eval(nbv, nbv, wj[j], ab, rr, mb, M->f0, diffuse, fr, dca[j], dcr[j], dcm[j]);
+                    for (int c = 0; c < 3; ++c) {
+                        cj[j][c] = M_PI * fr[c];
+                        dca[j][c] *= M_PI;
+                        dcr[j][c] *= M_PI;
+                        dcm[j][c] *= M_PI;
+                        Lo[c] += cj[j][c] * Vj[j] * Ej[j][c];
+                    }
+                }
+                for (int c = 0; c < 3; ++c) Lo[c] /= N2;
+                for (int c = 0; c < 3; ++c) gV += G[c] * (Le[c] - Lo[c]);
+                double gLo[3] = {(1.0 - V) * G[0], (1.0 - V) * G[1], (1.0 - V) * G[2]};
+                double gfb[OR_MAXF], gz[OR_MAXIN];
+                for (int i = 0; i < nf; ++i) gfb[i] = 0.0;
+                double ga[3] = {0, 0, 0}, gr = 0.0, gm = 0.0;
+                for (int j = 0; j < N2; ++j) {
+                    double gvj = 0.0;
+                    for (int c = 0; c < 3; ++c) gvj += gLo[c] * cj[j][c] * Ej[j][c];
+                    gvj /= N2;
+                    double go[OR_MAXOUT] = {0};
+                    go[0] = gvj * Vj[j] * (1.0 - Vj[j]);
+                    /* recompute the tracer activations at (f', w'_j) */
+                    for (int i = 0; i < nf; ++i) z[i] = fb[i];
+                    z[nf] = wj[j][0]; z[nf + 1] = wj[j][1]; z[nf + 2] = wj[j][2];
+                    mlp_fwd(&M->irt, z, h1, h2, o);
+                    mlp_bwd(&M->irt, z, h1, h2, go, li, gz);
+                    for (int i = 0; i < nf; ++i) gfb[i] += gz[i];
+                    for (int c = 0; c < 3; ++c) {
+                        double gc = gLo[c] * Vj[j] * Ej[j][c] / N2;
+                        ga[c] += gc * dca[j][c];
+                        gr += gc * dcr[j][c];
+                        gm += gc * dcm[j][c];
+                    }
+                }
+                double gob[OR_MAXOUT] = {0};
+                for (int c = 0; c < 3; ++c) gob[c] = ga[c] * ab[c] * (1.0 - ab[c]);
+                gob[3] = gr * 0.91 * s3 * (1.0 - s3);
+                gob[4] = gm * mb * (1.0 - mb);
+                mlp_bwd(&M->brdf, fb, hb1, hb2, gob, lb, gz);
+                for (int i = 0; i < nf; ++i) gfb[i] += gz[i];
+                scatter_table(g, &rb, gfb, g_table);
+                encode_dx(g, &rb, gfb, gxb);
+                double gt = gxb[0] * w[0] + gxb[1] * w[1] + gxb[2] * w[2];
+                gd += span * gt;
+            } else {
+                for (int c = 0; c < 3; ++c) gV += G[c] * Le[c];
+            }
+            /* tracer at (f(x), w) */
+            for (int i = 0; i < nf; ++i) z[i] = f[i];
+            z[nf] = w[0]; z[nf + 1] = w[1]; z[nf + 2] = w[2];
+            mlp_fwd(&M->irt, z, h1, h2, o);
+            double go[OR_MAXOUT] = {0};
+            go[0] = gV * V * (1.0 - V);
+            go[1] = sp < 1.0 ? gd * sigmoid(o[1]) : 0.0;
+            double gz[OR_MAXIN];
+            mlp_bwd(&M->irt, z, h1, h2, go, li, gz);
+            scatter_table(g, &rx, gz, g_table);
+            if (g_pos) {
+                double gx[3];
+                encode_dx(g, &rx, gz, gx);
+                for (int k = 0; k < 3; ++k) g_pos[3 * p + k] = gx[k] + gxb[k];
+            }
+        }
+#pragma omp critical
+        {
+            for (int64_t i = 0; i < nb_par; ++i) g_brdf[i] += lb[i];
+            for (int64_t i = 0; i < ni_par; ++i) g_irt[i] += li[i];
+        }
+        free(lb);
+        free(li);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adam (Kingma & Ba 2015) with bias correction; weight decay added to the  */
+/* gradient (L2 form).  One step t >= 1 over n parameters, in FP64.         */
+/* ------------------------------------------------------------------------ */
+void or_adam(double *param, const double *grad, double *m, double *v, int64_t n, int32_t step,
+             double lr, double b1, double b2, double eps, double wd)
+{
+    double bc1 = 1.0 - pow(b1, step), bc2 = 1.0 - pow(b2, step);
+    for (int64_t i = 0; i < n; ++i) {
+        double gi = grad[i] + wd * param[i];
+        m[i] = b1 * m[i] + (1.0 - b1) * gi;
+        v[i] = b2 * v[i] + (1.0 - b2) * gi * gi;
+        double mh = m[i] / bc1, vh = v[i] / bc2;
+        param[i] -= lr * mh / (sqrt(vh) + eps);
+    }
+}
