@@ -1,0 +1,192 @@
+"""Benchmark of the hash-grid secondary-ray renderer on one MI355X.
+
+A step renders one 800x800 frame of the analytic scene with 128 stratified
+directions per pixel and one indirect bounce with 8 secondary directions
+(81.92M secondary queries, FP32 path), the frame-size workload.  The same
+run also times the mixed-precision frame (FP16 tables, BF16 matrix-core
+MLPs) when available, and one distillation training step (query-mode forward
+over 2^18 samples, L2 loss, hand-written backward, Adam), and reports the
+FP64 oracle on a bounded pixel subset on the host's cores.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_VEC_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+
+# Algorithmic work per secondary query (one (pixel, direction) pair):
+# tracer at x with the first layer split into a per-point part and a
+# direction part (3*64 + 64*64 + 64*2 MAC), decoder at x' (32*64 + 64*64 +
+# 64*5), the per-point part at x' (32*64) and N' = 8 direction parts:
+# 4416 + 6464 + 2048 + 8*4416 = 48,256 MAC = 96,512 FLOP.
+FLOP_PER_QUERY = 2 * (4416 + 6464 + 2048 + 8 * 4416)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--img", type=int, default=800)
+    ap.add_argument("--n-dirs", type=int, default=128)
+    ap.add_argument("--train-batch", type=int, default=1 << 18)
+    ap.add_argument("--no-train", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-stride", type=int, default=8)
+    return ap.parse_args()
+
+
+def time_events(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    per = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.record()
+        fn()
+        e.record()
+        e.synchronize()
+        per.append(s.elapsed_time(e))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return float(np.mean(per)), per, wall
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (rendering shards by pixel with "
+              "no exchange; see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import hg_inputs as H
+    import paper_2409_10327_amd as hg
+
+    dev = "cuda:0"
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    cfg = H.config("c2")
+    cfg.img_h = cfg.img_w = args.img
+    cfg.n_dirs = args.n_dirs
+    print(f"[bench] building inputs {args.img}x{args.img} N={args.n_dirs}", file=sys.stderr, flush=True)
+    model = H.make_model(cfg)
+    env = H.make_env(cfg.env_h, cfg.env_w)
+    pos, nrm, wo = H.make_scene(cfg.img_h, cfg.img_w)
+    r = hg.HashRenderer(model, dev)
+    env_t, pos_t, nrm_t, wo_t = t(env), t(pos), t(nrm), t(wo)
+    P = pos.shape[0]
+    S = P * cfg.n_dirs
+    rgb = torch.empty((P, 3), device=dev)
+
+    def frame_fp32():
+        hg.render(r, env_t, pos_t, nrm_t, wo_t, n_dirs=cfg.n_dirs, n_dirs2=cfg.n_dirs2, seed=H.SEED_DIRS,
+                  indirect=True, out=(rgb, None, None))
+
+    print("[bench] FP32 frame", file=sys.stderr, flush=True)
+    ms, per, wall = time_events(frame_fp32, args.steps, args.warmup, torch)
+    out = {
+        "metric": "secondary-ray queries/s (FP32 forward, 800x800 frame, 128 dirs + 1 bounce x 8)",
+        "value": S / (ms * 1e-3),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"frame {args.img}x{args.img}, N={cfg.n_dirs}, N'={cfg.n_dirs2}, L=16, "
+                               f"T=2^{cfg.log2_T}, res 16..2048, env 64x128 (FP32 path)",
+                   "shaded_px_per_s": P / (ms * 1e-3), "secondary_queries": S},
+    }
+    achieved = FLOP_PER_QUERY * S / (ms * 1e-3) / 1e12
+    out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": FP32_VEC_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": achieved / FP32_VEC_PEAK_TFLOPS, "traffic": None,
+                       "kernel": "k_render_shade<true> (FP32)"}
+
+    if not args.no_mixed:
+        try:
+            rgbm = torch.empty((P, 3), device=dev)
+            r.refresh_shadows()
+
+            def frame_mixed():
+                hg.render(r, env_t, pos_t, nrm_t, wo_t, n_dirs=cfg.n_dirs, n_dirs2=cfg.n_dirs2,
+                          seed=H.SEED_DIRS, indirect=True, precision="mixed", out=(rgbm, None, None))
+            print("[bench] mixed frame", file=sys.stderr, flush=True)
+            msm, _, _ = time_events(frame_mixed, args.steps, args.warmup, torch)
+            a_m = FLOP_PER_QUERY * S / (msm * 1e-3) / 1e12
+            out["mixed"] = {"value": S / (msm * 1e-3), "ms_per_step": msm, "shaded_px_per_s": P / (msm * 1e-3),
+                            "dtype": "bf16-mfma/f16-table/f32-acc",
+                            "roofline": {"bound": "mfma", "achieved": a_m, "peak": BF16_MFMA_PEAK_TFLOPS,
+                                         "unit": "TFLOP/s", "frac": a_m / BF16_MFMA_PEAK_TFLOPS}}
+        except hg.HGError as e:
+            out["mixed"] = {"unavailable": str(e)}
+
+    if not args.no_train:
+        B = args.train_batch
+        print(f"[bench] training step B={B}", file=sys.stderr, flush=True)
+        teacher = hg.HashRenderer(H.make_teacher(cfg), dev)
+        bp, bd = H.make_train_batch(B)
+        bp_t, bd_t = t(bp), t(bd)
+        trgb, tvis, tdep = hg.render(teacher, env_t, bp_t, dirs=bd_t)
+        tgt = torch.cat([trgb, tvis[:, None], tdep[:, None]], 1).contiguous()
+        del teacher
+        grads = hg.zero_grads(r)
+        params = [r.table] + r.brdf + r.irt
+        gl = [grads["table"]] + grads["brdf"] + grads["irt"]
+        ms_ = [torch.zeros_like(p) for p in params]
+        vs_ = [torch.zeros_like(p) for p in params]
+        step = [0]
+
+        def train_step():
+            step[0] += 1
+            for g in gl:
+                g.zero_()
+            rgb_, vis_, dep_ = hg.render(r, env_t, bp_t, dirs=bd_t)
+            loss, g_rgb, g_vis, g_dep = hg.l2_loss(rgb_, vis_, dep_, tgt)
+            hg.backward(r, env_t, bp_t, bd_t, g_rgb, g_vis, g_dep, grads)
+            for i, (p_, g_) in enumerate(zip(params, gl)):
+                hg.adam_step(p_, g_, ms_[i], vs_[i], step[0], lr=2e-3, weight_decay=0.0 if i == 0 else 1e-6)
+            return loss
+
+        mst, _, _ = time_events(train_step, max(2, args.steps // 2), 1, torch)
+        out["train"] = {"samples_per_s": B / (mst * 1e-3), "ms_per_step": mst, "batch": B,
+                        "secondary_queries_per_s_fwd_bwd": B / (mst * 1e-3), "dtype": "f32"}
+
+    if not args.no_cpu:
+        from oracle import oracle as O
+        sub = H.subset_rows_cols(cfg.img_h, cfg.img_w, args.cpu_stride)
+        om, oe = O.OracleModel(model, H.BOX_LO, H.BOX_EXTENT), O.OracleEnv(env)
+        print(f"[bench] oracle on {len(sub)} px", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        O.render(om, oe, O.sampling(cfg.n_dirs, cfg.n_dirs2, H.SEED_DIRS, 0), pos[sub], nrm[sub], wo[sub],
+                 indirect=True, want_vis=False)
+        dt = time.perf_counter() - t0
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        out["cpu_baseline"] = {"value": len(sub) * cfg.n_dirs / dt, "unit": "queries/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": f"every {args.cpu_stride}th row and column ({len(sub)} px x "
+                                         f"{cfg.n_dirs} dirs), FP64, {dt:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,202 @@
+/*
+ * hg.h -- C ABI of the MI355X (gfx950) hash-grid secondary-ray renderer.
+ *
+ * The library implements the hash-grid renderer of "Baking Relightable NeRF
+ * for Real-time Direct/Indirect Illumination Rendering" (arXiv 2409.10327):
+ * a multi-resolution hash-grid encoder H, a BRDF decoder B and an implicit
+ * ray tracer I (Sec. 3.2), one recursive bounce at the secondary point
+ * x' = x + t w (Sec. 3.1), and the Monte Carlo rendering equation over an
+ * equirectangular environment map (Eq. 1, Eq. 2, Sec. 2.2), plus the
+ * hand-written backward, L2 loss and Adam used to distil it (Sec. 3.3).
+ *
+ * Conventions for every call:
+ *   - Array arguments are DEVICE pointers (HBM), caller-allocated,
+ *     contiguous, row-major, at least 16-byte aligned (8-byte for FP16/BF16
+ *     parameter arrays).  Descriptor structs are HOST memory, read only
+ *     during the call.
+ *   - Work is enqueued asynchronously on `stream`; nothing synchronises.
+ *   - No call allocates device memory; gradients are accumulated (+=) into
+ *     caller buffers, so the caller zeroes them between steps.
+ *   - Return value: HG_OK, or an error code with no work enqueued
+ *     (HG_E_INVALID / HG_E_UNSUPPORTED: argument validation on the host) or
+ *     HG_E_HIP (a launch failed).  hg_last_error() gives a message for the
+ *     calling thread's last failure.  n == 0 is a valid no-op.
+ *   - Supported shapes: F = 2 features per level, L = 16 levels, hidden
+ *     width 64, decoder 32->64->64->5, tracer 35->64->64->2 (the decoder and
+ *     tracer of Sec. 3.2 with 3 layers of width 64, Sec. 4.1), log2_T in
+ *     [10, 24], per-level resolutions strictly increasing in [2, 2^20],
+ *     box extent a power of two, n_dirs and n_dirs2 powers of two in
+ *     [1, 1024] and [1, 64].
+ *   - Precision pairs: FP32 tables with FP32 MLP weights (plain path); FP16
+ *     tables with BF16 MLP weights (mixed path: BF16 matrix-core products,
+ *     FP32 accumulation, FP32 interpolation, compensated FP32 sums over light
+ *     directions).  The backward also accepts FP16 tables with FP32 weights.
+ */
+#ifndef HG_H
+#define HG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HG_OK = 0,
+    HG_E_INVALID = 1,     /* malformed argument (NULL, size, alignment, shape) */
+    HG_E_UNSUPPORTED = 2, /* well-formed but not built (shape, dtype pair) */
+    HG_E_WORKSPACE = 3,   /* reserved */
+    HG_E_HIP = 4          /* a HIP launch or runtime call failed */
+} hg_status;
+
+typedef enum { HG_F32 = 0, HG_F16 = 1, HG_BF16 = 2 } hg_dtype;
+
+/* hg_sampling.flags */
+#define HG_DIFFUSE_ONLY 1u /* f_r = albedo/pi (furnace tests) */
+
+/* Multi-resolution hash grid (Sec. 3.2, InstantNGP layout).
+ * table: [L][T][F], T = 2^log2_T, entries FP32 or FP16.
+ * res[l]: resolution N_l of level l (host-computed integers).
+ * A position x maps to u = clamp((x - box_lo) / box_extent, 0, 1); the
+ * subtraction is rounded to FP32 and box_extent is a power of two.  Level l
+ * uses cell c = min(floor(u N_l), N_l - 1), fractional weights w = u N_l - c
+ * (cell chosen from the exact product), vertex index dense row-major when
+ * (N_l+1)^3 <= T, else the spatial hash of Mueller et al. 2022 (Eq. 4),
+ * primes (1, 2654435761, 805459861) masked to T.  Features are trilinear
+ * blends, concatenated level-major: f[l*F + k]. */
+typedef struct {
+    int32_t L, F, log2_T;
+    int32_t res[32];
+    float box_lo, box_extent;
+    hg_dtype dtype;
+    const void *table;
+} hg_grid;
+
+/* Three-layer ReLU MLP n_in -> n_hidden -> n_hidden -> n_out.
+ * W[k]: [out][in] (FP32 or BF16), b[k]: [out] FP32. */
+typedef struct {
+    int32_t n_in, n_hidden, n_out;
+    hg_dtype dtype;
+    const void *W[3];
+    const float *b[3];
+} hg_mlp;
+
+/* The hash renderer: grid, BRDF decoder B (outputs: albedo logits 0..2,
+ * roughness logit 3 -> 0.09 + 0.91 sigmoid, metallic logit 4 -> sigmoid) and
+ * tracer I (input [f, w]; output 0 -> visibility sigmoid, output 1 -> depth
+ * d = min(softplus, 1), t = t_near + (t_far - t_near) d).  f0 is the
+ * dielectric Fresnel reflectance (0.04 in the paper, Sec. 5). */
+typedef struct {
+    hg_grid grid;
+    hg_mlp brdf, irt;
+    float t_near, t_far, f0;
+} hg_model;
+
+/* Equirectangular HDR map [H][W][3] FP32; y is up, row 0 at the zenith,
+ * azimuth atan2(w_z, w_x) from -pi at column 0; bilinear lookup at texel
+ * centres, columns wrap, rows clamp (Sec. 2.2, image-based lighting). */
+typedef struct {
+    int32_t H, W;
+    const float *rgb;
+} hg_env;
+
+/* Light sampling: n_dirs stratified cosine-weighted directions per primary
+ * point and n_dirs2 per secondary point (8 in the paper's renderer,
+ * supplementary "Rendering Details").  The uniforms come from
+ * Philox4x32-10 (key = seed, counter = (point, primary direction index or 0,
+ * sample >> 2, 0 primary / 1 secondary), 16-bit halves of word sample & 3). */
+typedef struct {
+    int32_t n_dirs, n_dirs2;
+    uint64_t seed;
+    uint32_t flags;
+} hg_sampling;
+
+/* Points, each [n][3] FP32 on the device.
+ * Shade mode (dir == NULL): pos, nrm (unit normal), wo (unit direction to
+ * the viewer) of primary surface points.
+ * Query mode (dir != NULL): pos and a unit direction per query; nrm and wo
+ * are ignored. */
+typedef struct {
+    int64_t n;
+    const float *pos, *nrm, *wo, *dir;
+} hg_points;
+
+/* f = H(x) (Sec. 3.2, "Indirect Illumination Renderer").
+ * pos [n][3] FP32 -> feat [n][L*F] FP32. */
+hg_status hg_encode(const hg_grid *grid, const float *pos, int64_t n, float *feat,
+                    hipStream_t stream);
+
+/* Index stage of H for inspection and bit-exact testing: for each point and
+ * level, the table indices of the 8 cell corners (corner bit 0 = +x, bit 1 =
+ * +y, bit 2 = +z) and the in-cell weights w = u N_l - c.
+ * pos [n][3] FP32 -> idx [n][L][8] uint32, w [n][L][3] FP32 (w may be NULL). */
+hg_status hg_encode_index(const hg_grid *grid, const float *pos, int64_t n, uint32_t *idx, float *w,
+                          hipStream_t stream);
+
+/* Direct illumination with shadows ("d" rows of Table 3): Eq. (1) with the
+ * incoming radiance V(x, w_i) L_env(w_i), V from the tracer.
+ * Shade mode: rgb [n][3] = 1/N sum_i pi f_r(x; w_i, w_o) V_i L_env(w_i);
+ *   vis, depth (optional, may be NULL) [n][n_dirs] receive V_i and d_i.
+ * Query mode: rgb [n][3] = V L_env(dir), vis [n] = V, depth [n] = d. */
+hg_status hg_render_direct(const hg_model *model, const hg_env *env, const hg_sampling *samp,
+                           const hg_points *pts, float *rgb, float *vis, float *depth,
+                           hipStream_t stream);
+
+/* Direct + one indirect bounce ("d+id" rows of Table 3): the incoming
+ * radiance of Eq. (2), L_in = V L_env(w) + (1 - V) L'_o, with
+ * L'_o = 1/N' sum_j pi f_r(x'; w'_j, -w) V'_j L_env(w'_j) at
+ * x' = x + t w, (a', r', m') = B(H(x')), facing normal n' = -w,
+ * V'_j = sigmoid(I(H(x'), w'_j)_0) (Sec. 3.1, Sec. 3.2 "Overview").
+ * Outputs as for hg_render_direct; in query mode rgb = L_in. */
+hg_status hg_render_indirect(const hg_model *model, const hg_env *env, const hg_sampling *samp,
+                             const hg_points *pts, float *rgb, float *vis, float *depth,
+                             hipStream_t stream);
+
+/* Backward of query mode (the distillation forward, Sec. 3.3), with the
+ * bounce activations recomputed, not stored.  Given upstream gradients
+ * g_rgb [n][3], g_vis [n], g_depth [n], ADDS the gradients of
+ * sum_p (g_rgb.rgb + g_vis vis + g_depth depth) to
+ *   g_table [L][T][F] FP32 (atomic scatter-add through the trilinear weights),
+ *   g_brdf[6], g_irt[6]: FP32 W0,b0,W1,b1,W2,b2 of decoder and tracer,
+ * and WRITES d/dpos into g_pos [n][3] if it is not NULL.
+ * indirect selects the query mode of hg_render_indirect (1) or
+ * hg_render_direct (0).  MLP weights must be FP32 (the masters); the table
+ * may be FP32 or FP16.  Accumulation order of the atomics is unspecified. */
+hg_status hg_backward(const hg_model *model, const hg_env *env, const hg_sampling *samp,
+                      const hg_points *pts, int32_t indirect, const float *g_rgb,
+                      const float *g_vis, const float *g_depth, float *g_table,
+                      float *const g_brdf[6], float *const g_irt[6], float *g_pos,
+                      hipStream_t stream);
+
+/* L2 distillation loss (squared-error reading of Sec. 3.3's losses):
+ *   loss = 1/n sum_p [ |rgb_p - t_p[0:3]|^2 + (vis_p - t_p[3])^2 +
+ *                      (depth_p - t_p[4])^2 ],
+ * tgt [n][5].  Writes loss [1] (FP32 sum order unspecified) and the
+ * gradients g_rgb [n][3], g_vis [n], g_depth [n] (elementwise, exact
+ * order). */
+hg_status hg_l2_loss(const float *rgb, const float *vis, const float *depth, const float *tgt,
+                     int64_t n, float *loss, float *g_rgb, float *g_vis, float *g_depth,
+                     hipStream_t stream);
+
+/* One Adam step (Kingma & Ba) with bias correction, weight decay added to
+ * the gradient (the paper trains with Adam, lr 2e-3, weight decay 1e-6 on
+ * the MLPs; supplementary training details).  step >= 1.  Updates param,
+ * m, v in place (FP32).  If shadow != NULL, also writes the updated
+ * parameters rounded to nearest-even in shadow_dtype (HG_F16 for tables,
+ * HG_BF16 for MLP weights). */
+hg_status hg_adam_step(float *param, const float *grad, float *m, float *v, int64_t n,
+                       int32_t step, float lr, float beta1, float beta2, float eps,
+                       float weight_decay, void *shadow, hg_dtype shadow_dtype,
+                       hipStream_t stream);
+
+/* Message describing the calling thread's last failed call ("" if none). */
+const char *hg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HG_H */

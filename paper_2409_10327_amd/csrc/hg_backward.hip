@@ -1,0 +1,352 @@
+// hg_backward.hip -- hand-written backward of query mode (distillation).
+//
+// One query per lane.  Every activation of the recursive bounce is
+// recomputed here; nothing is stored by the forward.  Weight gradients of
+// the two MLPs are reduced over the 64 queries of a wave through LDS
+// (each lane owns one input column of a layer) and then added to global
+// memory with FP32 atomics; table gradients are scattered with FP32 atomics
+// through the trilinear weights.
+#include "hg_device.h"
+#include "hg_launch.h"
+
+namespace hg {
+
+constexpr int kDelStride = 68;  // del[s][k]: 16-byte aligned rows for broadcast reads
+constexpr int kWaveLds = 2 * kHBuf + 64 * kDelStride;
+constexpr int kBwdThreads = 64;
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void atomic_addf(float *p, float v) { unsafeAtomicAdd(p, v); }
+
+// dW[o][col] += sum_s del[s][o] * act[col][s] over the wave's 64 samples
+// (act in the [unit][kHS] layout of the forward, del in [sample][kDelStride]);
+// lane == col owns column col.  Bias gradients db[o] = sum_s del[s][o] are
+// added by lane == o.
+template <int NOUT, int NIN>
+__device__ __forceinline__ void reduce_layer(const float *act, const float *del, float *gW, float *gb, int lane) {
+    constexpr int CH = NOUT < 16 ? NOUT : 16;
+    if (lane < NIN) {
+#pragma unroll 1
+        for (int ob = 0; ob < NOUT; ob += CH) {
+            float acc[CH];
+#pragma unroll
+            for (int k = 0; k < CH; ++k) acc[k] = 0.0f;
+#pragma unroll 4
+            for (int s = 0; s < 64; ++s) {
+                const float a = act[lane * kHS + s];
+                const float *row = del + s * kDelStride + ob;
+                if constexpr (CH % 4 == 0) {
+#pragma unroll
+                    for (int k = 0; k < CH; k += 4) {
+                        const float4 d4 = *reinterpret_cast<const float4 *>(row + k);
+                        acc[k] = fmaf(d4.x, a, acc[k]);
+                        acc[k + 1] = fmaf(d4.y, a, acc[k + 1]);
+                        acc[k + 2] = fmaf(d4.z, a, acc[k + 2]);
+                        acc[k + 3] = fmaf(d4.w, a, acc[k + 3]);
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < CH; ++k) acc[k] = fmaf(row[k], a, acc[k]);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < CH; ++k) atomic_addf(gW + (size_t)(ob + k) * NIN + lane, acc[k]);
+        }
+    }
+    if (lane < NOUT) {
+        float acc = 0.0f;
+#pragma unroll 8
+        for (int s = 0; s < 64; ++s) acc += del[s * kDelStride + lane];
+        atomic_addf(gb + lane, acc);
+    }
+}
+
+__device__ __forceinline__ void store_row(float *del, int lane, const float (&v)[kH]) {
+#pragma unroll
+    for (int k = 0; k < kH; k += 4)
+        *reinterpret_cast<float4 *>(del + lane * kDelStride + k) = make_float4(v[k], v[k + 1], v[k + 2], v[k + 3]);
+}
+
+// Backward of one MLP evaluation for every lane of the wave (all lanes call
+// it together).  Recomputes the forward, accumulates parameter gradients
+// (gp = W0,b0,W1,b1,W2,b2) and returns d/d(input) for the first kNF inputs.
+template <int NIN, int NOUT>
+__device__ __forceinline__ void mlp_bwd_wave(const MlpK &m, float *const *gp, const float (&z)[NIN], const float (&gout)[NOUT],
+                             float *h1buf, float *h2buf, float *del, int lane, float (&dz)[kNF]) {
+    float h[kH], o[NOUT];
+    mlp_fwd<NIN, NOUT, float>(m, z, h1buf, h2buf, lane, h, o);  // h = h2
+    // ---- layer 2: out = W2 h2 + b2
+#pragma unroll
+    for (int k = 0; k < NOUT; ++k) del[lane * kDelStride + k] = gout[k];
+    wave_sync();
+    reduce_layer<NOUT, kH>(h2buf, del, gp[4], gp[5], lane);
+    wave_sync();
+    {
+        const WPtr<float> W2(m.W2);
+#pragma unroll
+        for (int k = 0; k < kH; ++k) {
+            float s = 0.0f;
+#pragma unroll
+            for (int oo = 0; oo < NOUT; ++oo) s = fmaf(W2[oo * kH + k], gout[oo], s);
+            h[k] = h[k] > 0.0f ? s : 0.0f;  // h now holds d/d(pre-activation 2)
+        }
+    }
+    // ---- layer 1: pre2 = W1 h1 + b1
+    store_row(del, lane, h);
+    wave_sync();
+    reduce_layer<kH, kH>(h1buf, del, gp[2], gp[3], lane);
+    wave_sync();
+    // d/d(pre-activation 1) = mask(h1) * W1^T g2, accumulated over rows k of W1
+#pragma unroll
+    for (int j = 0; j < kH; ++j) h[j] = 0.0f;
+#pragma unroll 1
+    for (int k = 0; k < kH; ++k) {
+        const WPtr<float> W1(m.W1);
+        const float g2 = del[lane * kDelStride + k];
+#pragma unroll
+        for (int j = 0; j < kH; ++j) h[j] = fmaf(W1[k * kH + j], g2, h[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < kH; ++j) h[j] = h1buf[j * kHS + lane] > 0.0f ? h[j] : 0.0f;
+    // ---- layer 0: pre1 = W0 z + b0; z goes into the h2 buffer
+    wave_sync();
+    store_row(del, lane, h);
+#pragma unroll
+    for (int i = 0; i < NIN; ++i) h2buf[i * kHS + lane] = z[i];
+    wave_sync();
+    reduce_layer<kH, NIN>(h2buf, del, gp[0], gp[1], lane);
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < kNF; ++i) dz[i] = 0.0f;
+#pragma unroll 1
+    for (int j = 0; j < kH; ++j) {
+        const WPtr<float> W0(m.W0);
+        const float g1 = del[lane * kDelStride + j];
+#pragma unroll
+        for (int i = 0; i < kNF; ++i) dz[i] = fmaf(W0[j * NIN + i], g1, dz[i]);
+    }
+}
+
+// Scatter gf through the trilinear weights of the cell of x into the table
+// gradient, and (optionally) return d/dx of the encoding contracted with gf.
+template <typename TT>
+__device__ __forceinline__ void encode_bwd(const GridK &g, float x, float y, float z, const float (&gf)[kNF], float *g_table,
+                           bool live, bool want_dx, float3 &gx) {
+    float u[3];
+    bool in[3];
+    pos_to_u(g, x, y, z, u, in);
+    float gxx = 0.f, gxy = 0.f, gxz = 0.f;
+#pragma unroll
+    for (int l = 0; l < kL; ++l) {
+        uint32_t c[3];
+        float w[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) cell_of(u[d], g.resf[l], g.nm1f[l], c[d], w[d]);
+        const size_t base = (size_t)l << g.log2T;
+        uint32_t idx[8];
+        corner_idx(g, l, c, idx);
+        const float w0[3] = {1.0f - w[0], 1.0f - w[1], 1.0f - w[2]};
+        const float sc = g.dscale[l];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int dx = k & 1, dy = (k >> 1) & 1, dzz = (k >> 2) & 1;
+            const size_t e = base + idx[k];
+            const float fx = dx ? w[0] : w0[0], fy = dy ? w[1] : w0[1], fz = dzz ? w[2] : w0[2];
+            const float wt = fx * fy * fz;
+            if (live) {
+                atomic_addf(g_table + 2 * e, wt * gf[2 * l]);
+                atomic_addf(g_table + 2 * e + 1, wt * gf[2 * l + 1]);
+            }
+            if (want_dx) {
+                const float2 te = TabLoad<TT>::ld(g.table, e);
+                const float ge = (gf[2 * l] * te.x + gf[2 * l + 1] * te.y) * sc;
+                gxx = fmaf(ge, (dx ? 1.0f : -1.0f) * fy * fz, gxx);
+                gxy = fmaf(ge, fx * (dy ? 1.0f : -1.0f) * fz, gxy);
+                gxz = fmaf(ge, fx * fy * (dzz ? 1.0f : -1.0f), gxz);
+            }
+        }
+    }
+    gx = make_float3(in[0] ? gxx : 0.f, in[1] ? gxy : 0.f, in[2] ? gxz : 0.f);
+}
+
+// pi f_r and its derivatives with respect to albedo (per channel),
+// roughness and metallic.
+struct BrdfGrad {
+    float3 c, dca, dcr, dcm;
+};
+__device__ __forceinline__ BrdfGrad pi_brdf_grad(float3 n, float3 v, float3 l, float3 a, float r, float m, float f0,
+                                                 bool diffuse) {
+    BrdfGrad o;
+    const float3 z = make_float3(0.f, 0.f, 0.f);
+    if (!(dot3(n, l) > 0.0f)) {
+        o.c = o.dca = o.dcr = o.dcm = z;
+        return o;
+    }
+    if (diffuse) {
+        o.c = a;
+        o.dca = make_float3(1.f, 1.f, 1.f);
+        o.dcr = o.dcm = z;
+        return o;
+    }
+    const BrdfTerms t = brdf_terms(n, v, l, r, true);
+    const float s = kPi * t.D * t.Vis;
+    const float q = 1.0f - t.P;
+    const float dsr = kPi * (t.dD_da2 * t.Vis + t.D * t.dVis_da2) * 4.0f * r * r * r;
+    const float av[3] = {a.x, a.y, a.z};
+    float c[3], da[3], dr[3], dm[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float F0 = f0 * (1.0f - m) + av[k] * m;
+        const float F = F0 * q + t.P;
+        c[k] = (1.0f - m) * av[k] + s * F;
+        da[k] = (1.0f - m) + s * q * m;
+        dm[k] = -av[k] + s * q * (av[k] - f0);
+        dr[k] = F * dsr;
+    }
+    o.c = make_float3(c[0], c[1], c[2]);
+    o.dca = make_float3(da[0], da[1], da[2]);
+    o.dcr = make_float3(dr[0], dr[1], dr[2]);
+    o.dcm = make_float3(dm[0], dm[1], dm[2]);
+    return o;
+}
+
+template <typename TT, bool INDIRECT>
+__global__ __launch_bounds__(kBwdThreads) void k_backward(const BwdK a) {
+    extern __shared__ float lds[];
+    const int lane = threadIdx.x & 63;
+    float *h1buf = lds + (threadIdx.x >> 6) * kWaveLds;
+    float *h2buf = h1buf + kHBuf;
+    float *del = h2buf + kHBuf;
+    const int64_t p_raw = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const RenderK &r = a.r;
+    const bool live = p_raw < r.n;
+    const int64_t p = live ? p_raw : r.n - 1;
+    const float3 x = make_float3(r.pos[3 * p], r.pos[3 * p + 1], r.pos[3 * p + 2]);
+    const float3 w = make_float3(r.dir[3 * p], r.dir[3 * p + 1], r.dir[3 * p + 2]);
+    float3 G = make_float3(0.f, 0.f, 0.f);
+    float gV = 0.f, gd = 0.f;
+    if (live) {
+        G = make_float3(a.g_rgb[3 * p], a.g_rgb[3 * p + 1], a.g_rgb[3 * p + 2]);
+        gV = a.g_vis[p];
+        gd = a.g_dep[p];
+    }
+    float f[kNF];
+    encode<TT>(r.g, x.x, x.y, x.z, f);
+    float z[kNI], h[kH], o[2];
+#pragma unroll
+    for (int i = 0; i < kNF; ++i) z[i] = f[i];
+    z[kNF] = w.x; z[kNF + 1] = w.y; z[kNF + 2] = w.z;
+    mlp_fwd<kNI, 2, float>(r.irt, z, h1buf, h1buf, lane, h, o);
+    const float V = sigmoidf_(o[0]);
+    const float o1p = o[1];
+    const float sp = softplusf_(o1p);
+    const float d = fminf(sp, 1.0f);
+    const float t = fmaf(r.t_span, d, r.t_near);
+    const float3 Le = env_lookup(r.env, w.x, w.y, w.z);
+    float3 gxb = make_float3(0.f, 0.f, 0.f);
+    float dz[kNF];
+    if constexpr (INDIRECT) {
+        const float3 xb = make_float3(fmaf(t, w.x, x.x), fmaf(t, w.y, x.y), fmaf(t, w.z, x.z));
+        float fb[kNF];
+        encode<TT>(r.g, xb.x, xb.y, xb.z, fb);
+        float ob[5];
+        mlp_fwd<kNF, 5, float>(r.brdf, fb, h1buf, h1buf, lane, h, ob);
+        const float3 ab = make_float3(sigmoidf_(ob[0]), sigmoidf_(ob[1]), sigmoidf_(ob[2]));
+        const float s3 = sigmoidf_(ob[3]);
+        const float rb = 0.09f + 0.91f * s3;
+        const float mb = sigmoidf_(ob[4]);
+        const float3 nb = make_float3(-w.x, -w.y, -w.z);
+        const Frame fr = make_frame(nb);
+        const bool diffuse = (r.s.flags & 1u) != 0;
+        const uint32_t N2 = r.s.n_dirs2;
+        const float invN2 = 1.0f / (float)N2;
+#pragma unroll
+        for (int i = 0; i < kNF; ++i) z[i] = fb[i];
+        // pass 1: L'_o
+        float Lx = 0.f, Ly = 0.f, Lz = 0.f;
+        uint4 words = make_uint4(0, 0, 0, 0);
+        for (uint32_t j = 0; j < N2; ++j) {
+            if ((j & 3u) == 0) words = philox4x32_10((uint32_t)p, 0u, j >> 2, 1u, r.s.key0, r.s.key1);
+            const float3 wj = sample_dir(pick4(words, j), j, r.s.nb2_shift, r.s.inv_na2, r.s.inv_nb2, fr);
+            z[kNF] = wj.x; z[kNF + 1] = wj.y; z[kNF + 2] = wj.z;
+            mlp_fwd<kNI, 2, float>(r.irt, z, h1buf, h1buf, lane, h, o);
+            const float vj = sigmoidf_(o[0]);
+            const float3 Ej = env_lookup(r.env, wj.x, wj.y, wj.z);
+            const float3 c = pi_brdf(nb, nb, wj, ab, rb, mb, r.f0, diffuse);
+            Lx = fmaf(c.x * vj, Ej.x, Lx);
+            Ly = fmaf(c.y * vj, Ej.y, Ly);
+            Lz = fmaf(c.z * vj, Ej.z, Lz);
+        }
+        Lx *= invN2; Ly *= invN2; Lz *= invN2;
+        gV += G.x * (Le.x - Lx) + G.y * (Le.y - Ly) + G.z * (Le.z - Lz);
+        const float3 gLo = make_float3((1.0f - V) * G.x, (1.0f - V) * G.y, (1.0f - V) * G.z);
+        float gfb[kNF];
+#pragma unroll
+        for (int i = 0; i < kNF; ++i) gfb[i] = 0.f;
+        float gax = 0.f, gay = 0.f, gaz = 0.f, gr = 0.f, gm = 0.f;
+        // pass 2: tracer backward at every secondary direction
+        for (uint32_t j = 0; j < N2; ++j) {
+            if ((j & 3u) == 0) words = philox4x32_10((uint32_t)p, 0u, j >> 2, 1u, r.s.key0, r.s.key1);
+            const float3 wj = sample_dir(pick4(words, j), j, r.s.nb2_shift, r.s.inv_na2, r.s.inv_nb2, fr);
+            z[kNF] = wj.x; z[kNF + 1] = wj.y; z[kNF + 2] = wj.z;
+            mlp_fwd<kNI, 2, float>(r.irt, z, h1buf, h1buf, lane, h, o);
+            const float vj = sigmoidf_(o[0]);
+            const float3 Ej = env_lookup(r.env, wj.x, wj.y, wj.z);
+            const BrdfGrad bg = pi_brdf_grad(nb, nb, wj, ab, rb, mb, r.f0, diffuse);
+            const float gvj = (gLo.x * bg.c.x * Ej.x + gLo.y * bg.c.y * Ej.y + gLo.z * bg.c.z * Ej.z) * invN2;
+            const float go[2] = {gvj * vj * (1.0f - vj), 0.0f};
+            mlp_bwd_wave<kNI, 2>(r.irt, a.gi, z, go, h1buf, h2buf, del, lane, dz);
+#pragma unroll
+            for (int i = 0; i < kNF; ++i) gfb[i] += dz[i];
+            const float kx = gLo.x * vj * Ej.x * invN2, ky = gLo.y * vj * Ej.y * invN2, kz = gLo.z * vj * Ej.z * invN2;
+            gax = fmaf(kx, bg.dca.x, gax);
+            gay = fmaf(ky, bg.dca.y, gay);
+            gaz = fmaf(kz, bg.dca.z, gaz);
+            gr += kx * bg.dcr.x + ky * bg.dcr.y + kz * bg.dcr.z;
+            gm += kx * bg.dcm.x + ky * bg.dcm.y + kz * bg.dcm.z;
+        }
+        const float gob[5] = {gax * ab.x * (1.0f - ab.x), gay * ab.y * (1.0f - ab.y), gaz * ab.z * (1.0f - ab.z),
+                              gr * 0.91f * s3 * (1.0f - s3), gm * mb * (1.0f - mb)};
+        mlp_bwd_wave<kNF, 5>(r.brdf, a.gb, fb, gob, h1buf, h2buf, del, lane, dz);
+#pragma unroll
+        for (int i = 0; i < kNF; ++i) gfb[i] += dz[i];
+        encode_bwd<TT>(r.g, xb.x, xb.y, xb.z, gfb, a.g_table, live, true, gxb);
+        const float gt = gxb.x * w.x + gxb.y * w.y + gxb.z * w.z;
+        gd = fmaf(r.t_span, gt, gd);
+    } else {
+        gV += G.x * Le.x + G.y * Le.y + G.z * Le.z;
+    }
+    // tracer at (f(x), w)
+#pragma unroll
+    for (int i = 0; i < kNF; ++i) z[i] = f[i];
+    z[kNF] = w.x; z[kNF + 1] = w.y; z[kNF + 2] = w.z;
+    const float go2[2] = {gV * V * (1.0f - V), sp < 1.0f ? gd * sigmoidf_(o1p) : 0.0f};
+    mlp_bwd_wave<kNI, 2>(r.irt, a.gi, z, go2, h1buf, h2buf, del, lane, dz);
+    float3 gx;
+    encode_bwd<TT>(r.g, x.x, x.y, x.z, dz, a.g_table, live, a.g_pos != nullptr, gx);
+    if (live && a.g_pos) {
+        a.g_pos[3 * p] = gx.x + gxb.x;
+        a.g_pos[3 * p + 1] = gx.y + gxb.y;
+        a.g_pos[3 * p + 2] = gx.z + gxb.z;
+    }
+}
+
+hipError_t launch_backward(const BwdK &a, bool f16, bool indirect, hipStream_t s) {
+    const unsigned blocks = (unsigned)((a.r.n + kBwdThreads - 1) / kBwdThreads);
+    const size_t lds = (size_t)(kBwdThreads / 64) * kWaveLds * sizeof(float);
+    if (f16) {
+        if (indirect) hipLaunchKernelGGL((k_backward<__half, true>), dim3(blocks), dim3(kBwdThreads), lds, s, a);
+        else hipLaunchKernelGGL((k_backward<__half, false>), dim3(blocks), dim3(kBwdThreads), lds, s, a);
+    } else {
+        if (indirect) hipLaunchKernelGGL((k_backward<float, true>), dim3(blocks), dim3(kBwdThreads), lds, s, a);
+        else hipLaunchKernelGGL((k_backward<float, false>), dim3(blocks), dim3(kBwdThreads), lds, s, a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace hg

@@ -1,0 +1,451 @@
+// hg_device.h -- device building blocks of the gfx950 hash-grid renderer.
+//
+// Included by the .hip translation units only.  Every routine here works on
+// one query per lane (64-wide wavefronts); the matrix-core MLP lives in
+// hg_mfma.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace hg {
+
+constexpr int kL = 16;          // levels
+constexpr int kF = 2;           // features per level
+constexpr int kNF = kL * kF;    // feature width (32)
+constexpr int kH = 64;          // hidden width
+constexpr int kNI = kNF + 3;    // tracer input width (35)
+constexpr float kPi = 3.14159265358979323846f;
+
+// --------------------------------------------------------------------------
+// Kernel-side descriptors (passed by value as kernel arguments).
+// --------------------------------------------------------------------------
+struct GridK {
+    const void *table;      // [L][T][F] FP32 or FP16
+    uint32_t log2T, Tmask;
+    float lo, inv_ext;      // u = (x - lo) * inv_ext, inv_ext = 2^-k
+    float resf[kL];         // N_l as float (exact)
+    float nm1f[kL];         // N_l - 1 as float
+    float dscale[kL];       // N_l / extent (d u N_l / dx)
+    uint32_t stride[kL];    // N_l + 1 (dense levels)
+    uint32_t dense_mask;    // bit l set: level l is dense
+};
+
+struct MlpK {
+    const void *W0; const float *b0;
+    const void *W1; const float *b1;
+    const void *W2; const float *b2;
+};
+
+struct EnvK {
+    const float *rgb;  // [H][W][3]
+    int32_t H, W;
+    float Hf, Wf;
+};
+
+struct SampK {
+    uint32_t n_dirs, n_dirs2;
+    uint32_t key0, key1, flags;
+    uint32_t nb_shift, nb2_shift;   // log2 of the azimuth strata count
+    float inv_na, inv_nb, inv_na2, inv_nb2;
+    uint32_t g_shift;               // log2(min(n_dirs, 64)) (shade reduction)
+};
+
+struct RenderK {
+    GridK g;
+    MlpK brdf, irt;
+    EnvK env;
+    SampK s;
+    float t_near, t_span, f0;
+    const float *pos, *nrm, *wo, *dir;
+    float *rgb, *vis, *depth;
+    int64_t n;
+};
+
+// --------------------------------------------------------------------------
+// Small helpers
+// --------------------------------------------------------------------------
+__device__ __forceinline__ float clamp01(float u) { return fminf(fmaxf(u, 0.0f), 1.0f); }
+__device__ __forceinline__ float sigmoidf_(float z) { return 1.0f / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float softplusf_(float z) {
+    return fmaxf(z, 0.0f) + log1pf(__expf(-fabsf(z)));
+}
+
+// Weights are read through constant-address-space pointers so that the
+// wave-uniform reads become scalar loads.  The pointer is passed through an
+// empty asm statement at every MLP evaluation: this keeps the compiler from
+// hoisting thousands of loop-invariant weight loads out of the bounce loop.
+typedef __attribute__((address_space(4))) const float *cf32_p;
+typedef __attribute__((address_space(4))) const uint32_t *cu32_p;
+
+__device__ __forceinline__ uint64_t opaque64(const void *p) {
+    uint64_t v = reinterpret_cast<uint64_t>(p);
+    asm volatile("" : "+s"(v));
+    return v;
+}
+
+template <typename T> struct WPtr;
+template <> struct WPtr<float> {
+    cf32_p p;
+    __device__ __forceinline__ explicit WPtr(const void *q) : p((cf32_p)opaque64(q)) {}
+    __device__ __forceinline__ float operator[](int i) const { return p[i]; }
+};
+// BF16 stored as raw 16-bit patterns; read as 32-bit pairs.
+template <> struct WPtr<uint16_t> {
+    cu32_p p;
+    __device__ __forceinline__ explicit WPtr(const void *q) : p((cu32_p)opaque64(q)) {}
+    __device__ __forceinline__ float operator[](int i) const {
+        const uint32_t w = p[i >> 1];
+        return __uint_as_float((i & 1) ? (w & 0xffff0000u) : (w << 16));
+    }
+};
+struct BPtr {
+    cf32_p p;
+    __device__ __forceinline__ explicit BPtr(const float *q) : p((cf32_p)opaque64(q)) {}
+    __device__ __forceinline__ float operator[](int i) const { return p[i]; }
+};
+
+// --------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64-bit
+// products with the round multipliers, key bumped by the Weyl constants.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                               uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+__device__ __forceinline__ uint32_t pick4(const uint4 &w, uint32_t k) {
+    const uint32_t s = k & 3u;
+    return s == 0 ? w.x : (s == 1 ? w.y : (s == 2 ? w.z : w.w));
+}
+
+// Orthonormal basis about a unit normal (Duff et al., JCGT 2017).
+struct Frame { float3 t, b, n; };
+__device__ __forceinline__ Frame make_frame(float3 n) {
+    const float sgn = copysignf(1.0f, n.z);
+    const float a = -1.0f / (sgn + n.z);
+    const float bb = n.x * n.y * a;
+    Frame f;
+    f.t = make_float3(1.0f + sgn * n.x * n.x * a, sgn * bb, -sgn * n.x);
+    f.b = make_float3(bb, sgn + n.y * n.y * a, -n.y);
+    f.n = n;
+    return f;
+}
+
+// Stratified cosine-weighted direction for sample k of an N = n_a x n_b
+// stratification; `word` holds two 16-bit uniforms (bin centres).
+__device__ __forceinline__ float3 sample_dir(uint32_t word, uint32_t k, uint32_t nb_shift,
+                                             float inv_na, float inv_nb, const Frame &fr) {
+    const float u1 = ((float)(word & 0xffffu) + 0.5f) * (1.0f / 65536.0f);
+    const float u2 = ((float)(word >> 16) + 0.5f) * (1.0f / 65536.0f);
+    const uint32_t a = k >> nb_shift;
+    const uint32_t b = k & ((1u << nb_shift) - 1u);
+    const float s1 = ((float)a + u1) * inv_na;
+    const float s2 = ((float)b + u2) * inv_nb;
+    const float r = sqrtf(s1);
+    float sn, cs;
+    sincospif(2.0f * s2, &sn, &cs);
+    const float lx = r * cs, ly = r * sn, lz = sqrtf(1.0f - s1);
+    return make_float3(lx * fr.t.x + ly * fr.b.x + lz * fr.n.x,
+                       lx * fr.t.y + ly * fr.b.y + lz * fr.n.y,
+                       lx * fr.t.z + ly * fr.b.z + lz * fr.n.z);
+}
+
+// --------------------------------------------------------------------------
+// Hash-grid index stage.  The cell is floor of the exact product u*N: the
+// rounded product p and its exact error e (TwoProduct via fma) decide the
+// case p integral with e < 0.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ void cell_of(float u, float Nf, float nm1f, uint32_t &c, float &w) {
+    const float p = u * Nf;
+    const float e = fmaf(u, Nf, -p);
+    float fl = floorf(p);
+    if (fl == p && e < 0.0f) fl -= 1.0f;
+    fl = fminf(fl, nm1f);
+    c = (uint32_t)fl;
+    w = (p - fl) + e;
+}
+
+__device__ __forceinline__ uint32_t vidx(const GridK &g, int l, uint32_t x, uint32_t y, uint32_t z) {
+    if ((g.dense_mask >> l) & 1u) {
+        const uint32_t s = g.stride[l];
+        return x + s * (y + s * z);
+    }
+    return (x ^ (y * 2654435761u) ^ (z * 805459861u)) & g.Tmask;
+}
+
+// Table entry loads.  `lvl` is the wave-uniform base of one level and the
+// entry offset is a 32-bit byte offset, so the loads use the scalar-base +
+// 32-bit vector-offset addressing form (one VGPR per address).
+template <typename TT> struct TabLoad;
+template <> struct TabLoad<float> {
+    static __device__ __forceinline__ const void *level(const void *t, int l, uint32_t log2T) {
+        return static_cast<const char *>(t) + ((size_t)l << (log2T + 3));
+    }
+    static __device__ __forceinline__ float2 ld(const void *lvl, uint32_t idx) {
+        return *reinterpret_cast<const float2 *>(static_cast<const char *>(lvl) + (idx << 3));
+    }
+    static __device__ __forceinline__ float2 ld(const void *t, size_t e) {
+        return static_cast<const float2 *>(t)[e];
+    }
+};
+template <> struct TabLoad<__half> {
+    static __device__ __forceinline__ const void *level(const void *t, int l, uint32_t log2T) {
+        return static_cast<const char *>(t) + ((size_t)l << (log2T + 2));
+    }
+    static __device__ __forceinline__ float2 ld(const void *lvl, uint32_t idx) {
+        return __half22float2(*reinterpret_cast<const __half2 *>(static_cast<const char *>(lvl) + (idx << 2)));
+    }
+    static __device__ __forceinline__ float2 ld(const void *t, size_t e) {
+        return __half22float2(static_cast<const __half2 *>(t)[e]);
+    }
+};
+
+// Per-level cell record (enough to recompute weights and indices).
+struct LevelCell {
+    uint32_t c[3];
+    float w[3];
+};
+
+__device__ __forceinline__ void pos_to_u(const GridK &g, float x, float y, float z, float u[3],
+                                         bool inside[3]) {
+    const float r[3] = {(x - g.lo) * g.inv_ext, (y - g.lo) * g.inv_ext, (z - g.lo) * g.inv_ext};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        inside[d] = (r[d] > 0.0f) && (r[d] < 1.0f);
+        u[d] = clamp01(r[d]);
+    }
+}
+
+// Table indices of the 8 corners of cell c at level l (corner bit 0 = +x,
+// bit 1 = +y, bit 2 = +z).  The dense/hashed choice is wave-uniform.
+__device__ __forceinline__ void corner_idx(const GridK &g, int l, const uint32_t (&c)[3], uint32_t (&idx)[8]) {
+    // both index forms are computed and selected, keeping the encoder free
+    // of branches (one straight-line scheduling region per level group)
+    const bool dense = (g.dense_mask >> l) & 1u;
+    const uint32_t s = g.stride[l];
+    const uint32_t b = c[0] + s * (c[1] + s * c[2]);
+    const uint32_t hy0 = c[1] * 2654435761u, hy1 = hy0 + 2654435761u;
+    const uint32_t hz0 = c[2] * 805459861u, hz1 = hz0 + 805459861u;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const uint32_t di = b + (k & 1) + ((k >> 1) & 1) * s + ((k >> 2) & 1) * s * s;
+        const uint32_t hi = ((c[0] + (k & 1)) ^ ((k >> 1) & 1 ? hy1 : hy0) ^ ((k >> 2) & 1 ? hz1 : hz0)) & g.Tmask;
+        idx[k] = dense ? di : hi;
+    }
+}
+
+// f = H(x), features level-major.  Levels are processed in groups of four
+// (32 gathers in flight per lane); the scheduling barrier keeps the compiler
+// from hoisting all 128 gathers, which would exhaust the register file.
+template <typename TT>
+__device__ __forceinline__ void encode(const GridK &g, float x, float y, float z, float (&f)[kNF]) {
+    float u[3];
+    bool in[3];
+    pos_to_u(g, x, y, z, u, in);
+#pragma unroll
+    for (int l0 = 0; l0 < kL; l0 += 4) {
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int l = l0; l < l0 + 4; ++l) {
+            uint32_t c[3];
+            float w[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) cell_of(u[d], g.resf[l], g.nm1f[l], c[d], w[d]);
+            uint32_t idx[8];
+            corner_idx(g, l, c, idx);
+            const void *lvl = TabLoad<TT>::level(g.table, l, g.log2T);
+            float2 e[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) e[k] = TabLoad<TT>::ld(lvl, idx[k]);
+            const float wx0 = 1.0f - w[0], wy0 = 1.0f - w[1], wz0 = 1.0f - w[2];
+            float f0 = 0.0f, f1 = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const float wt = ((k & 1) ? w[0] : wx0) * (((k >> 1) & 1) ? w[1] : wy0) * (((k >> 2) & 1) ? w[2] : wz0);
+                f0 = fmaf(wt, e[k].x, f0);
+                f1 = fmaf(wt, e[k].y, f1);
+            }
+            f[2 * l] = f0;
+            f[2 * l + 1] = f1;
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// --------------------------------------------------------------------------
+// Environment lookup: y up, azimuth atan2(w_z, w_x), polar angle from +y,
+// texel centres at +1/2, bilinear, columns wrap, rows clamp.  Indices are
+// clamped so that any input (including NaN) stays inside the map.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ float3 env_lookup(const EnvK &e, float wx, float wy, float wz) {
+    const float phi = atan2f(wz, wx);
+    const float th = atan2f(sqrtf(wx * wx + wz * wz), wy);
+    const float s = (phi + kPi) * (e.Wf * (0.5f / kPi)) - 0.5f;
+    const float q = th * (e.Hf * (1.0f / kPi)) - 0.5f;
+    const float xf = floorf(s), yf = floorf(q);
+    const float fx = s - xf, fy = q - yf;
+    int x0 = (int)xf, y0 = (int)yf;
+    if (x0 < 0) x0 += e.W;
+    x0 = min(max(x0, 0), e.W - 1);
+    const int x1 = (x0 + 1 == e.W) ? 0 : x0 + 1;
+    const int y1 = min(max(y0 + 1, 0), e.H - 1);
+    y0 = min(max(y0, 0), e.H - 1);
+    const float *r0 = e.rgb + (size_t)y0 * e.W * 3;
+    const float *r1 = e.rgb + (size_t)y1 * e.W * 3;
+    const float w00 = (1.0f - fy) * (1.0f - fx), w01 = (1.0f - fy) * fx;
+    const float w10 = fy * (1.0f - fx), w11 = fy * fx;
+    float3 o;
+    o.x = w00 * r0[x0 * 3 + 0] + w01 * r0[x1 * 3 + 0] + w10 * r1[x0 * 3 + 0] + w11 * r1[x1 * 3 + 0];
+    o.y = w00 * r0[x0 * 3 + 1] + w01 * r0[x1 * 3 + 1] + w10 * r1[x0 * 3 + 1] + w11 * r1[x1 * 3 + 1];
+    o.z = w00 * r0[x0 * 3 + 2] + w01 * r0[x1 * 3 + 2] + w10 * r1[x0 * 3 + 2] + w11 * r1[x1 * 3 + 2];
+    return o;
+}
+
+// --------------------------------------------------------------------------
+// Microfacet BRDF: Lambert (1-m) a/pi + GGX D (alpha = r^2) * Schlick F
+// (F0 = mix(f0, a, m)) * height-correlated Smith visibility.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+
+struct BrdfTerms {
+    float D, Vis, P;         // specular factors and Schlick weight (1 - VdotH)^5
+    float dD_da2, dVis_da2;  // derivatives w.r.t. alpha^2
+    bool live;               // n.l > 0
+};
+
+__device__ __forceinline__ BrdfTerms brdf_terms(float3 n, float3 v, float3 l, float r, bool want_d) {
+    BrdfTerms t;
+    const float NdotL = dot3(n, l);
+    t.live = NdotL > 0.0f;
+    float NdotV = fmaxf(dot3(n, v), 1e-4f);
+    float3 h = make_float3(l.x + v.x, l.y + v.y, l.z + v.z);
+    const float hh = dot3(h, h);
+    if (hh > 0.0f) {
+        const float inv = rsqrtf(hh);
+        h = make_float3(h.x * inv, h.y * inv, h.z * inv);
+    } else {
+        h = n;
+    }
+    const float NdotH = fmaxf(dot3(n, h), 0.0f);
+    const float VdotH = fmaxf(dot3(v, h), 0.0f);
+    const float al = r * r, a2 = al * al;
+    const float Q = NdotH * NdotH * (a2 - 1.0f) + 1.0f;
+    t.D = a2 / (kPi * Q * Q);
+    const float sv = sqrtf(NdotV * NdotV * (1.0f - a2) + a2);
+    const float sl = sqrtf(NdotL * NdotL * (1.0f - a2) + a2);
+    const float A = NdotL * sv, B = NdotV * sl;
+    t.Vis = 0.5f / (A + B);
+    const float om = 1.0f - VdotH;
+    const float om2 = om * om;
+    t.P = om2 * om2 * om;
+    if (want_d) {
+        t.dD_da2 = (Q - 2.0f * a2 * NdotH * NdotH) / (kPi * Q * Q * Q);
+        const float dA = NdotL * (1.0f - NdotV * NdotV) / (2.0f * sv);
+        const float dB = NdotV * (1.0f - NdotL * NdotL) / (2.0f * sl);
+        t.dVis_da2 = -0.5f * (dA + dB) / ((A + B) * (A + B));
+    } else {
+        t.dD_da2 = t.dVis_da2 = 0.0f;
+    }
+    return t;
+}
+
+// pi * f_r per channel.
+__device__ __forceinline__ float3 pi_brdf(float3 n, float3 v, float3 l, float3 a, float r, float m, float f0,
+                                          bool diffuse_only) {
+    if (!(dot3(n, l) > 0.0f)) return make_float3(0.f, 0.f, 0.f);
+    if (diffuse_only) return a;
+    const BrdfTerms t = brdf_terms(n, v, l, r, false);
+    const float s = kPi * t.D * t.Vis;
+    const float q = 1.0f - t.P;
+    const float F0x = f0 * (1.0f - m) + a.x * m, F0y = f0 * (1.0f - m) + a.y * m, F0z = f0 * (1.0f - m) + a.z * m;
+    return make_float3((1.0f - m) * a.x + s * (F0x * q + t.P), (1.0f - m) * a.y + s * (F0y * q + t.P),
+                       (1.0f - m) * a.z + s * (F0z * q + t.P));
+}
+
+// --------------------------------------------------------------------------
+// Three-layer ReLU MLP on the vector ALU, one sample per lane.  Weights are
+// read with wave-uniform addresses (scalar loads); W[k] is [out][in].
+// --------------------------------------------------------------------------
+// Per-lane activation storage in LDS: column `lane` of a [64][kHS] array
+// (padded stride, so that both the per-lane rows and the per-unit columns
+// are read without bank conflicts).  Each lane reads back only what it wrote,
+// so no barrier is needed between a write and its read.
+constexpr int kHS = 65;
+constexpr int kHBuf = kH * kHS;   // floats per wave per activation buffer
+
+// out[o] = act(b[o] + sum_i W[o][i] in[i]) for o < NOUT, written to
+// hbuf[o * kHS + lane].  The loop over outputs is not unrolled: each
+// iteration reads one weight row with scalar loads.
+template <int NIN, typename WT, bool RELU>
+__device__ __forceinline__ void layer_to_lds(const void *W, const float *b, int nout, const float (&in)[NIN],
+                                             float *hbuf, int lane) {
+#pragma unroll 1
+    for (int o = 0; o < nout; ++o) {
+        const WPtr<WT> w(W);
+        const BPtr bb(b);
+        float acc = bb[o];
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) acc = fmaf(w[o * NIN + i], in[i], acc);
+        hbuf[o * kHS + lane] = RELU ? fmaxf(acc, 0.0f) : acc;
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void load_col(const float *hbuf, int lane, float (&h)[N]) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) h[i] = hbuf[i * kHS + lane];
+}
+
+// Three-layer ReLU MLP for one sample per lane.  h1buf/h2buf receive the
+// hidden activations (they may alias when the caller does not need h1).
+// Returns the last hidden layer in h (registers) and the outputs in out.
+template <int NIN, int NOUT, typename WT>
+__device__ __forceinline__ void mlp_fwd(const MlpK &m, const float (&in)[NIN], float *h1buf, float *h2buf, int lane,
+                                        float (&h)[kH], float (&out)[NOUT]) {
+    layer_to_lds<NIN, WT, true>(m.W0, m.b0, kH, in, h1buf, lane);
+    load_col(h1buf, lane, h);
+    layer_to_lds<kH, WT, true>(m.W1, m.b1, kH, h, h2buf, lane);
+    load_col(h2buf, lane, h);
+    const WPtr<WT> W2(m.W2);
+    const BPtr b2(m.b2);
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) {
+        float acc = b2[o];
+#pragma unroll
+        for (int i = 0; i < kH; ++i) acc = fmaf(W2[o * kH + i], h[i], acc);
+        out[o] = acc;
+    }
+}
+
+// Compensated accumulation (Kahan) and exact pairwise combination (TwoSum).
+struct KSum {
+    float s, c;
+    __device__ __forceinline__ void add(float x) {
+        const float y = x - c;
+        const float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+};
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
+    s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+}  // namespace hg

@@ -1,0 +1,30 @@
+// hg_launch.h -- host-side launchers shared between the translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hg_device.h"
+
+namespace hg {
+
+struct BwdK {
+    RenderK r;
+    const float *g_rgb, *g_vis, *g_dep;
+    float *g_table;
+    float *gb[6];
+    float *gi[6];
+    float *g_pos;
+};
+
+hipError_t launch_encode(const GridK &g, bool f16, const float *pos, int64_t n, float *feat, hipStream_t s);
+hipError_t launch_encode_index(const GridK &g, const float *pos, int64_t n, uint32_t *idx, float *w, hipStream_t s);
+hipError_t launch_render_f32(const RenderK &a, bool indirect, bool query, hipStream_t s);
+hipError_t launch_render_mixed(const RenderK &a, bool indirect, bool query, hipStream_t s);
+hipError_t launch_backward(const BwdK &a, bool f16, bool indirect, hipStream_t s);
+hipError_t launch_l2_loss(const float *rgb, const float *vis, const float *dep, const float *tgt, int64_t n,
+                          float *loss, float *g_rgb, float *g_vis, float *g_dep, hipStream_t s);
+hipError_t launch_adam(float *param, const float *grad, float *m, float *v, int64_t n, float lr, float b1,
+                       float b2, float eps, float wd, float bc1, float bc2, void *shadow, int shadow_kind,
+                       hipStream_t s);
+
+}  // namespace hg

@@ -1,0 +1,137 @@
+"""Host-only checks of the C ABI: the library loads, exports every symbol
+declared in include/hg.h, and rejects malformed arguments on the host before
+any device work (these calls never reach the GPU)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_2409_10327_amd as hg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    src = open(os.path.join(ROOT, "include", "hg.h")).read()
+    return sorted(set(re.findall(r"^(?:hg_status|const char \*)\s*(hg_\w+)\s*\(", src, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    syms = header_symbols()
+    assert len(syms) == 8, syms
+    L = hg.lib()
+    for s in syms:
+        assert hasattr(L, s), s
+    assert set(syms) == set(hg.EXPORTS)
+
+
+FAKE = 0x7f0000000000  # 16-byte aligned non-null placeholder (never dereferenced)
+
+
+def fake_model(**over):
+    m = hg.Model()
+    g = m.grid
+    g.L, g.F, g.log2_T = 16, 2, 14
+    for i, r in enumerate([16, 20, 25, 32, 40, 50, 64, 80, 101, 128, 161, 203, 256, 322, 406, 512]):
+        g.res[i] = r
+    g.box_lo, g.box_extent, g.dtype, g.table = -8.0, 16.0, hg.HG_F32, FAKE
+    for mm, nin, nout in ((m.brdf, 32, 5), (m.irt, 35, 2)):
+        mm.n_in, mm.n_hidden, mm.n_out, mm.dtype = nin, 64, nout, hg.HG_F32
+        for k in range(3):
+            mm.W[k] = FAKE
+            mm.b[k] = FAKE
+    m.t_near, m.t_far, m.f0 = 0.05, 1.5, 0.04
+    for k, v in over.items():
+        obj, attr = k.split(".") if "." in k else (None, k)
+        setattr(getattr(m, obj) if obj else m, attr, v)
+    return m
+
+
+def call_render(m=None, env=None, samp=None, pts=None, rgb=FAKE):
+    m = m or fake_model()
+    if env is None:
+        env = hg.Env(); env.H, env.W, env.rgb = 16, 32, FAKE
+    samp = samp or hg.sampling_struct(32, 8, 7, 0)
+    if pts is None:
+        pts = hg.Points(); pts.n, pts.pos, pts.nrm, pts.wo, pts.dir = 10, FAKE, FAKE, FAKE, None
+    return hg.lib().hg_render_indirect(C.byref(m), C.byref(env), C.byref(samp), C.byref(pts), C.c_void_p(rgb),
+                                       None, None, None)
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("grid.F", 3, hg.HG_E_UNSUPPORTED),
+    ("grid.L", 14, hg.HG_E_UNSUPPORTED),
+    ("grid.log2_T", 9, hg.HG_E_INVALID),
+    ("grid.log2_T", 25, hg.HG_E_INVALID),
+    ("grid.box_extent", 12.0, hg.HG_E_INVALID),
+    ("grid.table", 0, hg.HG_E_INVALID),
+    ("grid.table", FAKE + 4, hg.HG_E_INVALID),
+    ("grid.dtype", 7, hg.HG_E_INVALID),
+    ("t_far", 0.01, hg.HG_E_INVALID),
+])
+def test_model_validation(field, value, status):
+    assert call_render(fake_model(**{field: value})) == status
+    assert hg.lib().hg_last_error().decode() != ""
+
+
+def test_mlp_shape_and_dtype_pairs():
+    m = fake_model()
+    m.brdf.n_hidden = 32
+    assert call_render(m) == hg.HG_E_UNSUPPORTED
+    m = fake_model()
+    m.irt.n_in = 34
+    assert call_render(m) == hg.HG_E_UNSUPPORTED
+    m = fake_model()
+    m.brdf.dtype = hg.HG_BF16
+    assert call_render(m) == hg.HG_E_INVALID  # brdf and irt dtypes differ
+    m = fake_model()
+    m.grid.dtype = hg.HG_F16   # F16 table + F32 MLPs: backward only
+    assert call_render(m) == hg.HG_E_UNSUPPORTED
+
+
+def test_res_must_increase():
+    m = fake_model()
+    m.grid.res[5] = m.grid.res[4]
+    assert call_render(m) == hg.HG_E_INVALID
+
+
+@pytest.mark.parametrize("n_dirs,n_dirs2", [(0, 8), (3, 8), (2048, 8), (32, 0), (32, 6), (32, 128)])
+def test_sampling_validation(n_dirs, n_dirs2):
+    assert call_render(samp=hg.sampling_struct(n_dirs, n_dirs2, 7, 0)) == hg.HG_E_INVALID
+
+
+def test_points_validation():
+    p = hg.Points(); p.n, p.pos, p.nrm, p.wo, p.dir = 10, FAKE, None, FAKE, None
+    assert call_render(pts=p) == hg.HG_E_INVALID            # shade mode needs normals
+    p = hg.Points(); p.n, p.pos, p.nrm, p.wo, p.dir = -1, FAKE, FAKE, FAKE, None
+    assert call_render(pts=p) == hg.HG_E_INVALID
+    p = hg.Points(); p.n, p.pos, p.nrm, p.wo, p.dir = 0, None, None, None, None
+    assert call_render(pts=p, rgb=0) == hg.HG_OK            # n == 0 is a no-op
+    assert call_render(rgb=0) == hg.HG_E_INVALID
+
+
+def test_other_entry_points_validate():
+    L = hg.lib()
+    g = fake_model().grid
+    assert L.hg_encode(C.byref(g), C.c_void_p(FAKE), 10, None, None) == hg.HG_E_INVALID
+    assert L.hg_encode(C.byref(g), None, 0, None, None) == hg.HG_OK
+    assert L.hg_encode_index(C.byref(g), C.c_void_p(FAKE), 10, None, None, None) == hg.HG_E_INVALID
+    assert L.hg_l2_loss(None, None, None, None, 5, C.c_void_p(FAKE), None, None, None, None) == hg.HG_E_INVALID
+    assert L.hg_adam_step(C.c_void_p(FAKE), C.c_void_p(FAKE), C.c_void_p(FAKE), C.c_void_p(FAKE), 10, 0,
+                          1e-3, 0.9, 0.999, 1e-8, 0.0, None, 0, None) == hg.HG_E_INVALID
+    assert L.hg_adam_step(C.c_void_p(FAKE), C.c_void_p(FAKE), C.c_void_p(FAKE), C.c_void_p(FAKE), 10, 1,
+                          1e-3, 1.0, 0.999, 1e-8, 0.0, None, 0, None) == hg.HG_E_INVALID
+    m = fake_model()
+    env = hg.Env(); env.H, env.W, env.rgb = 16, 32, FAKE
+    s = hg.sampling_struct(1, 8, 7, 0)
+    p = hg.Points(); p.n, p.pos, p.nrm, p.wo, p.dir = 10, FAKE, FAKE, FAKE, None
+    gb = (C.c_void_p * 6)(*[FAKE] * 6)
+    # backward needs query-mode points
+    assert L.hg_backward(C.byref(m), C.byref(env), C.byref(s), C.byref(p), 1, C.c_void_p(FAKE), C.c_void_p(FAKE),
+                         C.c_void_p(FAKE), C.c_void_p(FAKE), gb, gb, None, None) == hg.HG_E_INVALID
+    m.brdf.dtype = m.irt.dtype = hg.HG_BF16
+    m.grid.dtype = hg.HG_F16
+    p.dir = FAKE
+    assert L.hg_backward(C.byref(m), C.byref(env), C.byref(s), C.byref(p), 1, C.c_void_p(FAKE), C.c_void_p(FAKE),
+                         C.c_void_p(FAKE), C.c_void_p(FAKE), gb, gb, None, None) == hg.HG_E_UNSUPPORTED

@@ -1,0 +1,161 @@
+"""GPU parity of the training entry points (backward, loss, Adam) against the
+FP64 oracle, plus the FP64 central-difference check of the GPU gradients."""
+import numpy as np
+import pytest
+import torch
+
+import hg_inputs as H
+import paper_2409_10327_amd as hg
+from oracle import oracle as O
+from helpers import relerr
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def setup():
+    cfg = H.config("c1")
+    model = H.make_model(cfg)
+    # keep the depth head off its clamp so the bounce-point path is exercised
+    model["irt"][5] = np.array([0.2, -0.5], np.float32)
+    env = H.make_env(cfg.env_h, cfg.env_w)
+    r = hg.HashRenderer(model, DEV)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    om, oe = O.OracleModel(model, H.BOX_LO, H.BOX_EXTENT), O.OracleEnv(env)
+    return dict(cfg=cfg, model=model, env=env, r=r, t=t, om=om, oe=oe, env_t=t(env))
+
+
+@pytest.mark.parametrize("indirect", [True, False])
+@pytest.mark.parametrize("n", [1, 77, 1030])
+def test_backward_parity(setup, indirect, n):
+    print(f"case: backward indirect={indirect} n={n}", flush=True)
+    t = setup["t"]
+    pos, dirs = H.make_train_batch(n, seed=21)
+    rng = np.random.default_rng(5)
+    g_rgb = rng.standard_normal((n, 3)).astype(np.float32)
+    g_vis = rng.standard_normal(n).astype(np.float32)
+    g_dep = rng.standard_normal(n).astype(np.float32)
+    grads = hg.zero_grads(setup["r"])
+    g_pos = torch.empty((n, 3), device=DEV)
+    hg.backward(setup["r"], setup["env_t"], t(pos), t(dirs), t(g_rgb), t(g_vis), t(g_dep), grads,
+                indirect=indirect, g_pos=g_pos)
+    ref = O.backward(setup["om"], setup["oe"], O.sampling(1, 8, 7, 0), pos, dirs, g_rgb, g_vis, g_dep,
+                     indirect=indirect, want_pos=True)
+    assert relerr(grads["table"].cpu().numpy(), ref["table"]) < 1e-5
+    for k in ("brdf", "irt"):
+        for i in range(6):
+            a, b = grads[k][i].cpu().numpy(), ref[k][i]
+            if not indirect and k == "brdf":
+                assert np.all(a == 0) and np.all(b == 0)
+                continue
+            assert relerr(a, b) < 1e-5, (k, i, relerr(a, b))
+    assert relerr(g_pos.cpu().numpy(), ref["pos"]) < 1e-5
+
+
+def test_gpu_gradients_vs_central_differences(setup):
+    """64 sampled parameters (32 table entries across levels, 32 MLP
+    weights/biases across both MLPs and all layers): GPU analytic gradient
+    of L = sum(g . outputs) vs FP64 central differences of the oracle."""
+    print("case: GPU gradients vs FP64 central differences", flush=True)
+    from test_oracle_pins import _fd
+    model, env = setup["model"], setup["env"]
+    n = 64
+    pos, dirs = H.make_train_batch(n, seed=31)
+    rng = np.random.default_rng(7)
+    g_rgb = rng.standard_normal((n, 3)).astype(np.float32)
+    g_vis = rng.standard_normal(n).astype(np.float32)
+    g_dep = rng.standard_normal(n).astype(np.float32)
+    t = setup["t"]
+    grads = hg.zero_grads(setup["r"])
+    hg.backward(setup["r"], setup["env_t"], t(pos), t(dirs), t(g_rgb), t(g_vis), t(g_dep), grads)
+    G = dict(table=grads["table"].cpu().numpy(), brdf=[g.cpu().numpy() for g in grads["brdf"]],
+             irt=[g.cpu().numpy() for g in grads["irt"]])
+    samp = O.sampling(1, 8, 7, 0)
+    cand = []
+    nz = np.argwhere(np.abs(G["table"]) > 1e-5)
+    levels = np.unique(nz[:, 0])
+    per = max(1, 32 // len(levels))
+    for l in levels:
+        rows = nz[nz[:, 0] == l]
+        for r in rows[rng.permutation(len(rows))[:per]]:
+            cand.append(("table", tuple(r)))
+    for k in ("brdf", "irt"):
+        for i in range(6):
+            flat = np.argwhere(np.abs(G[k][i]) > 1e-6)
+            for r in flat[rng.permutation(len(flat))[:6]]:
+                cand.append(((k, i), tuple(r)))
+    checked = 0
+    for key, index in cand:
+        if checked >= 64:
+            break
+        ana = G["table"][index] if key == "table" else G[key[0]][key[1]][index]
+        fd1 = _fd(model, key, index, env, pos, dirs, g_rgb, g_vis, g_dep, samp, 1e-4)
+        fd2 = _fd(model, key, index, env, pos, dirs, g_rgb, g_vis, g_dep, samp, 2.5e-5)
+        scale = max(abs(fd1), abs(fd2), 1e-3)
+        if abs(fd1 - fd2) > 1e-6 * scale:
+            continue
+        assert abs(ana - fd1) <= 1e-4 * scale + 1e-6, (key, index, ana, fd1)
+        checked += 1
+    assert checked >= 48, checked
+
+
+def test_l2_loss_parity(setup):
+    t = setup["t"]
+    n = 1 << 14
+    rng = np.random.default_rng(2)
+    rgb = rng.standard_normal((n, 3)).astype(np.float32)
+    vis = rng.uniform(0, 1, n).astype(np.float32)
+    dep = rng.uniform(0, 1, n).astype(np.float32)
+    tgt = H.make_targets(n)
+    loss, gr, gv, gd = hg.l2_loss(t(rgb), t(vis), t(dep), t(tgt))
+    ol, ogr, ogv, ogd = O.l2_loss(rgb, vis, dep, tgt)
+    assert abs(loss.item() / ol - 1) < 1e-5
+    for a, b in ((gr, ogr), (gv, ogv), (gd, ogd)):
+        assert relerr(a.cpu().numpy(), b) < 1e-6
+
+
+@pytest.mark.parametrize("n,shadow", [(1, None), (1027, "f16"), (4096, "bf16")])
+def test_adam_parity(setup, n, shadow):
+    t = setup["t"]
+    rng = np.random.default_rng(3)
+    p = rng.standard_normal(n).astype(np.float32)
+    g = rng.standard_normal(n).astype(np.float32)
+    m = (rng.standard_normal(n) * 0.1).astype(np.float32)
+    v = rng.uniform(0, 0.1, n).astype(np.float32)
+    pt, mt, vt = t(p), t(m), t(v)
+    sh = None
+    if shadow == "f16":
+        sh = torch.empty(n, dtype=torch.float16, device=DEV)
+    elif shadow == "bf16":
+        sh = torch.empty(n, dtype=torch.bfloat16, device=DEV)
+    hg.adam_step(pt, t(g), mt, vt, 3, lr=2e-3, weight_decay=1e-6, shadow=sh)
+    op, om_, ov = O.adam(p, g, m, v, 3, lr=2e-3, wd=1e-6)
+    assert relerr(pt.cpu().numpy(), op) < 1e-6
+    assert relerr(mt.cpu().numpy(), om_) < 1e-6 and relerr(vt.cpu().numpy(), ov) < 1e-6
+    if sh is not None:
+        assert torch.equal(sh, pt.to(sh.dtype))
+
+
+def test_autograd_function_matches_backward(setup):
+    t = setup["t"]
+    r = setup["r"]
+    n = 300
+    pos, dirs = H.make_train_batch(n, seed=41)
+    params = [r.table] + r.brdf + r.irt
+    for p_ in params:
+        p_.requires_grad_(True)
+    try:
+        rgb, vis, dep = hg.HGQueryFn.apply(r, setup["env_t"], t(pos), t(dirs), 8, 7, True, "fp32", *params)
+        (rgb.sum() + 2 * vis.sum() - dep.sum()).backward()
+        grads = hg.zero_grads(r)
+        ones = torch.ones((n, 3), device=DEV)
+        hg.backward(r, setup["env_t"], t(pos), t(dirs), ones, torch.full((n,), 2.0, device=DEV),
+                    torch.full((n,), -1.0, device=DEV), grads)
+        assert relerr(r.table.grad.cpu().numpy(), grads["table"].cpu().numpy()) < 1e-6
+        for a, b in zip(r.irt, grads["irt"]):
+            assert relerr(a.grad.cpu().numpy(), b.cpu().numpy()) < 1e-6
+    finally:
+        for p_ in params:
+            p_.requires_grad_(False)
+            p_.grad = None
