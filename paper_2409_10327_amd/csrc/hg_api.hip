@@ -194,6 +194,7 @@ hg_status render(const hg_model *model, const hg_env *env, const hg_sampling *sa
     CHECK(check_points(pts, query));
     CHECK(check_sampling(samp, !query, k.s));
     SUPPORT(prec != Prec::F16TableF32Mlp, "rendering needs (F32 table, F32 MLP) or (F16 table, BF16 MLP)");
+    SUPPORT(prec != Prec::Mixed || query || samp->n_dirs >= 16, "the mixed path needs n_dirs >= 16 in shade mode");
     if (pts->n == 0) return HG_OK;
     CHECK(check_ptr(rgb, "rgb"));
     if (query) {

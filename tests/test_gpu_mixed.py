@@ -1,0 +1,72 @@
+"""GPU parity of the mixed-precision path (FP16 tables, BF16 matrix-core MLPs,
+FP32 accumulation) against the FP64 oracle evaluated on the FP32 masters,
+so quantisation error counts as error.  Bar: radiance <= 2e-3 norm-wise
+relative error and >= 45 dB PSNR; visibility and depth errors are reported
+and bounded."""
+import numpy as np
+import pytest
+import torch
+
+import hg_inputs as H
+import paper_2409_10327_amd as hg
+from oracle import oracle as O
+from helpers import c1_setup, max_rel, psnr, relerr
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def c1():
+    cfg, model, env, pos, nrm, wo = c1_setup()
+    r = hg.HashRenderer(model, DEV)
+    r.refresh_shadows()
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    return dict(cfg=cfg, model=model, env=env, pos=pos, nrm=nrm, wo=wo, r=r, t=t,
+                om=O.OracleModel(model, H.BOX_LO, H.BOX_EXTENT), oe=O.OracleEnv(env))
+
+
+@pytest.mark.parametrize("indirect", [False, True])
+def test_mixed_shade_c1(c1, indirect):
+    print(f"case: mixed shade indirect={indirect}, c1 frame", flush=True)
+    cfg, t = c1["cfg"], c1["t"]
+    rgb, vis, dep = hg.render(c1["r"], t(c1["env"]), t(c1["pos"]), t(c1["nrm"]), t(c1["wo"]), n_dirs=cfg.n_dirs,
+                              indirect=indirect, want_vis=True, precision="mixed")
+    s = O.sampling(cfg.n_dirs, 8, 7, 0)
+    orgb, ovis, odep = O.render(c1["om"], c1["oe"], s, c1["pos"], c1["nrm"], c1["wo"], indirect=indirect)
+    rgb, vis, dep = rgb.cpu().numpy(), vis.cpu().numpy(), dep.cpu().numpy()
+    e = (relerr(rgb, orgb), psnr(rgb, orgb), relerr(vis, ovis), relerr(dep, odep))
+    print("mixed: rgb rel %.3g psnr %.1f dB vis rel %.3g depth rel %.3g" % e)
+    assert e[0] < 2e-3 and e[1] >= 45.0
+    assert e[2] < 5e-3 and e[3] < 5e-3
+
+
+@pytest.mark.parametrize("indirect", [False, True])
+def test_mixed_query_c1(c1, indirect):
+    print(f"case: mixed query indirect={indirect}", flush=True)
+    t = c1["t"]
+    pos, dirs = H.make_train_batch(4099, seed=12)
+    rgb, vis, dep = hg.render(c1["r"], t(c1["env"]), t(pos), dirs=t(dirs), indirect=indirect, precision="mixed")
+    orgb, ovis, odep = O.render(c1["om"], c1["oe"], O.sampling(1, 8, 7, 0), pos, dirs=dirs, indirect=indirect)
+    e = (relerr(rgb.cpu().numpy(), orgb), relerr(vis.cpu().numpy(), ovis), relerr(dep.cpu().numpy(), odep))
+    print("mixed query: rgb %.3g vis %.3g depth %.3g" % e)
+    assert e[0] < 2e-3 and e[1] < 5e-3 and e[2] < 5e-3
+
+
+@pytest.mark.parametrize("N,npix", [(16, 67), (32, 33), (64, 3), (256, 2)])
+def test_mixed_sample_counts_and_ragged(c1, N, npix):
+    print(f"case: mixed shade N={N} npix={npix}", flush=True)
+    t = c1["t"]
+    sl = slice(1000, 1000 + npix)
+    pos, nrm, wo = c1["pos"][sl], c1["nrm"][sl], c1["wo"][sl]
+    rgb = hg.render(c1["r"], t(c1["env"]), t(pos), t(nrm), t(wo), n_dirs=N, precision="mixed")[0]
+    orgb = O.render(c1["om"], c1["oe"], O.sampling(N, 8, 7, 0), pos, nrm, wo, indirect=True)[0]
+    assert relerr(rgb.cpu().numpy(), orgb) < 2e-3
+
+
+def test_mixed_deterministic(c1):
+    t = c1["t"]
+    args = (c1["r"], t(c1["env"]), t(c1["pos"]), t(c1["nrm"]), t(c1["wo"]))
+    a = hg.render(*args, n_dirs=32, precision="mixed")[0]
+    b = hg.render(*args, n_dirs=32, precision="mixed")[0]
+    assert torch.equal(a, b)
