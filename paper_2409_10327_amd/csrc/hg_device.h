@@ -171,6 +171,9 @@ __device__ __forceinline__ float3 sample_dir(uint32_t word, uint32_t k, uint32_t
 // case p integral with e < 0.
 // --------------------------------------------------------------------------
 __device__ __forceinline__ void cell_of(float u, float Nf, float nm1f, uint32_t &c, float &w) {
+    // no contraction here: fusing u*Nf - fl into one fma would add the
+    // product's rounding error e to w a second time
+#pragma clang fp contract(off)
     const float p = u * Nf;
     const float e = fmaf(u, Nf, -p);
     float fl = floorf(p);

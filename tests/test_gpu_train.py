@@ -130,7 +130,9 @@ def test_adam_parity(setup, n, shadow):
     elif shadow == "bf16":
         sh = torch.empty(n, dtype=torch.bfloat16, device=DEV)
     hg.adam_step(pt, t(g), mt, vt, 3, lr=2e-3, weight_decay=1e-6, shadow=sh)
-    op, om_, ov = O.adam(p, g, m, v, 3, lr=2e-3, wd=1e-6)
+    # the library receives FP32 hyper-parameters; the oracle gets the same values
+    f = lambda x: float(np.float32(x))
+    op, om_, ov = O.adam(p, g, m, v, 3, lr=f(2e-3), b1=f(0.9), b2=f(0.999), eps=f(1e-8), wd=f(1e-6))
     assert relerr(pt.cpu().numpy(), op) < 1e-6
     assert relerr(mt.cpu().numpy(), om_) < 1e-6 and relerr(vt.cpu().numpy(), ov) < 1e-6
     if sh is not None:
