@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP32_VEC_PEAK_TFLOPS = 157.3
+FP32_MFMA_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 
 # Algorithmic work per secondary query (one (pixel, direction) pair):
@@ -118,9 +118,9 @@ def main():
                    "shaded_px_per_s": P / (ms * 1e-3), "secondary_queries": S},
     }
     achieved = FLOP_PER_QUERY * S / (ms * 1e-3) / 1e12
-    out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": FP32_VEC_PEAK_TFLOPS, "unit": "TFLOP/s",
-                       "frac": achieved / FP32_VEC_PEAK_TFLOPS, "traffic": None,
-                       "kernel": "k_render_shade<true> (FP32)"}
+    out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": None,
+                       "kernel": "k_render_mma<F32Path, indirect, shade>"}
 
     if not args.no_mixed:
         try:
@@ -136,7 +136,8 @@ def main():
             out["mixed"] = {"value": S / (msm * 1e-3), "ms_per_step": msm, "shaded_px_per_s": P / (msm * 1e-3),
                             "dtype": "bf16-mfma/f16-table/f32-acc",
                             "roofline": {"bound": "mfma", "achieved": a_m, "peak": BF16_MFMA_PEAK_TFLOPS,
-                                         "unit": "TFLOP/s", "frac": a_m / BF16_MFMA_PEAK_TFLOPS}}
+                                         "unit": "TFLOP/s", "frac": a_m / BF16_MFMA_PEAK_TFLOPS,
+                                         "kernel": "k_render_mma<Bf16Path, indirect, shade>"}}
         except hg.HGError as e:
             out["mixed"] = {"unavailable": str(e)}
 

@@ -214,8 +214,13 @@ hg_status render(const hg_model *model, const hg_env *env, const hg_sampling *sa
     k.vis = vis;
     k.depth = depth;
     k.n = pts->n;
-    hipError_t e = prec == Prec::F32 ? hg::launch_render_f32(k, indirect, query, stream)
-                                     : hg::launch_render_mixed(k, indirect, query, stream);
+    // FP32: matrix-core kernel for query mode and for shade mode with at
+    // least 16 directions per point (at most four points per wave); the
+    // vector-ALU kernel covers 1..8 directions.
+    hipError_t e;
+    if (prec == Prec::Mixed) e = hg::launch_render_mixed(k, indirect, query, stream);
+    else if (query || samp->n_dirs >= 16) e = hg::launch_render_f32_mma(k, indirect, query, stream);
+    else e = hg::launch_render_f32(k, indirect, query, stream);
     return hip_status(e, indirect ? "hg_render_indirect" : "hg_render_direct");
 }
 

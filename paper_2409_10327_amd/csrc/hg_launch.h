@@ -19,6 +19,7 @@ struct BwdK {
 hipError_t launch_encode(const GridK &g, bool f16, const float *pos, int64_t n, float *feat, hipStream_t s);
 hipError_t launch_encode_index(const GridK &g, const float *pos, int64_t n, uint32_t *idx, float *w, hipStream_t s);
 hipError_t launch_render_f32(const RenderK &a, bool indirect, bool query, hipStream_t s);
+hipError_t launch_render_f32_mma(const RenderK &a, bool indirect, bool query, hipStream_t s);
 hipError_t launch_render_mixed(const RenderK &a, bool indirect, bool query, hipStream_t s);
 hipError_t launch_backward(const BwdK &a, bool f16, bool indirect, hipStream_t s);
 hipError_t launch_l2_loss(const float *rgb, const float *vis, const float *dep, const float *tgt, int64_t n,

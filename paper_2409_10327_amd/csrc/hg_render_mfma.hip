@@ -1,8 +1,10 @@
-// hg_render_mfma.hip -- mixed-precision forward on the CDNA4 matrix cores.
+// hg_render_mfma.hip -- forward on the CDNA4 matrix cores, FP32 and mixed.
 //
-// FP16 hash tables gathered with FP32 interpolation; both MLPs run as
-// v_mfma_f32_16x16x32_bf16 tiles (BF16 operands, FP32 accumulation); the
-// light-direction sum is compensated FP32.
+// Two precisions share one kernel body:
+//   FP32:  FP32 tables, FP32 weights, v_mfma_f32_16x16x4f32 (K = 4 per step);
+//   mixed: FP16 tables (FP32 interpolation), BF16 weights and activations,
+//          v_mfma_f32_16x16x32_bf16 (K = 32 per step), FP32 accumulation.
+// The light-direction sum is compensated FP32 in both.
 //
 // Work decomposition.  A wave owns 64 queries (one per lane) for the scalar
 // work: direction sampling, hash-grid gathers, environment lookups, BRDF.
@@ -10,19 +12,17 @@
 // matrix-core products with the units of a layer as rows (M) and the
 // queries as columns (N):
 //   layer output D (16x16 per M-tile): lane l holds rows 4*(l/16)+r,
-//   column l%16 -- so the fp32 accumulators of one layer, after ReLU and
-//   conversion to BF16, are already the B operand of the next layer once the
-//   weight columns are permuted accordingly (no data movement between
-//   layers).
+//   column l%16 -- so the accumulators of one layer, after ReLU (and, mixed,
+//   conversion to BF16), are already the B operand of the next layer once
+//   the weight columns are permuted accordingly (no data movement between
+//   layers);
 //   head rows are replicated so that every lane group receives the outputs
 //   of its column; lane l keeps N-tile l/16, which is its own query.
 // Inputs that come from other lanes (features, directions) go through LDS.
 // The tracer's first layer is split into a per-point part (W0f f + b0,
-// computed once per point and kept in registers as the accumulator input)
-// and a direction part (one matrix-core step with the direction split into
-// BF16 high and low halves).
-// Weight tiles are built once per workgroup in LDS in operand order; the
-// tracer's hot tiles are then held in registers.
+// computed once per point and used as the accumulator input) and a
+// direction part (one matrix-core step; the mixed path splits the direction
+// into BF16 high and low halves).
 #include <hip/hip_bf16.h>
 
 #include "hg_device.h"
@@ -34,9 +34,12 @@ typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef short s16x2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ f32x4 mfma(const uint4 &a, const uint4 &b, const f32x4 &c) {
+__device__ __forceinline__ f32x4 mfma_bf16(const uint4 &a, const uint4 &b, const f32x4 &c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b),
                                                     c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mfma_f32(float a, float b, const f32x4 &c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
 // Round-to-nearest-even FP32 -> BF16 of two values, packed (lo = a).
@@ -53,8 +56,8 @@ __device__ __forceinline__ uint32_t relu_bf16x2(uint32_t v) {
     return __builtin_bit_cast(uint32_t, s);
 }
 
-// Two accumulator tiles (M-tiles 2s and 2s+1 of one N-tile) -> B operand of
-// K-step s of the next layer, with ReLU.
+// Two accumulator tiles (M-tiles 2s and 2s+1 of one N-tile) -> BF16 B
+// operand of K-step s of the next layer, with ReLU.
 __device__ __forceinline__ uint4 act_pack(const f32x4 &d0, const f32x4 &d1) {
     uint4 r;
     r.x = relu_bf16x2(pack_bf16(d0[0], d0[1]));
@@ -64,80 +67,18 @@ __device__ __forceinline__ uint4 act_pack(const f32x4 &d0, const f32x4 &d1) {
     return r;
 }
 
-// Physical hidden unit feeding logical input k = 32 s + 8 g + e of a layer
-// whose input is the previous layer's accumulator tiles.
-__device__ __forceinline__ int unit_of(int s, int g, int e) { return 16 * (2 * s + (e >> 2)) + 4 * g + (e & 3); }
-
-// ----------------------------------------------------------------------------
-// Operand tiles in LDS: 64 lanes x 16 bytes each.
-// ----------------------------------------------------------------------------
-enum : int {
-    T_W0W = 0,     // tracer direction part, 4 M-tiles
-    T_W0F = 4,     // tracer feature part, 4 M-tiles
-    T_W1 = 8,      // tracer hidden layer, 4 M-tiles x 2 K-steps (m*2+s)
-    T_W2 = 16,     // tracer head, 2 K-steps
-    B_W0 = 18,     // decoder first layer, 4 M-tiles
-    B_W1 = 22,     // decoder hidden layer, 4 x 2
-    B_W2A = 30,    // decoder head outputs 0..3, 2 K-steps
-    B_W2B = 32,    // decoder head output 4, 2 K-steps
-    N_TILES = 34
-};
+// Physical hidden unit feeding logical input k of a layer whose input is the
+// previous layer's accumulator tiles.  BF16 (K-step s of 32, lane group g,
+// element e): k = 32 s + 8 g + e.  FP32 (K-step s of 4, lane group g):
+// k = 4 s + g.
+__device__ __forceinline__ int unit_bf16(int s, int g, int e) { return 16 * (2 * s + (e >> 2)) + 4 * g + (e & 3); }
+__device__ __forceinline__ int unit_f32(int s, int g) { return 16 * (s >> 2) + 4 * g + (s & 3); }
 
 __device__ __forceinline__ float wbf(const void *W, int idx) {
     return __uint_as_float((uint32_t) static_cast<const uint16_t *>(W)[idx] << 16);
 }
+__device__ __forceinline__ float wf(const void *W, int idx) { return static_cast<const float *>(W)[idx]; }
 
-// Value of operand tile `t` for lane position (i = row, g = k-group, e).
-__device__ float tile_value(const RenderK &a, int t, int i, int g, int e) {
-    if (t < T_W0F) {  // direction part: k-group 0 holds (w_hi, w_lo) coefficients
-        const int m = t - T_W0W;
-        if (g != 0 || e >= 6) return 0.0f;
-        return wbf(a.irt.W0, (16 * m + i) * kNI + kNF + (e % 3));
-    }
-    if (t < T_W1) {
-        const int m = t - T_W0F;
-        return wbf(a.irt.W0, (16 * m + i) * kNI + 8 * g + e);
-    }
-    if (t < T_W2) {
-        const int m = (t - T_W1) >> 1, s = (t - T_W1) & 1;
-        return wbf(a.irt.W1, (16 * m + i) * kH + unit_of(s, g, e));
-    }
-    if (t < B_W0) {
-        const int s = t - T_W2, r = i & 3;
-        return r < 2 ? wbf(a.irt.W2, r * kH + unit_of(s, g, e)) : 0.0f;
-    }
-    if (t < B_W1) {
-        const int m = t - B_W0;
-        return wbf(a.brdf.W0, (16 * m + i) * kNF + 8 * g + e);
-    }
-    if (t < B_W2A) {
-        const int m = (t - B_W1) >> 1, s = (t - B_W1) & 1;
-        return wbf(a.brdf.W1, (16 * m + i) * kH + unit_of(s, g, e));
-    }
-    if (t < B_W2B) {
-        const int s = t - B_W2A;
-        return wbf(a.brdf.W2, (i & 3) * kH + unit_of(s, g, e));
-    }
-    const int s = t - B_W2B;
-    return (i & 3) == 0 ? wbf(a.brdf.W2, 4 * kH + unit_of(s, g, e)) : 0.0f;
-}
-
-// BF16 values are copied bit-exactly (they already are the shadow weights).
-__device__ __forceinline__ uint32_t to_bits(float v) { return __float_as_uint(v) >> 16; }
-
-__device__ void build_tiles(const RenderK &a, uint4 *tiles) {
-    for (int q = threadIdx.x; q < N_TILES * 64; q += blockDim.x) {
-        const int t = q >> 6, l = q & 63;
-        const int i = l & 15, g = l >> 4;
-        uint32_t w[4];
-#pragma unroll
-        for (int p = 0; p < 4; ++p)
-            w[p] = to_bits(tile_value(a, t, i, g, 2 * p)) | (to_bits(tile_value(a, t, i, g, 2 * p + 1)) << 16);
-        tiles[q] = make_uint4(w[0], w[1], w[2], w[3]);
-    }
-}
-
-// Bias of unit row 16 m + 4 g + r as an accumulator tile input.
 __device__ __forceinline__ f32x4 bias_tile(const float *b, int m, int g) {
     const float4 v = *reinterpret_cast<const float4 *>(b + 16 * m + 4 * g);
     return f32x4{v.x, v.y, v.z, v.w};
@@ -149,120 +90,319 @@ __device__ __forceinline__ f32x4 head_bias(const float *b, int nout, int base) {
     return r;
 }
 
-// ----------------------------------------------------------------------------
-// Per-wave LDS scratch
-// ----------------------------------------------------------------------------
-struct WaveLds {
-    uint4 x[64][4];      // per-query input features (32 BF16) -- f(x) or f(x')
-    uint4 om[64];        // per-query direction operand (w_hi, w_lo)
-    float ax[4][kH];     // per-pixel tracer first-layer point part (shade mode)
-    float mat[4][8];     // per-pixel decoder outputs (shade mode)
-};
-
-// Hidden and head layers of the tracer for one N-tile, starting from the
-// first-layer accumulators d[4].  Returns the head tile (row r: output r).
-struct TracerRegs {
-    uint4 w0w[4];
-    uint4 w1[8];
-    uint4 w2[2];
-    f32x4 b1[4];
-    f32x4 b2;
-};
-
-__device__ __forceinline__ f32x4 tracer_rest(const TracerRegs &T, const f32x4 (&d)[4]) {
-    const uint4 h0 = act_pack(d[0], d[1]), h1 = act_pack(d[2], d[3]);
-    f32x4 e[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        e[m] = mfma(T.w1[2 * m], h0, T.b1[m]);
-        e[m] = mfma(T.w1[2 * m + 1], h1, e[m]);
-    }
-    const uint4 k0 = act_pack(e[0], e[1]), k1 = act_pack(e[2], e[3]);
-    f32x4 o = mfma(T.w2[0], k0, T.b2);
-    return mfma(T.w2[1], k1, o);
-}
-
-// Decoder B on the features in x[16n..16n+15] for N-tile n; returns the two
-// head tiles (outputs 0..3 in oa, output 4 in ob row 0).
-__device__ __forceinline__ void decoder_tile(const uint4 *tiles, const float *b0, const float *b1, const float *b2,
-                                             const uint4 &xb, int g, f32x4 &oa, f32x4 &ob) {
-    f32x4 d[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) d[m] = mfma(tiles[(B_W0 + m) * 64 + (threadIdx.x & 63)], xb, bias_tile(b0, m, g));
-    const uint4 h0 = act_pack(d[0], d[1]), h1 = act_pack(d[2], d[3]);
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        d[m] = mfma(tiles[(B_W1 + 2 * m) * 64 + (threadIdx.x & 63)], h0, bias_tile(b1, m, g));
-        d[m] = mfma(tiles[(B_W1 + 2 * m + 1) * 64 + (threadIdx.x & 63)], h1, d[m]);
-    }
-    const uint4 k0 = act_pack(d[0], d[1]), k1 = act_pack(d[2], d[3]);
-    oa = mfma(tiles[B_W2A * 64 + (threadIdx.x & 63)], k0, head_bias(b2, 5, 0));
-    oa = mfma(tiles[(B_W2A + 1) * 64 + (threadIdx.x & 63)], k1, oa);
-    ob = mfma(tiles[B_W2B * 64 + (threadIdx.x & 63)], k0, head_bias(b2, 5, 4));
-    ob = mfma(tiles[(B_W2B + 1) * 64 + (threadIdx.x & 63)], k1, ob);
-}
-
-__device__ __forceinline__ uint4 dir_operand(float3 w) {
-    const __bf16 hx = (__bf16)w.x, hy = (__bf16)w.y, hz = (__bf16)w.z;
-    const float lx = w.x - (float)hx, ly = w.y - (float)hy, lz = w.z - (float)hz;
-    uint4 r;
-    r.x = pack_bf16((float)hx, (float)hy);
-    r.y = pack_bf16((float)hz, lx);
-    r.z = pack_bf16(ly, lz);
-    r.w = 0u;
-    return r;
-}
-
 __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Features of one query packed to BF16 into x[row] (4 x uint4).
-__device__ __forceinline__ void store_feat(WaveLds &W, int row, const float (&f)[kNF]) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-        W.x[row][q] = make_uint4(pack_bf16(f[8 * q], f[8 * q + 1]), pack_bf16(f[8 * q + 2], f[8 * q + 3]),
-                                 pack_bf16(f[8 * q + 4], f[8 * q + 5]), pack_bf16(f[8 * q + 6], f[8 * q + 7]));
-}
+// ============================================================================
+// Mixed path: BF16 operands, K = 32 per matrix-core step.
+// ============================================================================
+struct Bf16Path {
+    typedef __half Table;
+    enum : int {
+        T_W0W = 0, T_W0F = 4, T_W1 = 8, T_W2 = 16,       // tracer
+        B_W0 = 18, B_W1 = 22, B_W2A = 30, B_W2B = 32,    // decoder
+        N_TILES = 34
+    };
+    typedef uint4 Tile;  // 8 BF16 per lane
 
-// ----------------------------------------------------------------------------
+    struct Wave {
+        uint4 x[64][4];   // per-query input features (32 BF16)
+        uint4 om[64];     // per-query direction operand (w_hi, w_lo)
+        float ax[4][kH];  // per-pixel tracer point part (shade mode)
+        float mat[4][8];  // per-pixel decoder outputs (shade mode)
+    };
+
+    static __device__ float tile_value(const RenderK &a, int t, int i, int g, int e) {
+        if (t < T_W0F) {
+            const int m = t - T_W0W;
+            if (g != 0 || e >= 6) return 0.0f;
+            return wbf(a.irt.W0, (16 * m + i) * kNI + kNF + (e % 3));
+        }
+        if (t < T_W1) return wbf(a.irt.W0, (16 * (t - T_W0F) + i) * kNI + 8 * g + e);
+        if (t < T_W2) {
+            const int m = (t - T_W1) >> 1, s = (t - T_W1) & 1;
+            return wbf(a.irt.W1, (16 * m + i) * kH + unit_bf16(s, g, e));
+        }
+        if (t < B_W0) {
+            const int s = t - T_W2, r = i & 3;
+            return r < 2 ? wbf(a.irt.W2, r * kH + unit_bf16(s, g, e)) : 0.0f;
+        }
+        if (t < B_W1) return wbf(a.brdf.W0, (16 * (t - B_W0) + i) * kNF + 8 * g + e);
+        if (t < B_W2A) {
+            const int m = (t - B_W1) >> 1, s = (t - B_W1) & 1;
+            return wbf(a.brdf.W1, (16 * m + i) * kH + unit_bf16(s, g, e));
+        }
+        if (t < B_W2B) return wbf(a.brdf.W2, (i & 3) * kH + unit_bf16(t - B_W2A, g, e));
+        return (i & 3) == 0 ? wbf(a.brdf.W2, 4 * kH + unit_bf16(t - B_W2B, g, e)) : 0.0f;
+    }
+
+    static __device__ void build_tiles(const RenderK &a, Tile *tiles) {
+        for (int q = threadIdx.x; q < N_TILES * 64; q += blockDim.x) {
+            const int t = q >> 6, l = q & 63, i = l & 15, g = l >> 4;
+            uint32_t w[4];
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+                w[p] = (__float_as_uint(tile_value(a, t, i, g, 2 * p)) >> 16) |
+                       (__float_as_uint(tile_value(a, t, i, g, 2 * p + 1)) & 0xffff0000u);
+            tiles[q] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    }
+
+    // hot tracer operands held in registers
+    struct Tracer {
+        uint4 w0w[4], w1[8], w2[2];
+        f32x4 b1[4], b2;
+        __device__ void load(const Tile *tiles, const RenderK &a, int lane, int g) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) w0w[m] = tiles[(T_W0W + m) * 64 + lane];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) w1[k] = tiles[(T_W1 + k) * 64 + lane];
+            w2[0] = tiles[T_W2 * 64 + lane];
+            w2[1] = tiles[(T_W2 + 1) * 64 + lane];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) b1[m] = bias_tile(a.irt.b1, m, g);
+            b2 = head_bias(a.irt.b2, 2, 0);
+        }
+    };
+
+    static __device__ __forceinline__ void store_feat(Wave &W, int row, const float (&f)[kNF]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            W.x[row][q] = make_uint4(pack_bf16(f[8 * q], f[8 * q + 1]), pack_bf16(f[8 * q + 2], f[8 * q + 3]),
+                                     pack_bf16(f[8 * q + 4], f[8 * q + 5]), pack_bf16(f[8 * q + 6], f[8 * q + 7]));
+    }
+    static __device__ __forceinline__ void store_level(Wave &W, int row, int lvl, float f0, float f1) {
+        reinterpret_cast<uint32_t *>(&W.x[row][0])[lvl] = pack_bf16(f0, f1);
+    }
+    static __device__ __forceinline__ void store_dir(Wave &W, int lane, float3 w) {
+        const __bf16 hx = (__bf16)w.x, hy = (__bf16)w.y, hz = (__bf16)w.z;
+        const float lx = w.x - (float)hx, ly = w.y - (float)hy, lz = w.z - (float)hz;
+        W.om[lane] = make_uint4(pack_bf16((float)hx, (float)hy), pack_bf16((float)hz, lx), pack_bf16(ly, lz), 0u);
+    }
+
+    // tracer point part W0f x + b0 of N-tile nt
+    static __device__ __forceinline__ void point_part(const Tile *tiles, const RenderK &a, const Wave &W, int nt,
+                                                      int lane, int g, f32x4 (&d)[4]) {
+        const uint4 xb = W.x[16 * nt + (lane & 15)][g];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) d[m] = mfma_bf16(tiles[(T_W0F + m) * 64 + lane], xb, bias_tile(a.irt.b0, m, g));
+    }
+
+    // decoder on the features of N-tile nt: oa rows 0..3 = outputs 0..3,
+    // ob row 0 = output 4
+    static __device__ __forceinline__ void decoder(const Tile *tiles, const RenderK &a, const Wave &W, int nt,
+                                                   int lane, int g, f32x4 &oa, f32x4 &ob) {
+        const uint4 xb = W.x[16 * nt + (lane & 15)][g];
+        f32x4 d[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) d[m] = mfma_bf16(tiles[(B_W0 + m) * 64 + lane], xb, bias_tile(a.brdf.b0, m, g));
+        const uint4 h0 = act_pack(d[0], d[1]), h1 = act_pack(d[2], d[3]);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            d[m] = mfma_bf16(tiles[(B_W1 + 2 * m) * 64 + lane], h0, bias_tile(a.brdf.b1, m, g));
+            d[m] = mfma_bf16(tiles[(B_W1 + 2 * m + 1) * 64 + lane], h1, d[m]);
+        }
+        const uint4 k0 = act_pack(d[0], d[1]), k1 = act_pack(d[2], d[3]);
+        oa = mfma_bf16(tiles[B_W2A * 64 + lane], k0, head_bias(a.brdf.b2, 5, 0));
+        oa = mfma_bf16(tiles[(B_W2A + 1) * 64 + lane], k1, oa);
+        ob = mfma_bf16(tiles[B_W2B * 64 + lane], k0, head_bias(a.brdf.b2, 5, 4));
+        ob = mfma_bf16(tiles[(B_W2B + 1) * 64 + lane], k1, ob);
+    }
+
+    // tracer for N-tile nt from the point part c: returns the head tile
+    static __device__ __forceinline__ f32x4 tracer(const Tracer &T, const Tile *, const Wave &W, int nt, int lane,
+                                                   const f32x4 (&c)[4]) {
+        const uint4 ob_ = W.om[16 * nt + (lane & 15)];
+        f32x4 d[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) d[m] = mfma_bf16(T.w0w[m], ob_, c[m]);
+        const uint4 h0 = act_pack(d[0], d[1]), h1 = act_pack(d[2], d[3]);
+        f32x4 e[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            e[m] = mfma_bf16(T.w1[2 * m], h0, T.b1[m]);
+            e[m] = mfma_bf16(T.w1[2 * m + 1], h1, e[m]);
+        }
+        const uint4 k0 = act_pack(e[0], e[1]), k1 = act_pack(e[2], e[3]);
+        f32x4 o = mfma_bf16(T.w2[0], k0, T.b2);
+        return mfma_bf16(T.w2[1], k1, o);
+    }
+};
+
+// ============================================================================
+// FP32 path: FP32 operands, K = 4 per matrix-core step.
+// ============================================================================
+struct F32Path {
+    typedef float Table;
+    // tracer tiles in LDS (decoder operands are read from the FP32 weights)
+    enum : int {
+        T_W0W = 0,       // 4 M-tiles, one K-step (w_x, w_y, w_z, 0)
+        T_W0F = 4,       // 4 M-tiles x 8 K-steps (m*8 + s)
+        T_W1 = 36,       // 4 M-tiles x 16 K-steps (m*16 + s)
+        T_W2 = 100,      // 16 K-steps
+        N_TILES = 116
+    };
+    typedef float Tile;
+    static constexpr int kXS = 36;  // row stride of the feature rows (16-byte aligned, 2-way banks)
+
+    struct Wave {
+        float x[64][kXS];
+        float4 om[64];
+        float ax[4][kH];
+        float mat[4][8];
+    };
+
+    static __device__ float tile_value(const RenderK &a, int t, int i, int g) {
+        if (t < T_W0F) {
+            const int m = t - T_W0W;
+            return g < 3 ? wf(a.irt.W0, (16 * m + i) * kNI + kNF + g) : 0.0f;
+        }
+        if (t < T_W1) {
+            const int m = (t - T_W0F) >> 3, s = (t - T_W0F) & 7;
+            return wf(a.irt.W0, (16 * m + i) * kNI + 4 * s + g);
+        }
+        if (t < T_W2) {
+            const int m = (t - T_W1) >> 4, s = (t - T_W1) & 15;
+            return wf(a.irt.W1, (16 * m + i) * kH + unit_f32(s, g));
+        }
+        const int s = t - T_W2, r = i & 3;
+        return r < 2 ? wf(a.irt.W2, r * kH + unit_f32(s, g)) : 0.0f;
+    }
+
+    static __device__ void build_tiles(const RenderK &a, Tile *tiles) {
+        for (int q = threadIdx.x; q < N_TILES * 64; q += blockDim.x) {
+            const int t = q >> 6, l = q & 63;
+            tiles[q] = tile_value(a, t, l & 15, l >> 4);
+        }
+    }
+
+    struct Tracer {
+        f32x4 b1[4], b2;
+        __device__ void load(const Tile *, const RenderK &a, int, int g) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) b1[m] = bias_tile(a.irt.b1, m, g);
+            b2 = head_bias(a.irt.b2, 2, 0);
+        }
+    };
+
+    static __device__ __forceinline__ void store_feat(Wave &W, int row, const float (&f)[kNF]) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            *reinterpret_cast<float4 *>(&W.x[row][4 * q]) = make_float4(f[4 * q], f[4 * q + 1], f[4 * q + 2], f[4 * q + 3]);
+    }
+    static __device__ __forceinline__ void store_level(Wave &W, int row, int lvl, float f0, float f1) {
+        *reinterpret_cast<float2 *>(&W.x[row][2 * lvl]) = make_float2(f0, f1);
+    }
+    static __device__ __forceinline__ void store_dir(Wave &W, int lane, float3 w) {
+        W.om[lane] = make_float4(w.x, w.y, w.z, 0.0f);
+    }
+
+    static __device__ __forceinline__ void point_part(const Tile *tiles, const RenderK &a, const Wave &W, int nt,
+                                                      int lane, int g, f32x4 (&d)[4]) {
+        const float *xr = W.x[16 * nt + (lane & 15)];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) d[m] = bias_tile(a.irt.b0, m, g);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const float b = xr[4 * s + g];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) d[m] = mfma_f32(tiles[(T_W0F + 8 * m + s) * 64 + lane], b, d[m]);
+        }
+    }
+
+    // decoder operands straight from the FP32 weights (L1/L2 resident)
+    static __device__ __forceinline__ void decoder(const Tile *, const RenderK &a, const Wave &W, int nt, int lane,
+                                                   int g, f32x4 &oa, f32x4 &ob) {
+        const int i = lane & 15;
+        const float *xr = W.x[16 * nt + i];
+        const float *W0 = static_cast<const float *>(a.brdf.W0);
+        const float *W1 = static_cast<const float *>(a.brdf.W1);
+        const float *W2 = static_cast<const float *>(a.brdf.W2);
+        f32x4 d[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) d[m] = bias_tile(a.brdf.b0, m, g);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const float b = xr[4 * s + g];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) d[m] = mfma_f32(W0[(16 * m + i) * kNF + 4 * s + g], b, d[m]);
+        }
+        f32x4 e[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) e[m] = bias_tile(a.brdf.b1, m, g);
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const float b = fmaxf(d[s >> 2][s & 3], 0.0f);
+            const int u = unit_f32(s, g);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) e[m] = mfma_f32(W1[(16 * m + i) * kH + u], b, e[m]);
+        }
+        oa = head_bias(a.brdf.b2, 5, 0);
+        ob = head_bias(a.brdf.b2, 5, 4);
+        const int r = i & 3;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const float b = fmaxf(e[s >> 2][s & 3], 0.0f);
+            const int u = unit_f32(s, g);
+            oa = mfma_f32(W2[r * kH + u], b, oa);
+            ob = mfma_f32(r == 0 ? W2[4 * kH + u] : 0.0f, b, ob);
+        }
+    }
+
+    static __device__ __forceinline__ f32x4 tracer(const Tracer &T, const Tile *tiles, const Wave &W, int nt,
+                                                   int lane, const f32x4 (&c)[4]) {
+        const int g = lane >> 4;
+        const float b0 = reinterpret_cast<const float *>(&W.om[16 * nt + (lane & 15)])[g];
+        f32x4 d[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) d[m] = mfma_f32(tiles[(T_W0W + m) * 64 + lane], b0, c[m]);
+        f32x4 e[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) e[m] = T.b1[m];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const float b = fmaxf(d[s >> 2][s & 3], 0.0f);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) e[m] = mfma_f32(tiles[(T_W1 + 16 * m + s) * 64 + lane], b, e[m]);
+        }
+        f32x4 o = T.b2;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) o = mfma_f32(tiles[(T_W2 + s) * 64 + lane], fmaxf(e[s >> 2][s & 3], 0.0f), o);
+        return o;
+    }
+};
+
+// ============================================================================
 // The kernel.  QUERY: one query per lane with its own point and direction;
-// otherwise shade mode with G = min(N, 64) lanes per pixel.
-// ----------------------------------------------------------------------------
+// otherwise shade mode with G = min(N, 64) lanes per pixel (N >= 16, so at
+// most four pixels per wave).
+// ============================================================================
 constexpr int kMixThreads = 256;
 
-template <bool INDIRECT, bool QUERY>
-__global__ __launch_bounds__(kMixThreads) void k_render_mixed(const RenderK a, int64_t n_items) {
-    __shared__ uint4 tiles[N_TILES * 64];
-    __shared__ WaveLds wl[kMixThreads / 64];
-    build_tiles(a, tiles);
+template <class PP, bool INDIRECT, bool QUERY>
+__global__ __launch_bounds__(kMixThreads) void k_render_mma(const RenderK a, int64_t n_items) {
+    typedef typename PP::Table TT;
+    __shared__ typename PP::Tile tiles[PP::N_TILES * 64];
+    __shared__ typename PP::Wave wl[kMixThreads / 64];
+    PP::build_tiles(a, tiles);
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4, jcol = lane & 15;
-    WaveLds &W = wl[threadIdx.x >> 6];
-
-    TracerRegs T;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) T.w0w[m] = tiles[(T_W0W + m) * 64 + lane];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) T.w1[k] = tiles[(T_W1 + k) * 64 + lane];
-    T.w2[0] = tiles[T_W2 * 64 + lane];
-    T.w2[1] = tiles[(T_W2 + 1) * 64 + lane];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) T.b1[m] = bias_tile(a.irt.b1, m, g);
-    T.b2 = head_bias(a.irt.b2, 2, 0);
+    typename PP::Wave &W = wl[threadIdx.x >> 6];
+    typename PP::Tracer T;
+    T.load(tiles, a, lane, g);
 
     const bool diffuse = (a.s.flags & 1u) != 0;
     const uint32_t gs = a.s.g_shift;
     const uint32_t G = 1u << gs;
-    const int ppw = 64 >> gs;  // pixels per wave (shade mode)
+    const int ppw = 64 >> gs;
     const int64_t waves_total = (int64_t)gridDim.x * (kMixThreads / 64);
     const int64_t wave_id = (int64_t)blockIdx.x * (kMixThreads / 64) + (threadIdx.x >> 6);
 
     for (int64_t item = wave_id; item < n_items; item += waves_total) {
-        // ---------------- per-lane query identity ----------------
         int64_t p_raw;
         if (QUERY) p_raw = item * 64 + lane;
         else p_raw = item * ppw + (lane >> gs);
@@ -270,25 +410,24 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mixed(const RenderK a, i
         const int64_t p = live ? p_raw : a.n - 1;
         const float3 x = make_float3(a.pos[3 * p], a.pos[3 * p + 1], a.pos[3 * p + 2]);
 
-        // ---------------- primary point: features, decoder, point part ----------------
-        f32x4 apt[4][4];  // point part of the tracer's first layer, per (M-tile, N-tile)
+        // ---------------- primary point ----------------
+        f32x4 apt[4][4];  // query mode: tracer point part at x per (M-tile, N-tile)
         float3 n_ = make_float3(0.f, 0.f, 1.f), v_ = n_, alb = n_;
         float rr = 0.5f, mm = 0.f;
         if (QUERY) {
             float f[kNF];
-            encode<__half>(a.g, x.x, x.y, x.z, f);
-            store_feat(W, lane, f);
+            encode<TT>(a.g, x.x, x.y, x.z, f);
+            PP::store_feat(W, lane, f);
             wave_sync_lds();
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt) {
-                const uint4 xb = W.x[16 * nt + jcol][g];
+                f32x4 d[4];
+                PP::point_part(tiles, a, W, nt, lane, g, d);
 #pragma unroll
-                for (int m = 0; m < 4; ++m)
-                    apt[m][nt] = mfma(tiles[(T_W0F + m) * 64 + lane], xb, bias_tile(a.irt.b0, m, g));
+                for (int m = 0; m < 4; ++m) apt[m][nt] = d[m];
             }
         } else {
-            // lane l encodes level l % 16 of pixel slot l / 16 (one pass:
-            // N >= 16 gives at most four pixels per wave)
+            // lane l encodes level l % 16 of pixel slot l / 16
             const int slot = lane >> 4, lvl = lane & 15;
             const int64_t ps_raw = item * ppw + slot;
             const int64_t ps = ps_raw < a.n ? ps_raw : a.n - 1;
@@ -302,26 +441,22 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mixed(const RenderK a, i
                 for (int d = 0; d < 3; ++d) cell_of(u[d], a.g.resf[lvl], a.g.nm1f[lvl], c[d], w[d]);
                 uint32_t ix[8];
                 corner_idx(a.g, lvl, c, ix);
-                const void *lv = TabLoad<__half>::level(a.g.table, lvl, a.g.log2T);
+                const void *lv = TabLoad<TT>::level(a.g.table, lvl, a.g.log2T);
                 float f0 = 0.f, f1 = 0.f;
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
-                    const float2 e = TabLoad<__half>::ld(lv, ix[k]);
+                    const float2 e = TabLoad<TT>::ld(lv, ix[k]);
                     const float wt = ((k & 1) ? w[0] : 1.f - w[0]) * (((k >> 1) & 1) ? w[1] : 1.f - w[1]) *
                                      (((k >> 2) & 1) ? w[2] : 1.f - w[2]);
                     f0 = fmaf(wt, e.x, f0);
                     f1 = fmaf(wt, e.y, f1);
                 }
-                reinterpret_cast<uint32_t *>(&W.x[slot][0])[lvl] = pack_bf16(f0, f1);
+                PP::store_level(W, slot, lvl, f0, f1);
             }
             wave_sync_lds();
-            // N-tile 0 holds the pixels in columns 0..ppw-1
-            const uint4 xb = W.x[jcol][g];
-            f32x4 oa, ob;
-            decoder_tile(tiles, a.brdf.b0, a.brdf.b1, a.brdf.b2, xb, g, oa, ob);
-            f32x4 ax[4];
-#pragma unroll
-            for (int m = 0; m < 4; ++m) ax[m] = mfma(tiles[(T_W0F + m) * 64 + lane], xb, bias_tile(a.irt.b0, m, g));
+            f32x4 oa, ob, ax[4];
+            PP::decoder(tiles, a, W, 0, lane, g, oa, ob);
+            PP::point_part(tiles, a, W, 0, lane, g, ax);
             if (jcol < ppw) {
 #pragma unroll
                 for (int m = 0; m < 4; ++m)
@@ -348,7 +483,7 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mixed(const RenderK a, i
         KSum sx{0.f, 0.f}, sy{0.f, 0.f}, sz{0.f, 0.f};
 
         for (uint32_t i = i0; i < N; i += step) {
-            // ---------------- primary direction ----------------
+            // ---------------- primary direction and tracer ----------------
             float3 w;
             if (QUERY) {
                 w = make_float3(a.dir[3 * p], a.dir[3 * p + 1], a.dir[3 * p + 2]);
@@ -356,26 +491,23 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mixed(const RenderK a, i
                 const uint4 words = philox4x32_10((uint32_t)p, 0u, i >> 2, 0u, a.s.key0, a.s.key1);
                 w = sample_dir(pick4(words, i), i, a.s.nb_shift, a.s.inv_na, a.s.inv_nb, fr);
             }
-            W.om[lane] = dir_operand(w);
+            PP::store_dir(W, lane, w);
             wave_sync_lds();
             float o0 = 0.f, o1 = 0.f;
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt) {
-                const uint4 ob_ = W.om[16 * nt + jcol];
-                f32x4 d[4];
+                f32x4 c[4];
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
-                    f32x4 c0;
                     if (QUERY) {
-                        c0 = apt[m][nt];
+                        c[m] = apt[m][nt];
                     } else {
                         // columns of N-tile nt belong to pixel slot (16 nt) >> gs
                         const float4 v4 = *reinterpret_cast<const float4 *>(&W.ax[(16 * nt) >> gs][16 * m + 4 * g]);
-                        c0 = f32x4{v4.x, v4.y, v4.z, v4.w};
+                        c[m] = f32x4{v4.x, v4.y, v4.z, v4.w};
                     }
-                    d[m] = mfma(T.w0w[m], ob_, c0);
                 }
-                const f32x4 h = tracer_rest(T, d);
+                const f32x4 h = PP::tracer(T, tiles, W, nt, lane, c);
                 if (g == nt) {
                     o0 = h[0];
                     o1 = h[1];
@@ -392,20 +524,20 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mixed(const RenderK a, i
                 const float t = fmaf(a.t_span, dd, a.t_near);
                 const float3 xb = make_float3(fmaf(t, w.x, x.x), fmaf(t, w.y, x.y), fmaf(t, w.z, x.z));
                 float fb[kNF];
-                encode<__half>(a.g, xb.x, xb.y, xb.z, fb);
-                wave_sync_lds();  // previous readers of W.x are done
-                store_feat(W, lane, fb);
+                encode<TT>(a.g, xb.x, xb.y, xb.z, fb);
+                wave_sync_lds();
+                PP::store_feat(W, lane, fb);
                 wave_sync_lds();
                 f32x4 bpt[4][4];
                 float ob0 = 0.f, ob1 = 0.f, ob2 = 0.f, ob3 = 0.f, ob4 = 0.f;
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt) {
-                    const uint4 xb_ = W.x[16 * nt + jcol][g];
+                    f32x4 d[4];
+                    PP::point_part(tiles, a, W, nt, lane, g, d);
 #pragma unroll
-                    for (int m = 0; m < 4; ++m)
-                        bpt[m][nt] = mfma(tiles[(T_W0F + m) * 64 + lane], xb_, bias_tile(a.irt.b0, m, g));
+                    for (int m = 0; m < 4; ++m) bpt[m][nt] = d[m];
                     f32x4 oa, obb;
-                    decoder_tile(tiles, a.brdf.b0, a.brdf.b1, a.brdf.b2, xb_, g, oa, obb);
+                    PP::decoder(tiles, a, W, nt, lane, g, oa, obb);
                     if (g == nt) {
                         ob0 = oa[0]; ob1 = oa[1]; ob2 = oa[2]; ob3 = oa[3]; ob4 = obb[0];
                     }
@@ -422,16 +554,13 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mixed(const RenderK a, i
                     if ((j & 3u) == 0) words2 = philox4x32_10((uint32_t)p, q, j >> 2, 1u, a.s.key0, a.s.key1);
                     const float3 wj = sample_dir(pick4(words2, j), j, a.s.nb2_shift, a.s.inv_na2, a.s.inv_nb2, frb);
                     wave_sync_lds();
-                    W.om[lane] = dir_operand(wj);
+                    PP::store_dir(W, lane, wj);
                     wave_sync_lds();
                     float vo = 0.f;
 #pragma unroll
                     for (int nt = 0; nt < 4; ++nt) {
-                        const uint4 ob_ = W.om[16 * nt + jcol];
-                        f32x4 d[4];
-#pragma unroll
-                        for (int m = 0; m < 4; ++m) d[m] = mfma(T.w0w[m], ob_, bpt[m][nt]);
-                        const f32x4 h = tracer_rest(T, d);
+                        const f32x4 c[4] = {bpt[0][nt], bpt[1][nt], bpt[2][nt], bpt[3][nt]};
+                        const f32x4 h = PP::tracer(T, tiles, W, nt, lane, c);
                         if (g == nt) vo = h[0];
                     }
                     const float vj = sigmoidf_(vo);
@@ -495,7 +624,8 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mixed(const RenderK a, i
 
 static int g_num_cus = 0;
 
-hipError_t launch_render_mixed(const RenderK &a, bool indirect, bool query, hipStream_t s) {
+template <class PP>
+static hipError_t launch_mma(const RenderK &a, bool indirect, bool query, hipStream_t s) {
     if (!query && a.s.n_dirs < 16) return hipErrorNotSupported;
     if (g_num_cus == 0) {
         int dev = 0;
@@ -510,13 +640,21 @@ hipError_t launch_render_mixed(const RenderK &a, bool indirect, bool query, hipS
     const int64_t cap = (int64_t)g_num_cus * 2;
     const unsigned blocks = (unsigned)(want < cap ? want : cap);
     if (query) {
-        if (indirect) hipLaunchKernelGGL((k_render_mixed<true, true>), dim3(blocks), dim3(kMixThreads), 0, s, a, items);
-        else hipLaunchKernelGGL((k_render_mixed<false, true>), dim3(blocks), dim3(kMixThreads), 0, s, a, items);
+        if (indirect) hipLaunchKernelGGL((k_render_mma<PP, true, true>), dim3(blocks), dim3(kMixThreads), 0, s, a, items);
+        else hipLaunchKernelGGL((k_render_mma<PP, false, true>), dim3(blocks), dim3(kMixThreads), 0, s, a, items);
     } else {
-        if (indirect) hipLaunchKernelGGL((k_render_mixed<true, false>), dim3(blocks), dim3(kMixThreads), 0, s, a, items);
-        else hipLaunchKernelGGL((k_render_mixed<false, false>), dim3(blocks), dim3(kMixThreads), 0, s, a, items);
+        if (indirect) hipLaunchKernelGGL((k_render_mma<PP, true, false>), dim3(blocks), dim3(kMixThreads), 0, s, a, items);
+        else hipLaunchKernelGGL((k_render_mma<PP, false, false>), dim3(blocks), dim3(kMixThreads), 0, s, a, items);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_render_mixed(const RenderK &a, bool indirect, bool query, hipStream_t s) {
+    return launch_mma<Bf16Path>(a, indirect, query, s);
+}
+
+hipError_t launch_render_f32_mma(const RenderK &a, bool indirect, bool query, hipStream_t s) {
+    return launch_mma<F32Path>(a, indirect, query, s);
 }
 
 }  // namespace hg
