@@ -79,7 +79,10 @@ typedef struct {
 typedef struct {
     int64_t n;
     const float *pos, *nrm, *wo, *dir; /* [n][3]; dir != NULL selects query mode */
+    const uint32_t *pid;               /* [n] point ids for the sampler, NULL: 0..n-1 */
 } or_points;
+
+static uint32_t point_id(const or_points *P, int64_t p) { return P->pid ? P->pid[p] : (uint32_t)p; }
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw: "Parallel random numbers: as   */
@@ -583,7 +586,7 @@ void or_render(const or_model *M, const or_env *E, const or_sampling *S, const o
         if (query) {
             double w[3] = {P->dir[3 * p], P->dir[3 * p + 1], P->dir[3 * p + 2]};
             double Lin[3], V, d;
-            incoming(M, E, S, indirect, f, x, w, (uint32_t)p, 0u, Lin, &V, &d);
+            incoming(M, E, S, indirect, f, x, w, point_id(P, p), 0u, Lin, &V, &d);
             for (int c = 0; c < 3; ++c) rgb[3 * p + c] = Lin[c];
             if (vis) vis[p] = V;
             if (depth) depth[p] = d;
@@ -600,8 +603,8 @@ void or_render(const or_model *M, const or_env *E, const or_sampling *S, const o
         const int N = S->n_dirs;
         for (int i = 0; i < N; ++i) {
             double w[3], Lin[3], V, d, fr[3], t1[3], t2[3], t3[3];
-            sample_dir(S->seed, (uint32_t)p, 0u, (uint32_t)i, 0u, N, n, w);
-            incoming(M, E, S, indirect, f, x, w, (uint32_t)p, (uint32_t)i, Lin, &V, &d);
+            sample_dir(S->seed, point_id(P, p), 0u, (uint32_t)i, 0u, N, n, w);
+            incoming(M, E, S, indirect, f, x, w, point_id(P, p), (uint32_t)i, Lin, &V, &d);
             brdf_eval(n, v, w, a, r, m, M->f0, (S->flags & OR_DIFFUSE_ONLY) != 0, fr, t1, t2, t3);
             for (int c = 0; c < 3; ++c) Lo[c] += M_PI * fr[c] * Lin[c];
             if (vis) vis[p * N + i] = V;
@@ -742,7 +745,7 @@ void or_backward(const or_model *M, const or_env *E, const or_sampling *S, const
                 double dca[OR_MAXN2][3], dcr[OR_MAXN2][3], dcm[OR_MAXN2][3];
                 double Lo[3] = {0, 0, 0};
                 for (int j = 0; j < N2; ++j) {
-                    sample_dir(S->seed, (uint32_t)p, 0u, (uint32_t)j, 1u, N2, nbv, wj[j]);
+                    sample_dir(S->seed, point_id(P, p), 0u, (uint32_t)j, 1u, N2, nbv, wj[j]);
                     for (int i = 0; i < nf; ++i) z[i] = fb[i];
                     z[nf] = wj[j][0]; z[nf + 1] = wj[j][1]; z[nf + 2] = wj[j][2];
                     mlp_fwd(&M->irt, z, h1, h2, o);

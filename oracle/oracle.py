@@ -64,7 +64,7 @@ class Sampling(C.Structure):
 
 class Points(C.Structure):
     _fields_ = [("n", C.c_int64), ("pos", C.c_void_p), ("nrm", C.c_void_p),
-                ("wo", C.c_void_p), ("dir", C.c_void_p)]
+                ("wo", C.c_void_p), ("dir", C.c_void_p), ("pid", C.c_void_p)]
 
 
 _lib = None
@@ -145,12 +145,13 @@ def sampling(n_dirs, n_dirs2=8, seed=7, flags=0):
     return s
 
 
-def _points(pos, nrm=None, wo=None, dirs=None):
+def _points(pos, nrm=None, wo=None, dirs=None, pid=None):
     keep = [_f32(pos), None if nrm is None else _f32(nrm), None if wo is None else _f32(wo),
-            None if dirs is None else _f32(dirs)]
+            None if dirs is None else _f32(dirs),
+            None if pid is None else np.ascontiguousarray(pid, dtype=np.uint32)]
     P = Points()
     P.n = keep[0].shape[0]
-    P.pos, P.nrm, P.wo, P.dir = [_p(a) for a in keep]
+    P.pos, P.nrm, P.wo, P.dir, P.pid = [_p(a) for a in keep]
     return P, keep
 
 
@@ -230,10 +231,11 @@ def brdf(n, v, l, a, r, m, f0=0.04, diffuse_only=False):
 
 
 def render(om: OracleModel, oe: OracleEnv, samp: Sampling, pos, nrm=None, wo=None, dirs=None,
-           indirect=True, want_vis=True):
+           indirect=True, want_vis=True, pid=None):
     """Shade mode (dirs None): rgb [n,3], vis/depth [n,N].  Query mode:
-    rgb [n,3], vis [n], depth [n]."""
-    P, keep = _points(pos, nrm, wo, dirs)
+    rgb [n,3], vis [n], depth [n].  pid: the points' ids in the sampler's
+    counter (default 0..n-1), for evaluating a subset of a larger batch."""
+    P, keep = _points(pos, nrm, wo, dirs, pid)
     n = P.n
     rgb = np.empty((n, 3))
     if dirs is None:
@@ -266,10 +268,10 @@ def split_mlp_grad(flat, ws):
 
 
 def backward(om: OracleModel, oe: OracleEnv, samp: Sampling, pos, dirs, g_rgb, g_vis, g_dep,
-             indirect=True, want_pos=False):
+             indirect=True, want_pos=False, pid=None):
     """Gradients of sum_p (g_rgb.rgb + g_vis*vis + g_dep*depth) in query mode.
     Returns dict(table [L,T,F], brdf [6 arrays], irt [6 arrays], pos [n,3]|None)."""
-    P, keep = _points(pos, None, None, dirs)
+    P, keep = _points(pos, None, None, dirs, pid)
     g_rgb, g_vis, g_dep = _f32(g_rgb), _f32(g_vis), _f32(g_dep)
     gt = np.zeros(om.table.shape)
     gb = np.zeros(om.n_brdf_params())

@@ -1,0 +1,97 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark times: 800x800 frames (T = 2^19, res 16..2048, env 64x128) at 128
+and 512 directions, and training batches of 2^18 and 2^20 queries.  The
+oracle evaluates sampled outputs one by one (with the same sampler point
+ids); gradients at full size are checked by linearity (the full-batch
+gradient equals the sum of the gradients of two sub-batches) and one
+sub-batch against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import hg_inputs as H
+import paper_2409_10327_amd as hg
+from oracle import oracle as O
+from helpers import psnr, relerr
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def frame():
+    cfg = H.config("c2")
+    model = H.make_model(cfg)
+    env = H.make_env(cfg.env_h, cfg.env_w)
+    pos, nrm, wo = H.make_scene(cfg.img_h, cfg.img_w)
+    r = hg.HashRenderer(model, DEV)
+    r.refresh_shadows()
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    rng = np.random.default_rng(99)
+    P = pos.shape[0]
+    sample = np.unique(np.concatenate([rng.choice(P, 600, replace=False), [0, 799, P - 800, P - 1]]))
+    return dict(cfg=cfg, model=model, env=env, pos=pos, nrm=nrm, wo=wo, r=r, t=t, sample=sample,
+                om=O.OracleModel(model, H.BOX_LO, H.BOX_EXTENT), oe=O.OracleEnv(env))
+
+
+@pytest.mark.parametrize("N,precision", [(128, "fp32"), (128, "mixed"), (512, "mixed")])
+def test_full_frame_sampled_pixels(frame, N, precision):
+    print(f"case: full frame 800x800 N={N} {precision}", flush=True)
+    t = frame["t"]
+    rgb = hg.render(frame["r"], t(frame["env"]), t(frame["pos"]), t(frame["nrm"]), t(frame["wo"]), n_dirs=N,
+                    seed=H.SEED_DIRS, precision=precision)[0].cpu().numpy()
+    assert np.all(np.isfinite(rgb))
+    sm = frame["sample"] if N == 128 else frame["sample"][::4]
+    orgb = O.render(frame["om"], frame["oe"], O.sampling(N, 8, H.SEED_DIRS, 0), frame["pos"][sm],
+                    frame["nrm"][sm], frame["wo"][sm], indirect=True, want_vis=False, pid=sm)[0]
+    e, ps = relerr(rgb[sm], orgb), psnr(rgb[sm], orgb)
+    print(f"{precision} N={N}: sampled rgb rel {e:.3g}, PSNR {ps:.1f} dB")
+    if precision == "fp32":
+        assert e < 1e-5
+    else:
+        assert e < 2e-3 and ps >= 45.0
+
+
+@pytest.mark.parametrize("B,precision", [(1 << 18, "fp32"), (1 << 18, "mixed"), (1 << 20, "mixed")])
+def test_full_batch_query_sampled(frame, B, precision):
+    print(f"case: query batch {B} {precision}", flush=True)
+    t = frame["t"]
+    pos, dirs = H.make_train_batch(B)
+    rgb, vis, dep = hg.render(frame["r"], t(frame["env"]), t(pos), dirs=t(dirs), precision=precision)
+    rgb, vis, dep = rgb.cpu().numpy(), vis.cpu().numpy(), dep.cpu().numpy()
+    sm = np.random.default_rng(5).choice(B, 2048, replace=False)
+    orgb, ovis, odep = O.render(frame["om"], frame["oe"], O.sampling(1, 8, H.SEED_DIRS, 0), pos[sm], dirs=dirs[sm],
+                                indirect=True, pid=sm)
+    tol = 1e-5 if precision == "fp32" else 2e-3
+    for a, b in ((rgb[sm], orgb), (vis[sm], ovis), (dep[sm], odep)):
+        assert relerr(a, b) < (tol if precision == "fp32" else 5e-3)
+
+
+@pytest.mark.parametrize("B", [1 << 18, 1 << 20])
+def test_full_batch_gradients(frame, B):
+    """Full-batch backward = sum of two sub-batch backwards (same kernel, same
+    launch shape), and the first sub-batch matches the oracle."""
+    print(f"case: full-batch backward B={B}", flush=True)
+    t = frame["t"]
+    r = frame["r"]
+    pos, dirs = H.make_train_batch(B)
+    rng = np.random.default_rng(17)
+    g_rgb = (rng.standard_normal((B, 3)) / B).astype(np.float32)
+    g_vis = (rng.standard_normal(B) / B).astype(np.float32)
+    g_dep = (rng.standard_normal(B) / B).astype(np.float32)
+    T = lambda a: t(a)
+    full = hg.zero_grads(r)
+    hg.backward(r, T(frame["env"]), T(pos), T(dirs), T(g_rgb), T(g_vis), T(g_dep), full)
+    k = 4096
+    ga, gb = hg.zero_grads(r), hg.zero_grads(r)
+    hg.backward(r, T(frame["env"]), T(pos[:k]), T(dirs[:k]), T(g_rgb[:k]), T(g_vis[:k]), T(g_dep[:k]), ga)
+    hg.backward(r, T(frame["env"]), T(pos[k:]), T(dirs[k:]), T(g_rgb[k:]), T(g_vis[k:]), T(g_dep[k:]), gb)
+    tf, ta, tb = [[g["table"]] + g["brdf"] + g["irt"] for g in (full, ga, gb)]
+    for a, b, c in zip(tf, ta, tb):
+        assert relerr(a.cpu().numpy(), (b + c).cpu().numpy()) < 1e-5
+    ref = O.backward(frame["om"], frame["oe"], O.sampling(1, 8, H.SEED_DIRS, 0), pos[:k], dirs[:k], g_rgb[:k],
+                     g_vis[:k], g_dep[:k], indirect=True)
+    assert relerr(ga["table"].cpu().numpy(), ref["table"]) < 3e-5
+    for kk in ("brdf", "irt"):
+        for i in range(6):
+            assert relerr(ga[kk][i].cpu().numpy(), ref[kk][i]) < 3e-5
