@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=8)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -121,6 +123,14 @@ def main():
     out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                        "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": None,
                        "kernel": "k_render_mma<F32Path, indirect, shade>"}
+
+    if args.copy_probe:
+        src = torch.ones(1 << 28, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = 2 * src.numel() * 4
+        del src, dst
 
     if not args.no_mixed:
         try:
