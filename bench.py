@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-encode", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=8)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
@@ -150,6 +151,36 @@ def main():
                                          "kernel": "k_render_mma<Bf16Path, indirect, shade>"}}
         except hg.HGError as e:
             out["mixed"] = {"unavailable": str(e)}
+
+    if not args.no_encode:
+        # hg_encode gather bandwidth: 2^24 points uniform in the scene's
+        # bounding region, FP32 tables (T = 2^19, 64 MiB).  Algorithmic bytes
+        # per point: 16 levels x 8 corners x 8 B gathered + 12 B position +
+        # 128 B features.  Reference: a plain random 8-byte gather over the
+        # same table (torch index_select), the achievable random-gather rate.
+        ne = 1 << 24
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(3)
+        epos = (torch.rand((ne, 3), device=dev, generator=gen) * 8.0 - 4.0).contiguous()
+        feat = torch.empty((ne, 32), device=dev)
+
+        def enc():
+            hg.encode(r, epos)
+        mse, _, _ = time_events(enc, args.steps, 1, torch)
+        alg = ne * (16 * 8 * 8 + 12 + 128)
+        rows = r.table.view(-1, 2)
+        gidx = torch.randint(0, rows.shape[0], (ne * 16,), device=dev, generator=gen)
+        gout = torch.empty((ne * 16, 2), device=dev)
+
+        def gath():
+            torch.index_select(rows, 0, gidx, out=gout)
+        msg, _, _ = time_events(gath, args.steps, 1, torch)
+        g_bw = gidx.numel() * (8 + 8 + 8) / (msg * 1e-3) / 1e9
+        out["encode"] = {"points": ne, "ms": mse, "gather_GBps": alg / (mse * 1e-3) / 1e9,
+                         "achievable_random_gather_GBps": g_bw,
+                         "frac_of_achievable": (alg / (mse * 1e-3) / 1e9) / g_bw,
+                         "hbm_peak_GBps": HBM_PEAK_GBS}
+        del epos, feat, gidx, gout
 
     if not args.no_train:
         B = args.train_batch
