@@ -291,13 +291,39 @@ __device__ __forceinline__ void encode(const GridK &g, float x, float y, float z
 }
 
 // --------------------------------------------------------------------------
+// atan2 from a polynomial approximation of atan on [0, 1]:
+// atan(t) ~ t * P(t^2), P of degree 7, coefficients fitted here by weighted
+// least squares on 4000 Chebyshev nodes with Lawson reweighting towards the
+// minimax error; |error| < 1.5e-7 rad when evaluated in FP32 (about one ulp
+// of pi).  Octant reduction: t = min(|x|,|y|) / max(|x|,|y|).
+// --------------------------------------------------------------------------
+__device__ __forceinline__ float atan2_poly(float y, float x) {
+    const float ax = fabsf(x), ay = fabsf(y);
+    const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+    const float t = mx > 0.0f ? mn / mx : 0.0f;
+    const float s = t * t;
+    float p = -0.00405457f;
+    p = fmaf(p, s, 0.02186296f);
+    p = fmaf(p, s, -0.05591233f);
+    p = fmaf(p, s, 0.09642199f);
+    p = fmaf(p, s, -0.1390863f);
+    p = fmaf(p, s, 0.19946566f);
+    p = fmaf(p, s, -0.3332986f);
+    p = fmaf(p, s, 0.99999934f);
+    float r = p * t;
+    if (ay > ax) r = 1.57079632679489662f - r;
+    if (x < 0.0f) r = kPi - r;
+    return copysignf(r, y);
+}
+
+// --------------------------------------------------------------------------
 // Environment lookup: y up, azimuth atan2(w_z, w_x), polar angle from +y,
 // texel centres at +1/2, bilinear, columns wrap, rows clamp.  Indices are
 // clamped so that any input (including NaN) stays inside the map.
 // --------------------------------------------------------------------------
 __device__ __forceinline__ float3 env_lookup(const EnvK &e, float wx, float wy, float wz) {
-    const float phi = atan2f(wz, wx);
-    const float th = atan2f(sqrtf(wx * wx + wz * wz), wy);
+    const float phi = atan2_poly(wz, wx);
+    const float th = atan2_poly(sqrtf(wx * wx + wz * wz), wy);
     const float s = (phi + kPi) * (e.Wf * (0.5f / kPi)) - 0.5f;
     const float q = th * (e.Hf * (1.0f / kPi)) - 0.5f;
     const float xf = floorf(s), yf = floorf(q);
@@ -379,6 +405,39 @@ __device__ __forceinline__ float3 pi_brdf(float3 n, float3 v, float3 l, float3 a
     return make_float3((1.0f - m) * a.x + s * (F0x * q + t.P), (1.0f - m) * a.y + s * (F0y * q + t.P),
                        (1.0f - m) * a.z + s * (F0z * q + t.P));
 }
+
+// pi * f_r at a surface seen along its own normal (v = n, the bounce point's
+// facing reading): NdotV = 1, |l + n|^2 = 2 (1 + NdotL), so
+// NdotH^2 = VdotH^2 = (1 + NdotL) / 2 and the view term of the
+// height-correlated Smith visibility is 1.  Per-point factors are set once.
+struct FacingBrdf {
+    float3 kd, F0;     // (1-m) a and mix(f0, a, m)
+    float a2, a2m1;    // alpha^2 and alpha^2 - 1
+    bool diffuse;
+    __device__ __forceinline__ void set(float3 a, float r, float m, float f0, bool diffuse_only) {
+        diffuse = diffuse_only;
+        kd = diffuse_only ? a : make_float3((1.0f - m) * a.x, (1.0f - m) * a.y, (1.0f - m) * a.z);
+        F0 = make_float3(f0 * (1.0f - m) + a.x * m, f0 * (1.0f - m) + a.y * m, f0 * (1.0f - m) + a.z * m);
+        const float al = r * r;
+        a2 = al * al;
+        a2m1 = a2 - 1.0f;
+    }
+    __device__ __forceinline__ float3 eval(float NdotL) const {
+        if (!(NdotL > 0.0f)) return make_float3(0.f, 0.f, 0.f);
+        if (diffuse) return kd;
+        const float h2 = 0.5f * (1.0f + NdotL);
+        const float Q = fmaf(h2, a2m1, 1.0f);
+        const float D = a2 / (kPi * Q * Q);
+        const float sl = sqrtf(fmaf(NdotL * NdotL, -a2m1, a2));
+        const float Vis = 0.5f / (NdotL + sl);
+        const float om = 1.0f - sqrtf(h2);
+        const float om2 = om * om;
+        const float P = om2 * om2 * om;
+        const float sp = kPi * D * Vis, q = 1.0f - P;
+        return make_float3(fmaf(sp, fmaf(F0.x, q, P), kd.x), fmaf(sp, fmaf(F0.y, q, P), kd.y),
+                           fmaf(sp, fmaf(F0.z, q, P), kd.z));
+    }
+};
 
 // --------------------------------------------------------------------------
 // Three-layer ReLU MLP on the vector ALU, one sample per lane.  Weights are

@@ -113,6 +113,8 @@ __device__ __forceinline__ void incoming(const RenderK &a, const float (&f)[kNF]
     const float3 nb = make_float3(-w.x, -w.y, -w.z);
     const Frame fr = make_frame(nb);
     const bool diffuse = (a.s.flags & 1u) != 0;
+    FacingBrdf fb_;
+    fb_.set(ab, rb, mb, a.f0, diffuse);
 #pragma unroll
     for (int i = 0; i < kNF; ++i) z[i] = fb[i];
     float Lx = 0.f, Ly = 0.f, Lz = 0.f;
@@ -124,7 +126,7 @@ __device__ __forceinline__ void incoming(const RenderK &a, const float (&f)[kNF]
         mlp_fwd<kNI, 2, float>(a.irt, z, hbuf, hbuf, lane, h, o);
         const float vj = sigmoidf_(o[0]);
         const float3 Ej = env_lookup(a.env, wj.x, wj.y, wj.z);
-        const float3 c = pi_brdf(nb, nb, wj, ab, rb, mb, a.f0, diffuse);
+        const float3 c = fb_.eval(dot3(nb, wj));
         Lx = fmaf(c.x * vj, Ej.x, Lx);
         Ly = fmaf(c.y * vj, Ej.y, Ly);
         Lz = fmaf(c.z * vj, Ej.z, Lz);

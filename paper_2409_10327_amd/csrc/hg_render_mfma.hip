@@ -547,6 +547,8 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mma(const RenderK a, int
                 const float mb = sigmoidf_(ob4);
                 const float3 nb = make_float3(-w.x, -w.y, -w.z);
                 const Frame frb = make_frame(nb);
+                FacingBrdf fb_;
+                fb_.set(ab, rb, mb, a.f0, diffuse);
                 const uint32_t q = QUERY ? 0u : i;
                 float Lx = 0.f, Ly = 0.f, Lz = 0.f;
                 uint4 words2 = make_uint4(0, 0, 0, 0);
@@ -565,7 +567,7 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mma(const RenderK a, int
                     }
                     const float vj = sigmoidf_(vo);
                     const float3 Ej = env_lookup(a.env, wj.x, wj.y, wj.z);
-                    const float3 c = pi_brdf(nb, nb, wj, ab, rb, mb, a.f0, diffuse);
+                    const float3 c = fb_.eval(dot3(nb, wj));
                     Lx = fmaf(c.x * vj, Ej.x, Lx);
                     Ly = fmaf(c.y * vj, Ej.y, Ly);
                     Lz = fmaf(c.z * vj, Ej.z, Lz);
