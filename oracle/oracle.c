@@ -46,6 +46,7 @@
 #define OR_MAXN2 64     /* max secondary directions */
 
 #define OR_DIFFUSE_ONLY 1u
+#define OR_HARD_VIS 2u     /* binary visibility, bounce only on shadow rays */
 
 typedef struct {
     int32_t L, F, log2_T;
@@ -521,7 +522,9 @@ static void incoming(const or_model *M, const or_env *E, const or_sampling *S, i
     for (int i = 0; i < nf; ++i) z[i] = f[i];
     z[nf] = w[0]; z[nf + 1] = w[1]; z[nf + 2] = w[2];
     mlp_fwd(&M->irt, z, h1, h2, o);
-    double vis = sigmoid(o[0]);
+    const int hard = (S->flags & OR_HARD_VIS) != 0;
+    /* hard visibility (Sec. 3.2 "Overview"): v = 1 when sigmoid(o0) > 1/2 */
+    double vis = hard ? (o[0] > 0.0 ? 1.0 : 0.0) : sigmoid(o[0]);
     double sp = softplus(o[1]);
     double d = sp < 1.0 ? sp : 1.0;
     double t = M->t_near + (M->t_far - M->t_near) * d;
@@ -529,7 +532,8 @@ static void incoming(const or_model *M, const or_env *E, const or_sampling *S, i
     env_lookup(E, w, Le);
     *V = vis;
     *dep = d;
-    if (!indirect) {
+    if (!indirect || (hard && vis == 1.0)) {
+        /* direct only, or a visible ray under hard visibility: no bounce */
         for (int c = 0; c < 3; ++c) Lin[c] = vis * Le[c];
         return;
     }
@@ -550,7 +554,8 @@ static void incoming(const or_model *M, const or_env *E, const or_sampling *S, i
         for (int i = 0; i < nf; ++i) z[i] = fb[i];
         z[nf] = wj[0]; z[nf + 1] = wj[1]; z[nf + 2] = wj[2];
         mlp_fwd(&M->irt, z, h1, h2, o);
-        double vj = sigmoid(o[0]);
+        /* hard visibility: only visible secondary rays contribute */
+        double vj = hard ? (o[0] > 0.0 ? 1.0 : 0.0) : sigmoid(o[0]);
         env_lookup(E, wj, Ej);
         brdf_eval(nb, nb, wj, ab, rb, mb, M->f0, (S->flags & OR_DIFFUSE_ONLY) != 0, fr, t1, t2, t3);
         for (int c = 0; c < 3; ++c) Lo[c] += M_PI * fr[c] * vj * Ej[c];

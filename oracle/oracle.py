@@ -21,6 +21,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 GCC_FLAGS = ["-O2", "-fopenmp", "-ffp-contract=off", "-std=c11", "-Wall", "-shared", "-fPIC"]
 
 DIFFUSE_ONLY = 1
+HARD_VIS = 2
 
 
 def build(force: bool = True) -> str:

@@ -633,3 +633,48 @@ def test_adam_first_step_closed_form():
     p2, _, _ = O.adam(p1, g, m1, v1, 2, lr=lr, eps=eps)
     # (bias-corrected moments are again g and g^2)
     assert np.allclose(p2 - p1, -lr * g / (np.abs(g) + eps), rtol=1e-9, atol=1e-15)
+
+
+# ------------------------------------------------------- hard visibility --
+def test_hard_visibility_gates_the_bounce():
+    """Hard visibility (Sec. 3.2 "Overview"): v = [o0 > 0]; a visible ray
+    takes the environment radiance, a shadow ray takes L'_o built from the
+    visible secondary rays only.  The tracer here outputs o0 = w_y, so
+    v = [w_y > 0] at the primary and at the bounce point."""
+    L, log2T = 4, 10
+    m = small_model(L=L, log2T=log2T)
+    nf, hid = 2 * L, 64
+    W0 = np.zeros((hid, nf + 3), np.float32); W0[0, nf + 1] = 1.0     # h1[0] = w_y + 10
+    b0 = np.full(hid, 10.0, np.float32)
+    W1 = np.eye(hid, dtype=np.float32); b1 = np.zeros(hid, np.float32)
+    W2 = np.zeros((2, hid), np.float32); W2[0, 0] = 1.0
+    b2 = np.array([-10.0, 0.3], np.float32)                          # o0 = w_y
+    m["irt"] = [W0, b0, W1, b1, W2, b2]
+    alb = (0.3, 0.6, 0.9)
+    m["brdf"] = const_mlp(nf, 5, [logit(a) for a in alb] + [0.0, -40.0])
+    om = O.OracleModel(m, LO, EXT)
+    L_ = 1.5
+    oe = O.OracleEnv(np.full((8, 16, 3), L_, np.float32))
+    n = 200
+    x = np.random.default_rng(4).uniform(-1, 1, (n, 3)).astype(np.float32)
+    w = rand_normals(n, 33).astype(np.float32)
+    s = O.sampling(1, 8, 7, O.DIFFUSE_ONLY | O.HARD_VIS)
+    rgb, vis, dep = O.render(om, oe, s, x, dirs=w, indirect=True)
+    aa = 1 / (1 + np.exp(-np.array([np.float32(logit(a)) for a in alb], np.float64)))
+    Lf = float(np.float32(L_))
+    wd = w.astype(np.float64)
+    assert np.array_equal(vis, (wd[:, 1] > 0).astype(np.float64))
+    for p in range(n):
+        if wd[p, 1] > 0:
+            ref = np.full(3, Lf)
+        else:
+            nb = np.repeat(-wd[p:p + 1], 8, 0)
+            wj = O.sample_dirs(7, nb, p, 0, np.arange(8), 1, 8)
+            ref = aa * Lf * np.mean(wj[:, 1] > 0)
+        assert np.allclose(rgb[p], ref, rtol=1e-12, atol=1e-15), (p, rgb[p], ref)
+    # direct-only: L_in = v L
+    rgbd, _, _ = O.render(om, oe, s, x, dirs=w, indirect=False)
+    assert np.allclose(rgbd, (wd[:, 1:2] > 0) * Lf, rtol=1e-15)
+    # soft visibility on the same model differs (sigmoid of w_y, bounce always on)
+    rgbs, viss, _ = O.render(om, oe, O.sampling(1, 8, 7, O.DIFFUSE_ONLY), x, dirs=w, indirect=True)
+    assert np.allclose(viss, 1 / (1 + np.exp(-wd[:, 1])), rtol=1e-7)
