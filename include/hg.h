@@ -56,6 +56,9 @@ typedef enum { HG_F32 = 0, HG_F16 = 1, HG_BF16 = 2 } hg_dtype;
 
 /* hg_sampling.flags */
 #define HG_DIFFUSE_ONLY 1u /* f_r = albedo/pi (furnace tests) */
+#define HG_HARD_VIS 2u     /* binary visibility v = [o0 > 0]; the bounce runs only for shadow
+                              rays and sums visible secondary rays only (Sec. 3.2 "Overview");
+                              forward only */
 
 /* Multi-resolution hash grid (Sec. 3.2, InstantNGP layout).
  * table: [L][T][F], T = 2^log2_T, entries FP32 or FP16.

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libhg.so")
 HG_OK, HG_E_INVALID, HG_E_UNSUPPORTED, HG_E_WORKSPACE, HG_E_HIP = range(5)
 HG_F32, HG_F16, HG_BF16 = 0, 1, 2
 HG_DIFFUSE_ONLY = 1
+HG_HARD_VIS = 2
 
 BOX_LO = -8.0
 BOX_EXTENT = 16.0

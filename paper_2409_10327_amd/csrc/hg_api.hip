@@ -148,7 +148,7 @@ hg_status check_sampling(const hg_sampling *s, bool need_primary, hg::SampK &k) 
     if (need_primary)
         REQUIRE(pow2(s->n_dirs) && s->n_dirs <= 1024, "n_dirs = %d is not a power of two in [1, 1024]", s->n_dirs);
     REQUIRE(pow2(s->n_dirs2) && s->n_dirs2 <= 64, "n_dirs2 = %d is not a power of two in [1, 64]", s->n_dirs2);
-    REQUIRE((s->flags & ~HG_DIFFUSE_ONLY) == 0, "unknown sampling flags 0x%x", s->flags);
+    REQUIRE((s->flags & ~(HG_DIFFUSE_ONLY | HG_HARD_VIS)) == 0, "unknown sampling flags 0x%x", s->flags);
     const int N = need_primary ? s->n_dirs : 1;
     const int na = 1 << (ilog2(N) / 2), nb = N / na;
     const int N2 = s->n_dirs2;
@@ -277,6 +277,7 @@ hg_status hg_backward(const hg_model *model, const hg_env *env, const hg_samplin
     REQUIRE(query || pts->n == 0, "hg_backward needs query-mode points (dir != NULL)");
     CHECK(check_sampling(samp, false, k.r.s));
     SUPPORT(prec != Prec::Mixed, "hg_backward needs FP32 MLP weights (the masters)");
+    SUPPORT((samp->flags & HG_HARD_VIS) == 0, "hard visibility is a forward-only mode");
     REQUIRE(indirect == 0 || indirect == 1, "indirect must be 0 or 1");
     if (pts->n == 0) return HG_OK;
     CHECK(check_ptr(g_rgb, "g_rgb"));

@@ -94,10 +94,11 @@ __device__ __forceinline__ void incoming(const RenderK &a, const float (&f)[kNF]
     for (int i = 0; i < kNF; ++i) z[i] = f[i];
     z[kNF] = w.x; z[kNF + 1] = w.y; z[kNF + 2] = w.z;
     mlp_fwd<kNI, 2, float>(a.irt, z, hbuf, hbuf, lane, h, o);
-    V = sigmoidf_(o[0]);
+    const bool hard = (a.s.flags & 2u) != 0;
+    V = hard ? (o[0] > 0.0f ? 1.0f : 0.0f) : sigmoidf_(o[0]);
     d = fminf(softplusf_(o[1]), 1.0f);
     const float3 Le = env_lookup(a.env, w.x, w.y, w.z);
-    if (!INDIRECT) {
+    if (!INDIRECT || (hard && V == 1.0f)) {
         Lin = make_float3(V * Le.x, V * Le.y, V * Le.z);
         return;
     }
@@ -124,7 +125,7 @@ __device__ __forceinline__ void incoming(const RenderK &a, const float (&f)[kNF]
         const float3 wj = sample_dir(pick4(words, j), j, a.s.nb2_shift, a.s.inv_na2, a.s.inv_nb2, fr);
         z[kNF] = wj.x; z[kNF + 1] = wj.y; z[kNF + 2] = wj.z;
         mlp_fwd<kNI, 2, float>(a.irt, z, hbuf, hbuf, lane, h, o);
-        const float vj = sigmoidf_(o[0]);
+        const float vj = hard ? (o[0] > 0.0f ? 1.0f : 0.0f) : sigmoidf_(o[0]);
         const float3 Ej = env_lookup(a.env, wj.x, wj.y, wj.z);
         const float3 c = fb_.eval(dot3(nb, wj));
         Lx = fmaf(c.x * vj, Ej.x, Lx);

@@ -113,6 +113,8 @@ struct Bf16Path {
         uint4 om[64];     // per-query direction operand (w_hi, w_lo)
         float ax[4][kH];  // per-pixel tracer point part (shade mode)
         float mat[4][8];  // per-pixel decoder outputs (shade mode)
+        uint16_t qi[128]; // queued shadow rays (hard visibility): direction index
+        float qd[128];    // and normalised depth
     };
 
     static __device__ float tile_value(const RenderK &a, int t, int i, int g, int e) {
@@ -253,6 +255,8 @@ struct F32Path {
         float4 om[64];
         float ax[4][kH];
         float mat[4][8];
+        uint16_t qi[128];
+        float qd[128];
     };
 
     static __device__ float tile_value(const RenderK &a, int t, int i, int g) {
@@ -376,6 +380,69 @@ struct F32Path {
 };
 
 // ============================================================================
+// Outgoing radiance L'_o at the bounce point x' = x + t w of each lane's query
+// (all 64 lanes take part in the matrix-core products).
+// ============================================================================
+template <class PP, class TT>
+__device__ __forceinline__ float3 bounce_lo(const RenderK &a, const typename PP::Tile *tiles, typename PP::Wave &W,
+                                            const typename PP::Tracer &T, int lane, int g, float3 x, float3 w,
+                                            float dd, uint32_t pid, uint32_t q, bool hard, bool diffuse) {
+    const float t = fmaf(a.t_span, dd, a.t_near);
+    const float3 xb = make_float3(fmaf(t, w.x, x.x), fmaf(t, w.y, x.y), fmaf(t, w.z, x.z));
+    float fb[kNF];
+    encode<TT>(a.g, xb.x, xb.y, xb.z, fb);
+    wave_sync_lds();
+    PP::store_feat(W, lane, fb);
+    wave_sync_lds();
+    f32x4 bpt[4][4];
+    float ob0 = 0.f, ob1 = 0.f, ob2 = 0.f, ob3 = 0.f, ob4 = 0.f;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        f32x4 d[4];
+        PP::point_part(tiles, a, W, nt, lane, g, d);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) bpt[m][nt] = d[m];
+        f32x4 oa, obb;
+        PP::decoder(tiles, a, W, nt, lane, g, oa, obb);
+        if (g == nt) {
+            ob0 = oa[0]; ob1 = oa[1]; ob2 = oa[2]; ob3 = oa[3]; ob4 = obb[0];
+        }
+    }
+    const float3 ab = make_float3(sigmoidf_(ob0), sigmoidf_(ob1), sigmoidf_(ob2));
+    const float rb = 0.09f + 0.91f * sigmoidf_(ob3);
+    const float mb = sigmoidf_(ob4);
+    const float3 nb = make_float3(-w.x, -w.y, -w.z);
+    const Frame frb = make_frame(nb);
+    FacingBrdf fb_;
+    fb_.set(ab, rb, mb, a.f0, diffuse);
+    float Lx = 0.f, Ly = 0.f, Lz = 0.f;
+    uint4 words2 = make_uint4(0, 0, 0, 0);
+    for (uint32_t j = 0; j < a.s.n_dirs2; ++j) {
+        if ((j & 3u) == 0) words2 = philox4x32_10(pid, q, j >> 2, 1u, a.s.key0, a.s.key1);
+        const float3 wj = sample_dir(pick4(words2, j), j, a.s.nb2_shift, a.s.inv_na2, a.s.inv_nb2, frb);
+        wave_sync_lds();
+        PP::store_dir(W, lane, wj);
+        wave_sync_lds();
+        float vo = 0.f;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const f32x4 c[4] = {bpt[0][nt], bpt[1][nt], bpt[2][nt], bpt[3][nt]};
+            const f32x4 h = PP::tracer(T, tiles, W, nt, lane, c);
+            if (g == nt) vo = h[0];
+        }
+        // hard visibility: only visible secondary rays contribute
+        const float vj = hard ? (vo > 0.0f ? 1.0f : 0.0f) : sigmoidf_(vo);
+        const float3 Ej = env_lookup(a.env, wj.x, wj.y, wj.z);
+        const float3 c = fb_.eval(dot3(nb, wj));
+        Lx = fmaf(c.x * vj, Ej.x, Lx);
+        Ly = fmaf(c.y * vj, Ej.y, Ly);
+        Lz = fmaf(c.z * vj, Ej.z, Lz);
+    }
+    const float inv = 1.0f / (float)a.s.n_dirs2;
+    return make_float3(Lx * inv, Ly * inv, Lz * inv);
+}
+
+// ============================================================================
 // The kernel.  QUERY: one query per lane with its own point and direction;
 // otherwise shade mode with G = min(N, 64) lanes per pixel (N >= 16, so at
 // most four pixels per wave).
@@ -396,6 +463,7 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mma(const RenderK a, int
     T.load(tiles, a, lane, g);
 
     const bool diffuse = (a.s.flags & 1u) != 0;
+    const bool hard = (a.s.flags & 2u) != 0;
     const uint32_t gs = a.s.g_shift;
     const uint32_t G = 1u << gs;
     const int ppw = 64 >> gs;
@@ -481,101 +549,105 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mma(const RenderK a, int
         const uint32_t i0 = QUERY ? 0u : (uint32_t)(lane & (G - 1));
         const uint32_t step = QUERY ? 1u : G;
         KSum sx{0.f, 0.f}, sy{0.f, 0.f}, sz{0.f, 0.f};
-
-        for (uint32_t i = i0; i < N; i += step) {
-            // ---------------- primary direction and tracer ----------------
-            float3 w;
-            if (QUERY) {
-                w = make_float3(a.dir[3 * p], a.dir[3 * p + 1], a.dir[3 * p + 2]);
-            } else {
-                const uint4 words = philox4x32_10((uint32_t)p, 0u, i >> 2, 0u, a.s.key0, a.s.key1);
-                w = sample_dir(pick4(words, i), i, a.s.nb_shift, a.s.inv_na, a.s.inv_nb, fr);
-            }
-            PP::store_dir(W, lane, w);
-            wave_sync_lds();
-            float o0 = 0.f, o1 = 0.f;
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                f32x4 c[4];
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    if (QUERY) {
-                        c[m] = apt[m][nt];
-                    } else {
-                        // columns of N-tile nt belong to pixel slot (16 nt) >> gs
-                        const float4 v4 = *reinterpret_cast<const float4 *>(&W.ax[(16 * nt) >> gs][16 * m + 4 * g]);
-                        c[m] = f32x4{v4.x, v4.y, v4.z, v4.w};
-                    }
+        // Under hard visibility with one pixel per wave, only shadow rays
+        // need the bounce: they are queued in LDS and bounced 64 at a time.
+        const bool compact = INDIRECT && !QUERY && hard && ppw == 1;
+        uint32_t i_next = i0;
+        bool more = i_next < N;
+        int cnt = 0;
+        while (true) {
+            // ---------------- primary directions of the next chunk ----------------
+            float3 w_own = make_float3(0.f, 0.f, 1.f), Le_own = w_own;
+            float V_own = 0.f, d_own = 0.f;
+            const uint32_t i_own = i_next;
+            const bool had = more;
+            if (more) {
+                if (QUERY) {
+                    w_own = make_float3(a.dir[3 * p], a.dir[3 * p + 1], a.dir[3 * p + 2]);
+                } else {
+                    const uint4 words = philox4x32_10((uint32_t)p, 0u, i_own >> 2, 0u, a.s.key0, a.s.key1);
+                    w_own = sample_dir(pick4(words, i_own), i_own, a.s.nb_shift, a.s.inv_na, a.s.inv_nb, fr);
                 }
-                const f32x4 h = PP::tracer(T, tiles, W, nt, lane, c);
-                if (g == nt) {
-                    o0 = h[0];
-                    o1 = h[1];
-                }
-            }
-            const float V = sigmoidf_(o0);
-            const float dd = fminf(softplusf_(o1), 1.0f);
-            const float3 Le = env_lookup(a.env, w.x, w.y, w.z);
-            float3 Lin;
-            if (!INDIRECT) {
-                Lin = make_float3(V * Le.x, V * Le.y, V * Le.z);
-            } else {
-                // ---------------- bounce point ----------------
-                const float t = fmaf(a.t_span, dd, a.t_near);
-                const float3 xb = make_float3(fmaf(t, w.x, x.x), fmaf(t, w.y, x.y), fmaf(t, w.z, x.z));
-                float fb[kNF];
-                encode<TT>(a.g, xb.x, xb.y, xb.z, fb);
                 wave_sync_lds();
-                PP::store_feat(W, lane, fb);
+                PP::store_dir(W, lane, w_own);
                 wave_sync_lds();
-                f32x4 bpt[4][4];
-                float ob0 = 0.f, ob1 = 0.f, ob2 = 0.f, ob3 = 0.f, ob4 = 0.f;
+                float o0 = 0.f, o1 = 0.f;
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt) {
-                    f32x4 d[4];
-                    PP::point_part(tiles, a, W, nt, lane, g, d);
+                    f32x4 c[4];
 #pragma unroll
-                    for (int m = 0; m < 4; ++m) bpt[m][nt] = d[m];
-                    f32x4 oa, obb;
-                    PP::decoder(tiles, a, W, nt, lane, g, oa, obb);
+                    for (int m = 0; m < 4; ++m) {
+                        if (QUERY) {
+                            c[m] = apt[m][nt];
+                        } else {
+                            // columns of N-tile nt belong to pixel slot (16 nt) >> gs
+                            const float4 v4 =
+                                *reinterpret_cast<const float4 *>(&W.ax[(16 * nt) >> gs][16 * m + 4 * g]);
+                            c[m] = f32x4{v4.x, v4.y, v4.z, v4.w};
+                        }
+                    }
+                    const f32x4 h = PP::tracer(T, tiles, W, nt, lane, c);
                     if (g == nt) {
-                        ob0 = oa[0]; ob1 = oa[1]; ob2 = oa[2]; ob3 = oa[3]; ob4 = obb[0];
+                        o0 = h[0];
+                        o1 = h[1];
                     }
                 }
-                const float3 ab = make_float3(sigmoidf_(ob0), sigmoidf_(ob1), sigmoidf_(ob2));
-                const float rb = 0.09f + 0.91f * sigmoidf_(ob3);
-                const float mb = sigmoidf_(ob4);
-                const float3 nb = make_float3(-w.x, -w.y, -w.z);
-                const Frame frb = make_frame(nb);
-                FacingBrdf fb_;
-                fb_.set(ab, rb, mb, a.f0, diffuse);
-                const uint32_t q = QUERY ? 0u : i;
-                float Lx = 0.f, Ly = 0.f, Lz = 0.f;
-                uint4 words2 = make_uint4(0, 0, 0, 0);
-                for (uint32_t j = 0; j < a.s.n_dirs2; ++j) {
-                    if ((j & 3u) == 0) words2 = philox4x32_10((uint32_t)p, q, j >> 2, 1u, a.s.key0, a.s.key1);
-                    const float3 wj = sample_dir(pick4(words2, j), j, a.s.nb2_shift, a.s.inv_na2, a.s.inv_nb2, frb);
-                    wave_sync_lds();
-                    PP::store_dir(W, lane, wj);
-                    wave_sync_lds();
-                    float vo = 0.f;
-#pragma unroll
-                    for (int nt = 0; nt < 4; ++nt) {
-                        const f32x4 c[4] = {bpt[0][nt], bpt[1][nt], bpt[2][nt], bpt[3][nt]};
-                        const f32x4 h = PP::tracer(T, tiles, W, nt, lane, c);
-                        if (g == nt) vo = h[0];
-                    }
-                    const float vj = sigmoidf_(vo);
-                    const float3 Ej = env_lookup(a.env, wj.x, wj.y, wj.z);
-                    const float3 c = fb_.eval(dot3(nb, wj));
-                    Lx = fmaf(c.x * vj, Ej.x, Lx);
-                    Ly = fmaf(c.y * vj, Ej.y, Ly);
-                    Lz = fmaf(c.z * vj, Ej.z, Lz);
+                V_own = hard ? (o0 > 0.0f ? 1.0f : 0.0f) : sigmoidf_(o0);
+                d_own = fminf(softplusf_(o1), 1.0f);
+                Le_own = env_lookup(a.env, w_own.x, w_own.y, w_own.z);
+                if (!QUERY && live && a.vis) {
+                    a.vis[p * N + i_own] = V_own;
+                    a.depth[p * N + i_own] = d_own;
                 }
-                const float inv = 1.0f / (float)a.s.n_dirs2;
-                const float om = 1.0f - V;
-                Lin = make_float3(fmaf(V, Le.x, om * Lx * inv), fmaf(V, Le.y, om * Ly * inv),
-                                  fmaf(V, Le.z, om * Lz * inv));
+                if (compact) {
+                    // visible rays are finished here; shadow rays are queued
+                    const bool vis1 = V_own == 1.0f;
+                    if (vis1) {
+                        const float3 c = pi_brdf(n_, v_, w_own, alb, rr, mm, a.f0, diffuse);
+                        sx.add(c.x * Le_own.x);
+                        sy.add(c.y * Le_own.y);
+                        sz.add(c.z * Le_own.z);
+                    }
+                    const uint64_t qm = __ballot(!vis1);
+                    const int pos = cnt + __popcll(qm & ((1ull << lane) - 1ull));
+                    if (!vis1) {
+                        W.qi[pos] = (uint16_t)i_own;
+                        W.qd[pos] = d_own;
+                    }
+                    cnt += __popcll(qm);
+                }
+                i_next += step;
+                more = i_next < N;
+            }
+            const bool flush = compact ? (cnt >= 64 || (!more && cnt > 0)) : had;
+            if (!flush) {
+                if (!more) break;
+                continue;
+            }
+            // ---------------- bounce for 64 lanes ----------------
+            bool active = true;
+            uint32_t ie = i_own;
+            float de = d_own, Ve = V_own;
+            float3 we = w_own;
+            if (compact) {
+                wave_sync_lds();
+                active = lane < cnt;
+                const int slot = active ? lane : 0;
+                ie = W.qi[slot];
+                de = W.qd[slot];
+                Ve = 0.0f;
+                const uint4 words = philox4x32_10((uint32_t)p, 0u, ie >> 2, 0u, a.s.key0, a.s.key1);
+                we = sample_dir(pick4(words, ie), ie, a.s.nb_shift, a.s.inv_na, a.s.inv_nb, fr);
+            }
+            float3 Lin;
+            if (!INDIRECT) {
+                Lin = make_float3(Ve * Le_own.x, Ve * Le_own.y, Ve * Le_own.z);
+            } else {
+                const float3 Lo = bounce_lo<PP, TT>(a, tiles, W, T, lane, g, x, we, de, (uint32_t)p,
+                                                    QUERY ? 0u : ie, hard, diffuse);
+                const float om = 1.0f - Ve;
+                Lin = make_float3(fmaf(Ve, Le_own.x, om * Lo.x), fmaf(Ve, Le_own.y, om * Lo.y),
+                                  fmaf(Ve, Le_own.z, om * Lo.z));
             }
             if (QUERY) {
                 if (live) {
@@ -583,19 +655,32 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mma(const RenderK a, int
                     a.rgb[3 * p + 1] = Lin.y;
                     a.rgb[3 * p + 2] = Lin.z;
                     if (a.vis) {
-                        a.vis[p] = V;
-                        a.depth[p] = dd;
+                        a.vis[p] = V_own;
+                        a.depth[p] = d_own;
                     }
                 }
-            } else {
-                const float3 c = pi_brdf(n_, v_, w, alb, rr, mm, a.f0, diffuse);
+            } else if (active) {
+                const float3 c = pi_brdf(n_, v_, we, alb, rr, mm, a.f0, diffuse);
                 sx.add(c.x * Lin.x);
                 sy.add(c.y * Lin.y);
                 sz.add(c.z * Lin.z);
-                if (live && a.vis) {
-                    a.vis[p * N + i] = V;
-                    a.depth[p * N + i] = dd;
+            }
+            if (compact) {
+                // drop the 64 entries just bounced; move the rest to the front
+                wave_sync_lds();
+                const int rest = cnt - 64;
+                uint16_t ti = 0;
+                float td = 0.f;
+                if (lane < rest) {
+                    ti = W.qi[64 + lane];
+                    td = W.qd[64 + lane];
                 }
+                wave_sync_lds();
+                if (lane < rest) {
+                    W.qi[lane] = ti;
+                    W.qd[lane] = td;
+                }
+                cnt = rest > 0 ? rest : 0;
             }
             wave_sync_lds();
         }

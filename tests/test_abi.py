@@ -101,6 +101,10 @@ def test_sampling_validation(n_dirs, n_dirs2):
     assert call_render(samp=hg.sampling_struct(n_dirs, n_dirs2, 7, 0)) == hg.HG_E_INVALID
 
 
+def test_unknown_flags_rejected():
+    assert call_render(samp=hg.sampling_struct(32, 8, 7, 4)) == hg.HG_E_INVALID
+
+
 def test_points_validation():
     p = hg.Points(); p.n, p.pos, p.nrm, p.wo, p.dir = 10, FAKE, None, FAKE, None
     assert call_render(pts=p) == hg.HG_E_INVALID            # shade mode needs normals
@@ -130,8 +134,11 @@ def test_other_entry_points_validate():
     # backward needs query-mode points
     assert L.hg_backward(C.byref(m), C.byref(env), C.byref(s), C.byref(p), 1, C.c_void_p(FAKE), C.c_void_p(FAKE),
                          C.c_void_p(FAKE), C.c_void_p(FAKE), gb, gb, None, None) == hg.HG_E_INVALID
+    p.dir = FAKE
+    sh = hg.sampling_struct(1, 8, 7, hg.HG_HARD_VIS)   # hard visibility is forward-only
+    assert L.hg_backward(C.byref(m), C.byref(env), C.byref(sh), C.byref(p), 1, C.c_void_p(FAKE), C.c_void_p(FAKE),
+                         C.c_void_p(FAKE), C.c_void_p(FAKE), gb, gb, None, None) == hg.HG_E_UNSUPPORTED
     m.brdf.dtype = m.irt.dtype = hg.HG_BF16
     m.grid.dtype = hg.HG_F16
-    p.dir = FAKE
     assert L.hg_backward(C.byref(m), C.byref(env), C.byref(s), C.byref(p), 1, C.c_void_p(FAKE), C.c_void_p(FAKE),
                          C.c_void_p(FAKE), C.c_void_p(FAKE), gb, gb, None, None) == hg.HG_E_UNSUPPORTED

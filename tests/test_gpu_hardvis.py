@@ -1,0 +1,86 @@
+"""Hard-visibility rendering (v = [o0 > 0], bounce only for shadow rays, visible
+secondary rays only; Sec. 3.2 "Overview") against the FP64 oracle.
+
+The binary decisions are taken in each side's own precision, so queries whose
+tracer output lies within a hair of the threshold may decide differently:
+primary decisions are masked with the oracle's soft visibility, and the few
+queries (pixels) affected by a flipped secondary decision are counted and
+bounded rather than compared."""
+import numpy as np
+import pytest
+import torch
+
+import hg_inputs as H
+import paper_2409_10327_amd as hg
+from oracle import oracle as O
+from helpers import c1_setup, psnr, relerr
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+HARD = 2
+
+
+@pytest.fixture(scope="module")
+def c1():
+    cfg, model, env, pos, nrm, wo = c1_setup()
+    r = hg.HashRenderer(model, DEV)
+    r.refresh_shadows()
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    return dict(cfg=cfg, model=model, env=env, pos=pos, nrm=nrm, wo=wo, r=r, t=t,
+                om=O.OracleModel(model, H.BOX_LO, H.BOX_EXTENT), oe=O.OracleEnv(env))
+
+
+def split_ok(a, b, tol):
+    """Per-row relative error; returns (mask of rows within tol, norm-wise
+    error over those rows)."""
+    e = np.linalg.norm(a - b, axis=1) / (np.linalg.norm(b, axis=1) + 1e-6)
+    ok = e < tol
+    return ok, relerr(a[ok], b[ok])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "mixed"])
+def test_hard_query(c1, precision):
+    print(f"case: hard visibility query {precision}", flush=True)
+    t = c1["t"]
+    pos, dirs = H.make_train_batch(4099, seed=51)
+    rgb, vis, dep = hg.render(c1["r"], t(c1["env"]), t(pos), dirs=t(dirs), flags=HARD, precision=precision)
+    rgb, vis = rgb.cpu().numpy(), vis.cpu().numpy()
+    orgb, ovis, _ = O.render(c1["om"], c1["oe"], O.sampling(1, 8, 7, O.HARD_VIS), pos, dirs=dirs)
+    _, vsoft, _ = O.render(c1["om"], c1["oe"], O.sampling(1, 8, 7, 0), pos, dirs=dirs)
+    margin = 1e-4 if precision == "fp32" else 2e-2
+    clear = np.abs(vsoft - 0.5) > margin
+    assert np.array_equal(vis[clear], ovis[clear])
+    ok, e = split_ok(rgb[clear], orgb[clear], 1e-4 if precision == "fp32" else 2e-2)
+    print(f"hard query {precision}: {ok.mean():.4f} of clear queries agree, rel err {e:.3g}")
+    assert ok.mean() > (0.995 if precision == "fp32" else 0.97)
+    assert e < (1e-5 if precision == "fp32" else 2e-3)
+
+
+@pytest.mark.parametrize("N,precision", [(32, "fp32"), (128, "fp32"), (128, "mixed")])
+def test_hard_shade(c1, N, precision):
+    """N = 128 takes the shadow-ray queue (one pixel per wave); N = 32 does not."""
+    print(f"case: hard visibility shade N={N} {precision}", flush=True)
+    t = c1["t"]
+    sl = slice(0, 1024)
+    pos, nrm, wo = c1["pos"][sl], c1["nrm"][sl], c1["wo"][sl]
+    rgb, vis, _ = hg.render(c1["r"], t(c1["env"]), t(pos), t(nrm), t(wo), n_dirs=N, flags=HARD, want_vis=True,
+                            precision=precision)
+    rgb, vis = rgb.cpu().numpy(), vis.cpu().numpy()
+    orgb, ovis, _ = O.render(c1["om"], c1["oe"], O.sampling(N, 8, 7, O.HARD_VIS), pos, nrm, wo)
+    _, vsoft, _ = O.render(c1["om"], c1["oe"], O.sampling(N, 8, 7, 0), pos, nrm, wo)
+    margin = 1e-4 if precision == "fp32" else 2e-2
+    clear_px = np.all(np.abs(vsoft - 0.5) > margin, axis=1)
+    assert np.array_equal(vis[clear_px], ovis[clear_px])
+    ok, e = split_ok(rgb[clear_px], orgb[clear_px], 1e-4 if precision == "fp32" else 2e-2)
+    print(f"hard shade N={N} {precision}: {ok.mean():.4f} of clear pixels agree, rel err {e:.3g}, "
+          f"PSNR all {psnr(rgb, orgb):.1f} dB")
+    assert ok.mean() > (0.98 if precision == "fp32" else 0.9)
+    assert e < (1e-5 if precision == "fp32" else 2e-3)
+
+
+def test_hard_is_deterministic(c1):
+    t = c1["t"]
+    args = (c1["r"], t(c1["env"]), t(c1["pos"]), t(c1["nrm"]), t(c1["wo"]))
+    a = hg.render(*args, n_dirs=128, flags=HARD)[0]
+    b = hg.render(*args, n_dirs=128, flags=HARD)[0]
+    assert torch.equal(a, b)
