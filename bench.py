@@ -152,6 +152,18 @@ def main():
         except hg.HGError as e:
             out["mixed"] = {"unavailable": str(e)}
 
+        # hard visibility: the bounce runs only for shadow rays
+        def frame_hard(prec):
+            def f():
+                hg.render(r, env_t, pos_t, nrm_t, wo_t, n_dirs=cfg.n_dirs, n_dirs2=cfg.n_dirs2, seed=H.SEED_DIRS,
+                          indirect=True, flags=hg.HG_HARD_VIS, precision=prec, out=(rgb, None, None))
+            return f
+        print("[bench] hard-visibility frames", file=sys.stderr, flush=True)
+        msh32, _, _ = time_events(frame_hard("fp32"), args.steps, args.warmup, torch)
+        mshm, _, _ = time_events(frame_hard("mixed"), args.steps, args.warmup, torch)
+        out["hard_visibility"] = {"fp32_ms": msh32, "mixed_ms": mshm,
+                                  "fp32_queries_per_s": S / (msh32 * 1e-3), "mixed_queries_per_s": S / (mshm * 1e-3)}
+
     if not args.no_encode:
         # hg_encode gather bandwidth: 2^24 points uniform in the scene's
         # bounding region, FP32 tables (T = 2^19, 64 MiB).  Algorithmic bytes
