@@ -195,6 +195,30 @@ hg_status hg_adam_step(float *param, const float *grad, float *m, float *v, int6
                        float weight_decay, void *shadow, hg_dtype shadow_dtype,
                        hipStream_t stream);
 
+/* Spatial variance-guided a-trous filter of a rendered frame: SVGF without
+ * its temporal parts, as the paper applies it to the Monte Carlo result
+ * (Sec. 4.1); the depth gradient for the edge-stopping weight is a finite
+ * difference of the depth map (supplementary "Rendering Details").
+ * rgb, out [H][W][3]; depth [H][W]; nrm [H][W][3] (unit normals).
+ * Iteration k uses a 5x5 B3-spline footprint with step 2^k and weights
+ *   exp(-|z_p - z_q| / (sigma_z |grad z_p . (p - q)| + 1e-6))
+ *   * max(0, n_p . n_q)^sigma_n
+ *   * exp(-|l_p - l_q| / (sigma_l sqrt(g3(var)_p) + 1e-10)),
+ * luminance l with Rec. 709 weights, variance initialised from 7x7
+ * luminance moments and propagated with the squared weights; taps outside
+ * the image are dropped.  work: device scratch of at least
+ * hg_denoise_workspace_size(H, W) bytes, 16-byte aligned; its contents on
+ * entry are ignored.  iterations = 0 copies rgb to out. */
+typedef struct {
+    int32_t iterations;
+    float sigma_z, sigma_n, sigma_l;
+} hg_denoise_params;
+
+size_t hg_denoise_workspace_size(int32_t H, int32_t W);
+hg_status hg_denoise(const float *rgb, const float *depth, const float *nrm, int32_t H, int32_t W,
+                     const hg_denoise_params *params, float *out, void *work, size_t work_bytes,
+                     hipStream_t stream);
+
 /* Message describing the calling thread's last failed call ("" if none). */
 const char *hg_last_error(void);
 

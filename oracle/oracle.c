@@ -846,3 +846,103 @@ void or_adam(double *param, const double *grad, double *m, double *v, int64_t n,
         param[i] -= lr * mh / (sqrt(vh) + eps);
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Spatial variance-guided a-trous filter (SVGF, Schied et al. 2017) without */
+/* its temporal parts, as the paper applies it to the MC result (Sec. 4.1);  */
+/* the clip-space depth gradient is a finite difference of the depth map    */
+/* (supplementary "Rendering Details").  Readings:                          */
+/*  - luminance l = 0.2126 R + 0.7152 G + 0.0722 B;                          */
+/*  - initial variance: unweighted 7x7 moments, var = E[l^2] - E[l]^2,       */
+/*    over the taps inside the image;                                       */
+/*  - depth gradient: forward differences z(x+1,y)-z(x,y), z(x,y+1)-z(x,y)   */
+/*    (backward at the last column/row);                                    */
+/*  - iteration k (k = 0..iters-1) uses step 2^k and the 5x5 B3-spline taps  */
+/*    h = (1/16, 1/4, 3/8, 1/4, 1/16); taps outside the image are skipped;  */
+/*  - weights w = h h * exp(-|z_p - z_q| / (sz |grad z_p . (p-q)| + 1e-6))   */
+/*              * max(0, n_p . n_q)^sn                                       */
+/*              * exp(-|l_p - l_q| / (sl sqrt(g3(var)_p) + 1e-10)),          */
+/*    g3 = 3x3 binomial blur (1,2,1)/4 x (1,2,1)/4 of the variance (edges    */
+/*    clamped);                                                             */
+/*  - colour c' = sum w c / sum w, variance var' = sum w^2 var / (sum w)^2.  */
+/* Inputs rgb [H][W][3], depth [H][W], nrm [H][W][3]; output [H][W][3].      */
+/* ------------------------------------------------------------------------ */
+static double lum(const double *c) { return 0.2126 * c[0] + 0.7152 * c[1] + 0.0722 * c[2]; }
+
+void or_denoise(const float *rgb, const float *depth, const float *nrm, int32_t H, int32_t W, int32_t iters,
+                double sz, double sn, double sl, double *out)
+{
+    const size_t P = (size_t)H * W;
+    double *c = (double *)malloc(P * 3 * sizeof(double));
+    double *c2 = (double *)malloc(P * 3 * sizeof(double));
+    double *var = (double *)malloc(P * sizeof(double));
+    double *var2 = (double *)malloc(P * sizeof(double));
+    double *gx = (double *)malloc(P * sizeof(double));
+    double *gy = (double *)malloc(P * sizeof(double));
+    double *g3 = (double *)malloc(P * sizeof(double));
+    for (size_t i = 0; i < 3 * P; ++i) c[i] = rgb[i];
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            size_t p = (size_t)y * W + x;
+            gx[p] = x + 1 < W ? (double)depth[p + 1] - depth[p] : (double)depth[p] - depth[p - 1];
+            gy[p] = y + 1 < H ? (double)depth[p + W] - depth[p] : (double)depth[p] - depth[p - W];
+            double s1 = 0, s2 = 0;
+            int cnt = 0;
+            for (int dy = -3; dy <= 3; ++dy)
+                for (int dx = -3; dx <= 3; ++dx) {
+                    int xx = x + dx, yy = y + dy;
+                    if (xx < 0 || yy < 0 || xx >= W || yy >= H) continue;
+                    double l = lum(c + 3 * ((size_t)yy * W + xx));
+                    s1 += l;
+                    s2 += l * l;
+                    ++cnt;
+                }
+            double m = s1 / cnt, v = s2 / cnt - m * m;
+            var[p] = v > 0 ? v : 0;
+        }
+    static const double h[5] = {1.0 / 16, 1.0 / 4, 3.0 / 8, 1.0 / 4, 1.0 / 16};
+    for (int it = 0; it < iters; ++it) {
+        const int step = 1 << it;
+        for (int y = 0; y < H; ++y)
+            for (int x = 0; x < W; ++x) {
+                double s = 0;
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        int xx = x + dx < 0 ? 0 : (x + dx >= W ? W - 1 : x + dx);
+                        int yy = y + dy < 0 ? 0 : (y + dy >= H ? H - 1 : y + dy);
+                        s += (dx ? 0.25 : 0.5) * (dy ? 0.25 : 0.5) * var[(size_t)yy * W + xx];
+                    }
+                g3[(size_t)y * W + x] = s;
+            }
+        for (int y = 0; y < H; ++y)
+            for (int x = 0; x < W; ++x) {
+                size_t p = (size_t)y * W + x;
+                double lp = lum(c + 3 * p), zp = depth[p];
+                const float *np = nrm + 3 * p;
+                double ws = 0, acc[3] = {0, 0, 0}, vacc = 0;
+                double lden = sl * sqrt(g3[p] > 0 ? g3[p] : 0) + 1e-10;
+                for (int j = -2; j <= 2; ++j)
+                    for (int i = -2; i <= 2; ++i) {
+                        int xx = x + i * step, yy = y + j * step;
+                        if (xx < 0 || yy < 0 || xx >= W || yy >= H) continue;
+                        size_t q = (size_t)yy * W + xx;
+                        double zq = depth[q];
+                        double wz = exp(-fabs(zp - zq) / (sz * fabs(gx[p] * i * step + gy[p] * j * step) + 1e-6));
+                        double nd = (double)np[0] * nrm[3 * q] + (double)np[1] * nrm[3 * q + 1] +
+                                    (double)np[2] * nrm[3 * q + 2];
+                        double wn = pow(nd > 0 ? nd : 0, sn);
+                        double wl = exp(-fabs(lp - lum(c + 3 * q)) / lden);
+                        double w = h[i + 2] * h[j + 2] * wz * wn * wl;
+                        ws += w;
+                        for (int k = 0; k < 3; ++k) acc[k] += w * c[3 * q + k];
+                        vacc += w * w * var[q];
+                    }
+                for (int k = 0; k < 3; ++k) c2[3 * p + k] = acc[k] / ws;
+                var2[p] = vacc / (ws * ws);
+            }
+        double *t = c; c = c2; c2 = t;
+        t = var; var = var2; var2 = t;
+    }
+    for (size_t i = 0; i < 3 * P; ++i) out[i] = c[i];
+    free(c); free(c2); free(var); free(var2); free(gx); free(gy); free(g3);
+}

@@ -290,3 +290,14 @@ def adam(param, grad, m, v, step, lr=2e-3, b1=0.9, b2=0.999, eps=1e-8, wd=0.0):
     lib().or_adam(_p(p), _p(g), _p(m), _p(v), C.c_int64(p.size), C.c_int32(step), C.c_double(lr),
                   C.c_double(b1), C.c_double(b2), C.c_double(eps), C.c_double(wd))
     return p, m, v
+
+
+def denoise(rgb, depth, nrm, iters=5, sigma_z=1.0, sigma_n=128.0, sigma_l=4.0):
+    """Spatial SVGF filter of an [H, W, 3] image with depth [H, W] and normal
+    [H, W, 3] guides; returns [H, W, 3] float64."""
+    rgb, depth, nrm = _f32(rgb), _f32(depth), _f32(nrm)
+    H, W = depth.shape
+    out = np.empty((H, W, 3))
+    lib().or_denoise(_p(rgb), _p(depth), _p(nrm), C.c_int32(H), C.c_int32(W), C.c_int32(iters),
+                     C.c_double(sigma_z), C.c_double(sigma_n), C.c_double(sigma_l), _p(out))
+    return out

@@ -53,13 +53,17 @@ class Sampling(C.Structure):
     _fields_ = [("n_dirs", C.c_int32), ("n_dirs2", C.c_int32), ("seed", C.c_uint64), ("flags", C.c_uint32)]
 
 
+class DenoiseParams(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("sigma_z", C.c_float), ("sigma_n", C.c_float), ("sigma_l", C.c_float)]
+
+
 class Points(C.Structure):
     _fields_ = [("n", C.c_int64), ("pos", C.c_void_p), ("nrm", C.c_void_p), ("wo", C.c_void_p),
                 ("dir", C.c_void_p)]
 
 
-EXPORTS = ["hg_encode", "hg_encode_index", "hg_render_direct", "hg_render_indirect", "hg_backward", "hg_l2_loss", "hg_adam_step",
-           "hg_last_error"]
+EXPORTS = ["hg_encode", "hg_encode_index", "hg_render_direct", "hg_render_indirect", "hg_backward", "hg_l2_loss",
+           "hg_adam_step", "hg_denoise", "hg_denoise_workspace_size", "hg_last_error"]
 
 _lib = None
 
@@ -74,6 +78,10 @@ def lib():
         L.hg_last_error.restype = C.c_char_p
         for name in EXPORTS[:-1]:
             getattr(L, name).restype = C.c_int
+        L.hg_denoise_workspace_size.restype = C.c_size_t
+        L.hg_denoise_workspace_size.argtypes = [C.c_int32, C.c_int32]
+        L.hg_denoise.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.POINTER(DenoiseParams),
+                                 C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
         L.hg_encode.argtypes = [C.POINTER(Grid), C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
         L.hg_encode_index.argtypes = [C.POINTER(Grid), C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
         for nm in ("hg_render_direct", "hg_render_indirect"):
@@ -295,6 +303,19 @@ def adam_step(param, grad, m, v, step, lr=2e-3, beta1=0.9, beta2=0.999, eps=1e-8
         sd = HG_F16 if shadow.dtype == torch.float16 else HG_BF16
     _check(lib().hg_adam_step(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), param.numel(), step, lr, beta1, beta2,
                               eps, weight_decay, _ptr(shadow), sd, _stream(param.device)))
+
+
+def denoise(rgb, depth, nrm, iterations=5, sigma_z=1.0, sigma_n=128.0, sigma_l=4.0, work=None):
+    """Spatial SVGF filter: rgb [H,W,3], depth [H,W], nrm [H,W,3] -> [H,W,3]."""
+    H, W = depth.shape
+    out = torch.empty_like(rgb)
+    need = lib().hg_denoise_workspace_size(H, W)
+    if work is None or work.numel() * work.element_size() < need:
+        work = torch.empty(need // 4, device=rgb.device, dtype=torch.float32)
+    prm = DenoiseParams(iterations, sigma_z, sigma_n, sigma_l)
+    _check(lib().hg_denoise(_ptr(rgb), _ptr(depth), _ptr(nrm), H, W, C.byref(prm), _ptr(out), _ptr(work),
+                            work.numel() * work.element_size(), _stream(rgb.device)))
+    return out
 
 
 def zero_grads(r: HashRenderer):

@@ -351,4 +351,32 @@ hg_status hg_adam_step(float *param, const float *grad, float *m, float *v, int6
                       "hg_adam_step");
 }
 
+size_t hg_denoise_workspace_size(int32_t H, int32_t W) {
+    if (H <= 0 || W <= 0) return 0;
+    return hg::denoise_workspace_floats(H, W) * sizeof(float);
+}
+
+hg_status hg_denoise(const float *rgb, const float *depth, const float *nrm, int32_t H, int32_t W,
+                     const hg_denoise_params *params, float *out, void *work, size_t work_bytes,
+                     hipStream_t stream) {
+    g_err.clear();
+    REQUIRE(params != nullptr, "params is NULL");
+    REQUIRE(H >= 1 && W >= 1 && (int64_t)H * W < (int64_t(1) << 28), "image size %dx%d invalid", H, W);
+    REQUIRE(params->iterations >= 0 && params->iterations <= 10, "iterations = %d outside [0, 10]",
+            params->iterations);
+    REQUIRE(std::isfinite(params->sigma_z) && std::isfinite(params->sigma_n) && std::isfinite(params->sigma_l) &&
+                params->sigma_z >= 0.0f && params->sigma_n >= 0.0f && params->sigma_l >= 0.0f,
+            "sigmas must be finite and non-negative");
+    CHECK(check_ptr(rgb, "rgb"));
+    CHECK(check_ptr(depth, "depth"));
+    CHECK(check_ptr(nrm, "nrm"));
+    CHECK(check_ptr(out, "out"));
+    CHECK(check_ptr(work, "work"));
+    REQUIRE(work_bytes >= hg_denoise_workspace_size(H, W), "work_bytes %zu < %zu", work_bytes,
+            hg_denoise_workspace_size(H, W));
+    return hip_status(hg::launch_denoise(rgb, depth, nrm, H, W, params->iterations, params->sigma_z,
+                                         params->sigma_n, params->sigma_l, out, static_cast<float *>(work), stream),
+                      "hg_denoise");
+}
+
 }  // extern "C"

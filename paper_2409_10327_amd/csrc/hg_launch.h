@@ -24,6 +24,9 @@ hipError_t launch_render_mixed(const RenderK &a, bool indirect, bool query, hipS
 hipError_t launch_backward(const BwdK &a, bool f16, bool indirect, hipStream_t s);
 hipError_t launch_l2_loss(const float *rgb, const float *vis, const float *dep, const float *tgt, int64_t n,
                           float *loss, float *g_rgb, float *g_vis, float *g_dep, hipStream_t s);
+size_t denoise_workspace_floats(int H, int W);
+hipError_t launch_denoise(const float *rgb, const float *depth, const float *nrm, int H, int W, int iters, float sz,
+                          float sn, float sl, float *out, float *work, hipStream_t s);
 hipError_t launch_adam(float *param, const float *grad, float *m, float *v, int64_t n, float lr, float b1,
                        float b2, float eps, float wd, float bc1, float bc2, void *shadow, int shadow_kind,
                        hipStream_t s);

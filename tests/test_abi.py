@@ -14,12 +14,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def header_symbols():
     src = open(os.path.join(ROOT, "include", "hg.h")).read()
-    return sorted(set(re.findall(r"^(?:hg_status|const char \*)\s*(hg_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^(?:hg_status|const char \*|size_t)\s*(hg_\w+)\s*\(", src, re.M)))
 
 
 def test_library_exports_every_declared_symbol():
     syms = header_symbols()
-    assert len(syms) == 8, syms
+    assert len(syms) == 10, syms
     L = hg.lib()
     for s in syms:
         assert hasattr(L, s), s
@@ -113,6 +113,20 @@ def test_points_validation():
     p = hg.Points(); p.n, p.pos, p.nrm, p.wo, p.dir = 0, None, None, None, None
     assert call_render(pts=p, rgb=0) == hg.HG_OK            # n == 0 is a no-op
     assert call_render(rgb=0) == hg.HG_E_INVALID
+
+
+def test_denoise_validation():
+    L = hg.lib()
+    prm = hg.DenoiseParams(5, 1.0, 128.0, 4.0)
+    assert L.hg_denoise_workspace_size(800, 800) == 800 * 800 * 12 * 4
+    f = C.c_void_p(FAKE)
+    need = L.hg_denoise_workspace_size(8, 8)
+    assert L.hg_denoise(f, f, f, 8, 8, C.byref(prm), f, f, need - 4, None) == hg.HG_E_INVALID
+    assert L.hg_denoise(f, f, f, 0, 8, C.byref(prm), f, f, need, None) == hg.HG_E_INVALID
+    bad = hg.DenoiseParams(11, 1.0, 128.0, 4.0)
+    assert L.hg_denoise(f, f, f, 8, 8, C.byref(bad), f, f, need, None) == hg.HG_E_INVALID
+    bad = hg.DenoiseParams(5, -1.0, 128.0, 4.0)
+    assert L.hg_denoise(f, f, f, 8, 8, C.byref(bad), f, f, need, None) == hg.HG_E_INVALID
 
 
 def test_other_entry_points_validate():

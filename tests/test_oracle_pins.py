@@ -678,3 +678,58 @@ def test_hard_visibility_gates_the_bounce():
     # soft visibility on the same model differs (sigmoid of w_y, bounce always on)
     rgbs, viss, _ = O.render(om, oe, O.sampling(1, 8, 7, O.DIFFUSE_ONLY), x, dirs=w, indirect=True)
     assert np.allclose(viss, 1 / (1 + np.exp(-wd[:, 1])), rtol=1e-7)
+
+
+# ---------------------------------------------------------------- denoiser --
+def _atrous_reference(img, iters):
+    """Plain a-trous B3-spline cascade (taps outside the image dropped and the
+    remaining weights renormalised) via scipy's correlate: the SVGF filter
+    with every edge-stopping weight equal to one."""
+    from scipy import ndimage
+    h = np.array([1 / 16, 1 / 4, 3 / 8, 1 / 4, 1 / 16])
+    out = img.astype(np.float64)
+    ones = np.ones(img.shape[:2])
+    for it in range(iters):
+        step = 1 << it
+        k1 = np.zeros(4 * step + 1)
+        k1[::step] = h
+        K = np.outer(k1, k1)
+        norm = ndimage.correlate(ones, K, mode="constant", cval=0.0)
+        out = np.stack([ndimage.correlate(out[..., c], K, mode="constant", cval=0.0) / norm for c in range(3)], -1)
+    return out
+
+
+def test_denoise_constant_image_is_fixed():
+    rng = np.random.default_rng(0)
+    H, W = 37, 53
+    img = np.full((H, W, 3), [0.7, 1.3, 2.0], np.float32)
+    depth = rng.uniform(1, 5, (H, W)).astype(np.float32)
+    nrm = rand_normals(H * W, 2).reshape(H, W, 3).astype(np.float32)
+    out = O.denoise(img, depth, nrm)
+    assert np.max(np.abs(out - img)) < 1e-12
+
+
+def test_denoise_without_edge_stopping_is_atrous():
+    rng = np.random.default_rng(1)
+    H, W = 40, 47
+    img = rng.uniform(0, 3, (H, W, 3)).astype(np.float32)
+    depth = rng.uniform(1, 5, (H, W)).astype(np.float32)
+    nrm = rand_normals(H * W, 3).reshape(H, W, 3).astype(np.float32)
+    for iters in (1, 3, 5):
+        out = O.denoise(img, depth, nrm, iters=iters, sigma_z=1e30, sigma_n=0.0, sigma_l=1e30)
+        assert np.max(np.abs(out - _atrous_reference(img, iters))) < 1e-12
+
+
+def test_denoise_stops_at_normal_edges():
+    """Normals (0,0,1) on the left and (1,0,0) on the right: n_p . n_q = 0
+    across the edge, so each half keeps its own constant colour exactly."""
+    H, W = 32, 48
+    img = np.zeros((H, W, 3), np.float32)
+    img[:, : W // 2] = [1.0, 0.5, 0.25]
+    img[:, W // 2:] = [4.0, 3.0, 2.0]
+    nrm = np.zeros((H, W, 3), np.float32)
+    nrm[:, : W // 2, 2] = 1
+    nrm[:, W // 2:, 0] = 1
+    depth = np.full((H, W), 2.0, np.float32)
+    out = O.denoise(img, depth, nrm)
+    assert np.max(np.abs(out - img)) < 1e-12
