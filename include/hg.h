@@ -208,7 +208,10 @@ hg_status hg_adam_step(float *param, const float *grad, float *m, float *v, int6
  * luminance moments and propagated with the squared weights; taps outside
  * the image are dropped.  work: device scratch of at least
  * hg_denoise_workspace_size(H, W) bytes, 16-byte aligned; its contents on
- * entry are ignored.  iterations = 0 copies rgb to out. */
+ * entry are ignored.  iterations = 0 copies rgb to out.  Errors
+ * (HG_E_INVALID, nothing launched): NULL pointers, H or W < 1,
+ * H * W >= 2^28, H > 1048560, iterations outside [0, 10], negative or
+ * non-finite sigmas, work_bytes below the workspace size. */
 typedef struct {
     int32_t iterations;
     float sigma_z, sigma_n, sigma_l;

@@ -856,7 +856,7 @@ void or_adam(double *param, const double *grad, double *m, double *v, int64_t n,
 /*  - initial variance: unweighted 7x7 moments, var = E[l^2] - E[l]^2,       */
 /*    over the taps inside the image;                                       */
 /*  - depth gradient: forward differences z(x+1,y)-z(x,y), z(x,y+1)-z(x,y)   */
-/*    (backward at the last column/row);                                    */
+/*    (backward at the last column/row, zero along an axis one pixel long); */
 /*  - iteration k (k = 0..iters-1) uses step 2^k and the 5x5 B3-spline taps  */
 /*    h = (1/16, 1/4, 3/8, 1/4, 1/16); taps outside the image are skipped;  */
 /*  - weights w = h h * exp(-|z_p - z_q| / (sz |grad z_p . (p-q)| + 1e-6))   */
@@ -884,8 +884,8 @@ void or_denoise(const float *rgb, const float *depth, const float *nrm, int32_t 
     for (int y = 0; y < H; ++y)
         for (int x = 0; x < W; ++x) {
             size_t p = (size_t)y * W + x;
-            gx[p] = x + 1 < W ? (double)depth[p + 1] - depth[p] : (double)depth[p] - depth[p - 1];
-            gy[p] = y + 1 < H ? (double)depth[p + W] - depth[p] : (double)depth[p] - depth[p - W];
+            gx[p] = x + 1 < W ? (double)depth[p + 1] - depth[p] : (x > 0 ? (double)depth[p] - depth[p - 1] : 0.0);
+            gy[p] = y + 1 < H ? (double)depth[p + W] - depth[p] : (y > 0 ? (double)depth[p] - depth[p - W] : 0.0);
             double s1 = 0, s2 = 0;
             int cnt = 0;
             for (int dy = -3; dy <= 3; ++dy)

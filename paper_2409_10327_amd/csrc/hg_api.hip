@@ -361,7 +361,8 @@ hg_status hg_denoise(const float *rgb, const float *depth, const float *nrm, int
                      hipStream_t stream) {
     g_err.clear();
     REQUIRE(params != nullptr, "params is NULL");
-    REQUIRE(H >= 1 && W >= 1 && (int64_t)H * W < (int64_t(1) << 28), "image size %dx%d invalid", H, W);
+    REQUIRE(H >= 1 && W >= 1 && (int64_t)H * W < (int64_t(1) << 28) && H <= 65535 * 16,
+            "image size %dx%d invalid", H, W);
     REQUIRE(params->iterations >= 0 && params->iterations <= 10, "iterations = %d outside [0, 10]",
             params->iterations);
     REQUIRE(std::isfinite(params->sigma_z) && std::isfinite(params->sigma_n) && std::isfinite(params->sigma_l) &&

@@ -29,8 +29,10 @@ __global__ __launch_bounds__(kDnBlock * kDnBlock) void k_dn_init(const float *__
     const float r = rgb[3 * p], g = rgb[3 * p + 1], b = rgb[3 * p + 2];
     col[p] = make_float4(r, g, b, luminance(r, g, b));
     const float z = depth[p];
-    const float gx = x + 1 < W ? depth[p + 1] - z : z - depth[p - 1];
-    const float gy = y + 1 < H ? depth[p + W] - z : z - depth[p - W];
+    // forward differences, backward at the last column/row, zero along an
+    // axis that is one pixel long
+    const float gx = x + 1 < W ? depth[p + 1] - z : (x > 0 ? z - depth[p - 1] : 0.0f);
+    const float gy = y + 1 < H ? depth[p + W] - z : (y > 0 ? z - depth[p - W] : 0.0f);
     grad[p] = make_float2(gx, gy);
     float s1 = 0.f, s2 = 0.f;
     int cnt = 0;

@@ -733,3 +733,24 @@ def test_denoise_stops_at_normal_edges():
     depth = np.full((H, W), 2.0, np.float32)
     out = O.denoise(img, depth, nrm)
     assert np.max(np.abs(out - img)) < 1e-12
+
+
+@pytest.mark.parametrize("h,w", [(9, 13), (1, 7), (7, 1)])
+def test_denoise_commutes_with_transpose(h, w):
+    """The B3 footprint, the 3x3 variance blur and the depth-gradient
+    contraction are symmetric in x and y, so filtering the transposed image
+    gives the transposed result (a swapped index or stride breaks this)."""
+    rng = np.random.default_rng(h * 100 + w)
+    img = np.exp(rng.standard_normal((h, w, 3))).astype(np.float32)
+    depth = rng.uniform(1, 3, (h, w)).astype(np.float32)
+    nrm = rand_normals(h * w, 5).reshape(h, w, 3).astype(np.float32)
+    a = O.denoise(img, depth, nrm)
+    b = O.denoise(img.transpose(1, 0, 2), depth.T, nrm.transpose(1, 0, 2))
+    assert np.max(np.abs(a - b.transpose(1, 0, 2))) <= 1e-12 * np.max(np.abs(a))
+
+
+def test_denoise_single_pixel_is_identity():
+    """A 1x1 image has only its own tap (all edge-stopping weights 1)."""
+    img = np.array([[[0.3, 2.0, 7.5]]], np.float32)
+    out = O.denoise(img, np.array([[2.5]], np.float32), np.array([[[0.0, 0.6, 0.8]]], np.float32))
+    assert np.array_equal(out, img.astype(np.float64))
