@@ -45,7 +45,11 @@ def test_encode_features(c1):
     f = hg.encode(c1["r"], c1["t"](pos)).cpu().numpy()
     of = O.encode(c1["om"], pos)
     assert relerr(f, of) < 1e-6
-    assert max_rel(f, of) < 1e-4
+    # element-wise: a feature is a sum of 8 weight products w_k e_k; FP32
+    # weights and accumulation bound its error by a few ulp of max|e|
+    tmax = np.abs(c1["model"]["table"]).max(axis=(1, 2))  # per level
+    bound = 2.0 ** -20 * np.repeat(tmax, 2)[None, :]
+    assert np.all(np.abs(f - of) <= bound), np.max(np.abs(f - of) / bound)
     # exact reproduction at vertices of a level: weights are exactly 0/1
     N = c1["model"]["res"][9]  # 128
     k = np.random.default_rng(3).integers(0, N + 1, (500, 3))

@@ -69,8 +69,11 @@ def test_full_batch_query_sampled(frame, B, precision):
 
 @pytest.mark.parametrize("B", [1 << 18, 1 << 20])
 def test_full_batch_gradients(frame, B):
-    """Full-batch backward = sum of two sub-batch backwards (same kernel, same
-    launch shape), and the first sub-batch matches the oracle."""
+    """Linearity of the full-batch backward in the upstream gradient: the
+    launch with every sample's gradient equals the sum of two launches over
+    the same batch whose upstream gradients are zero outside the first 4096
+    samples and inside them (same launch shape, same sampler point ids); the
+    first part matches the oracle on those 4096 samples."""
     print(f"case: full-batch backward B={B}", flush=True)
     t = frame["t"]
     r = frame["r"]
@@ -80,12 +83,14 @@ def test_full_batch_gradients(frame, B):
     g_vis = (rng.standard_normal(B) / B).astype(np.float32)
     g_dep = (rng.standard_normal(B) / B).astype(np.float32)
     T = lambda a: t(a)
+    env_t, pos_t, dirs_t = T(frame["env"]), T(pos), T(dirs)
     full = hg.zero_grads(r)
-    hg.backward(r, T(frame["env"]), T(pos), T(dirs), T(g_rgb), T(g_vis), T(g_dep), full)
+    hg.backward(r, env_t, pos_t, dirs_t, T(g_rgb), T(g_vis), T(g_dep), full)
     k = 4096
+    head = np.arange(B) < k
     ga, gb = hg.zero_grads(r), hg.zero_grads(r)
-    hg.backward(r, T(frame["env"]), T(pos[:k]), T(dirs[:k]), T(g_rgb[:k]), T(g_vis[:k]), T(g_dep[:k]), ga)
-    hg.backward(r, T(frame["env"]), T(pos[k:]), T(dirs[k:]), T(g_rgb[k:]), T(g_vis[k:]), T(g_dep[k:]), gb)
+    for part, g in ((head, ga), (~head, gb)):
+        hg.backward(r, env_t, pos_t, dirs_t, T(g_rgb * part[:, None]), T(g_vis * part), T(g_dep * part), g)
     tf, ta, tb = [[g["table"]] + g["brdf"] + g["irt"] for g in (full, ga, gb)]
     for a, b, c in zip(tf, ta, tb):
         assert relerr(a.cpu().numpy(), (b + c).cpu().numpy()) < 1e-5

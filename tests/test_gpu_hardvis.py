@@ -69,13 +69,22 @@ def test_hard_shade(c1, N, precision):
     orgb, ovis, _ = O.render(c1["om"], c1["oe"], O.sampling(N, 8, 7, O.HARD_VIS), pos, nrm, wo)
     _, vsoft, _ = O.render(c1["om"], c1["oe"], O.sampling(N, 8, 7, 0), pos, nrm, wo)
     margin = 1e-4 if precision == "fp32" else 2e-2
-    clear_px = np.all(np.abs(vsoft - 0.5) > margin, axis=1)
-    assert np.array_equal(vis[clear_px], ovis[clear_px])
-    ok, e = split_ok(rgb[clear_px], orgb[clear_px], 1e-4 if precision == "fp32" else 2e-2)
-    print(f"hard shade N={N} {precision}: {ok.mean():.4f} of clear pixels agree, rel err {e:.3g}, "
-          f"PSNR all {psnr(rgb, orgb):.1f} dB")
-    assert ok.mean() > (0.98 if precision == "fp32" else 0.9)
-    assert e < (1e-5 if precision == "fp32" else 2e-3)
+    clear = np.abs(vsoft - 0.5) > margin
+    assert np.array_equal(vis[clear], ovis[clear])
+    if precision == "fp32":
+        clear_px = np.all(clear, axis=1)
+        ok, e = split_ok(rgb[clear_px], orgb[clear_px], 1e-4)
+        print(f"hard shade N={N} fp32: {ok.mean():.4f} of clear pixels agree, rel err {e:.3g}, "
+              f"PSNR all {psnr(rgb, orgb):.1f} dB")
+        assert ok.mean() > 0.98
+        assert e < 1e-5
+    else:
+        # over 128 directions almost every pixel has some direction whose BF16
+        # visibility lands within the margin of 0.5, so the mixed bar is the
+        # image-level one (PSNR against the FP64 oracle)
+        p = psnr(rgb, orgb)
+        print(f"hard shade N={N} mixed: {clear.mean():.4f} of directions clear, PSNR {p:.1f} dB")
+        assert p >= 45.0
 
 
 def test_hard_is_deterministic(c1):
