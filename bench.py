@@ -13,6 +13,7 @@ Prints ONE JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -39,7 +40,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--img", type=int, default=800)
     ap.add_argument("--n-dirs", type=int, default=128)
     ap.add_argument("--train-batch", type=int, default=1 << 18)
@@ -47,10 +48,35 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-encode", action="store_true")
-    ap.add_argument("--cpu-stride", type=int, default=8)
+    ap.add_argument("--cpu-stride", type=int, default=3)
+    ap.add_argument("--no-denoise", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
+
+
+def measured_traffic(img, n_dirs):
+    """HBM-side bytes per launch of the headline kernel, from the committed
+    FETCH_SIZE/WRITE_SIZE summary (copy-calibrated); None if the workload
+    differs or the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "k_render_mma_f32_frame800_n128_traffic.txt")
+    if img != 800 or n_dirs != 128 or not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(" "):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        h = hashlib.sha256()
+        for f in kv["kernel_sources"].split():
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest() != kv["source_sha256"]:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, OSError, ValueError):
+        return None
 
 
 def time_events(fn, steps, warmup, torch):
@@ -122,7 +148,8 @@ def main():
     }
     achieved = FLOP_PER_QUERY * S / (ms * 1e-3) / 1e12
     out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                       "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": None,
+                       "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
+                       "traffic": measured_traffic(args.img, cfg.n_dirs),
                        "kernel": "k_render_mma<F32Path, indirect, shade>"}
 
     if args.copy_probe:
@@ -163,6 +190,29 @@ def main():
         mshm, _, _ = time_events(frame_hard("mixed"), args.steps, args.warmup, torch)
         out["hard_visibility"] = {"fp32_ms": msh32, "mixed_ms": mshm,
                                   "fp32_queries_per_s": S / (msh32 * 1e-3), "mixed_queries_per_s": S / (mshm * 1e-3)}
+
+    if not args.no_denoise:
+        # spatial SVGF (5 a-trous iterations) on the FP32 frame, guided by the
+        # primary depth and normals.  Algorithmic bytes per pixel: init 44
+        # (rgb, depth, colour+luminance, variance, depth gradient), each
+        # iteration 64 (colour+luminance, variance, gradient, depth, normal in;
+        # colour+luminance, variance out), 12 for the output colour.
+        frame_fp32()
+        cam = torch.tensor(H.camera(), device=dev, dtype=torch.float64)
+        dmap = torch.linalg.norm(pos_t.double() - cam, dim=1).float().view(cfg.img_h, cfg.img_w)
+        rgb_img, nrm_img = rgb.view(cfg.img_h, cfg.img_w, 3), nrm_t.view(cfg.img_h, cfg.img_w, 3)
+        work = torch.empty(hg.lib().hg_denoise_workspace_size(cfg.img_h, cfg.img_w) // 4, device=dev)
+        its = 5
+
+        def dn():
+            hg.denoise(rgb_img, dmap, nrm_img, iterations=its, work=work)
+        print("[bench] denoise", file=sys.stderr, flush=True)
+        msd, _, _ = time_events(dn, args.steps, args.warmup, torch)
+        alg_d = P * (44 + 64 * its + 12)
+        out["denoise"] = {"ms": msd, "iterations": its, "px_per_s": P / (msd * 1e-3),
+                          "roofline": {"bound": "hbm", "achieved": alg_d / (msd * 1e-3) / 1e9,
+                                       "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                       "frac": alg_d / (msd * 1e-3) / 1e9 / HBM_PEAK_GBS}}
 
     if not args.no_encode:
         # hg_encode gather bandwidth: 2^24 points uniform in the scene's
