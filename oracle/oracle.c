@@ -47,6 +47,7 @@
 
 #define OR_DIFFUSE_ONLY 1u
 #define OR_HARD_VIS 2u     /* binary visibility, bounce only on shadow rays */
+#define OR_MIS 4u          /* primary directions: light + GGX-VNDF rays, balance heuristic */
 
 typedef struct {
     int32_t L, F, log2_T;
@@ -501,6 +502,285 @@ void or_brdf(const double *n, const double *v, const double *l, const double *a,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Multiple importance sampling of the primary directions (Sec. 4.1: one    */
+/* light-importance ray and one GGX ray drawn from the distribution of      */
+/* visible normals per primary point, combined with Veach's balance         */
+/* heuristic).  With n_dirs = 2M, directions k = 0..M-1 are light samples    */
+/* and k = M..2M-1 GGX samples; each strategy stratifies its M samples like  */
+/* the cosine sampler.  Sample i carries the weight                          */
+/*   c_i = 2 f_r(w_i) (n.w_i) / (p_env(w_i) + p_ggx(w_i))                    */
+/* so that L_o = 1/N sum_i c_i L_in(w_i) is the balance-heuristic estimator  */
+/* with M samples per strategy.                                              */
+/*                                                                          */
+/* Light distribution (reading): piecewise constant in solid angle over the */
+/* equirectangular texels.  Texel (y, x) spans theta in [pi y/H, pi(y+1)/H] */
+/* and phi in [-pi + 2 pi x/W, -pi + 2 pi (x+1)/W] (the lookup's texel       */
+/* centres); its probability is proportional to its luminance times its     */
+/* solid angle (2 pi/W)(cos theta_y - cos theta_{y+1}); inside the texel the */
+/* direction is uniform in solid angle.  The density is therefore           */
+/* lum(texel) / sum_texels lum * solid angle.  An all-black map falls back  */
+/* to the uniform sphere; a black row samples its columns uniformly (it is  */
+/* never chosen).  Rows and columns are found by inverting the marginal and */
+/* conditional CDFs with the two uniforms of the sample (continuous         */
+/* inversion: the offset inside the chosen interval places the direction    */
+/* inside the texel).  Uniforms: Philox counter (pid, 0, k >> 2, tag) with   */
+/* tag 2 for light and 3 for GGX samples, 16-bit halves at bin centres.     */
+/*                                                                          */
+/* GGX visible-normal sampling: Heitz, "Sampling the GGX Distribution of    */
+/* Visible Normals", JCGT 2018, with alpha = r^2 (the BRDF's alpha).  The    */
+/* view is taken in the normal's frame with its normal component clamped to */
+/* 1e-4 and renormalised (v_s); the reflected direction has the density     */
+/*   p_ggx(l) = G1(v_s) D(h) / (4 n.v_s),  h = normalize(v_s + l),           */
+/* for v_s.h > 0 and n.h > 0 (0 otherwise),                                */
+/* G1(v) = 2 n.v / (n.v + sqrt(a2 + (1 - a2)(n.v)^2)).                      */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int H, W;
+    double *ct;   /* [H+1] cos(pi y / H) */
+    double *marg; /* [H+1] marginal CDF over rows */
+    double *cond; /* [H][W+1] conditional CDF over the columns of each row */
+    double *dens; /* [H][W] solid-angle density of each texel */
+} env_dist;
+
+static void env_dist_build(const or_env *E, env_dist *D)
+{
+    const int H = E->H, W = E->W;
+    D->H = H;
+    D->W = W;
+    D->ct = (double *)malloc((size_t)(H + 1) * sizeof(double));
+    D->marg = (double *)malloc((size_t)(H + 1) * sizeof(double));
+    D->cond = (double *)malloc((size_t)H * (W + 1) * sizeof(double));
+    D->dens = (double *)malloc((size_t)H * W * sizeof(double));
+    double *wt = (double *)malloc((size_t)H * W * sizeof(double));
+    double *row = (double *)malloc((size_t)H * sizeof(double));
+    for (int y = 0; y <= H; ++y) D->ct[y] = cos(M_PI * y / H);
+    double total = 0.0;
+    for (int y = 0; y < H; ++y) {
+        const double omega = 2.0 * M_PI / W * (D->ct[y] - D->ct[y + 1]);
+        for (int x = 0; x < W; ++x) {
+            const float *t = E->rgb + ((size_t)y * W + x) * 3;
+            wt[y * W + x] = (0.2126 * t[0] + 0.7152 * t[1] + 0.0722 * t[2]) * omega;
+        }
+    }
+    for (int i = 0; i < H * W; ++i) total += wt[i];
+    const int uniform = !(total > 0.0);
+    if (uniform) {
+        total = 0.0;
+        for (int y = 0; y < H; ++y)
+            for (int x = 0; x < W; ++x) wt[y * W + x] = 2.0 * M_PI / W * (D->ct[y] - D->ct[y + 1]);
+        for (int i = 0; i < H * W; ++i) total += wt[i];
+    }
+    for (int y = 0; y < H; ++y) {
+        double *c = D->cond + (size_t)y * (W + 1);
+        double r = 0.0;
+        for (int x = 0; x < W; ++x) r += wt[y * W + x];
+        row[y] = r;
+        c[0] = 0.0;
+        double acc = 0.0;
+        for (int x = 0; x < W; ++x) {
+            acc += wt[y * W + x];
+            c[x + 1] = r > 0.0 ? acc / r : (double)(x + 1) / W;
+        }
+        c[W] = 1.0;
+        const double omega = 2.0 * M_PI / W * (D->ct[y] - D->ct[y + 1]);
+        for (int x = 0; x < W; ++x) D->dens[y * W + x] = wt[y * W + x] / total / omega;
+    }
+    D->marg[0] = 0.0;
+    double acc = 0.0;
+    for (int y = 0; y < H; ++y) {
+        acc += row[y];
+        D->marg[y + 1] = acc / total;
+    }
+    D->marg[H] = 1.0;
+    free(wt);
+    free(row);
+}
+
+static void env_dist_free(env_dist *D)
+{
+    free(D->ct);
+    free(D->marg);
+    free(D->cond);
+    free(D->dens);
+}
+
+/* largest i in [0, n-1] with c[i] <= u, for a nondecreasing c[0..n] */
+static int cdf_find(const double *c, int n, double u)
+{
+    int i = 0;
+    for (int k = 1; k < n; ++k)
+        if (c[k] <= u) i = k;
+    return i;
+}
+
+static double env_density(const env_dist *D, const double w[3])
+{
+    double phi = atan2(w[2], w[0]);
+    double th = atan2(sqrt(w[0] * w[0] + w[2] * w[2]), w[1]);
+    int x = (int)floor((phi + M_PI) / (2.0 * M_PI) * D->W);
+    int y = (int)floor(th / M_PI * D->H);
+    x = x < 0 ? 0 : (x >= D->W ? D->W - 1 : x);
+    y = y < 0 ? 0 : (y >= D->H ? D->H - 1 : y);
+    return D->dens[y * D->W + x];
+}
+
+/* light sample from the stratified uniforms (s1, s2); returns its density */
+static double env_sample(const env_dist *D, double s1, double s2, double w[3])
+{
+    const int H = D->H, W = D->W;
+    int y = cdf_find(D->marg, H, s1);
+    double fv = (s1 - D->marg[y]) / (D->marg[y + 1] - D->marg[y]);
+    const double *c = D->cond + (size_t)y * (W + 1);
+    int x = cdf_find(c, W, s2);
+    double fu = (s2 - c[x]) / (c[x + 1] - c[x]);
+    double cth = D->ct[y] - fv * (D->ct[y] - D->ct[y + 1]);
+    double sth = sqrt((1.0 - cth) * (1.0 + cth));
+    double phi = -M_PI + 2.0 * M_PI * (x + fu) / W;
+    w[0] = sth * cos(phi);
+    w[1] = cth;
+    w[2] = sth * sin(phi);
+    return D->dens[y * W + x];
+}
+
+static double ggx_g1(double nv, double a2) { return 2.0 * nv / (nv + sqrt(a2 + (1.0 - a2) * nv * nv)); }
+
+/* view in the normal's frame (t, b, n), normal component clamped, unit */
+static void ggx_view(const double n[3], const double v[3], double vl[3], double t[3], double b[3])
+{
+    onb(n, t, b);
+    vl[0] = dot3(v, t);
+    vl[1] = dot3(v, b);
+    vl[2] = dot3(v, n);
+    if (vl[2] < 1e-4) vl[2] = 1e-4;
+    double s = sqrt(dot3(vl, vl));
+    for (int d = 0; d < 3; ++d) vl[d] /= s;
+}
+
+static double ggx_density(const double n[3], const double v[3], double r, const double l[3])
+{
+    double vl[3], t[3], b[3];
+    ggx_view(n, v, vl, t, b);
+    double ll[3] = {dot3(l, t), dot3(l, b), dot3(l, n)};
+    double h[3] = {vl[0] + ll[0], vl[1] + ll[1], vl[2] + ll[2]};
+    double hn = sqrt(dot3(h, h));
+    if (!(hn > 0.0)) return 0.0;
+    for (int d = 0; d < 3; ++d) h[d] /= hn;
+    double vh = dot3(vl, h);
+    if (!(vh > 0.0)) return 0.0;
+    double nh = h[2];
+    if (!(nh > 0.0)) return 0.0; /* microfacet normals lie above the surface */
+    double alpha = r * r, a2 = alpha * alpha;
+    double Q = nh * nh * (a2 - 1.0) + 1.0;
+    double Dh = a2 / (M_PI * Q * Q);
+    return ggx_g1(vl[2], a2) * Dh / (4.0 * vl[2]);
+}
+
+static void ggx_sample(const double n[3], const double v[3], double r, double s1, double s2, double l[3])
+{
+    double vl[3], t[3], b[3];
+    ggx_view(n, v, vl, t, b);
+    const double alpha = r * r;
+    double vh[3] = {alpha * vl[0], alpha * vl[1], vl[2]};
+    double s = sqrt(dot3(vh, vh));
+    for (int d = 0; d < 3; ++d) vh[d] /= s;
+    double lensq = vh[0] * vh[0] + vh[1] * vh[1];
+    double T1[3], T2[3];
+    if (lensq > 0.0) {
+        double il = 1.0 / sqrt(lensq);
+        T1[0] = -vh[1] * il; T1[1] = vh[0] * il; T1[2] = 0.0;
+    } else {
+        T1[0] = 1.0; T1[1] = 0.0; T1[2] = 0.0;
+    }
+    T2[0] = vh[1] * T1[2] - vh[2] * T1[1];
+    T2[1] = vh[2] * T1[0] - vh[0] * T1[2];
+    T2[2] = vh[0] * T1[1] - vh[1] * T1[0];
+    double rr = sqrt(s1), ph = 2.0 * M_PI * s2;
+    double t1 = rr * cos(ph), t2 = rr * sin(ph);
+    double sv = 0.5 * (1.0 + vh[2]);
+    t2 = (1.0 - sv) * sqrt(1.0 - t1 * t1) + sv * t2;
+    double tz = 1.0 - t1 * t1 - t2 * t2;
+    tz = tz > 0.0 ? sqrt(tz) : 0.0;
+    double nh[3];
+    for (int d = 0; d < 3; ++d) nh[d] = t1 * T1[d] + t2 * T2[d] + tz * vh[d];
+    double ne[3] = {alpha * nh[0], alpha * nh[1], nh[2] > 0.0 ? nh[2] : 0.0};
+    double en = sqrt(dot3(ne, ne));
+    for (int d = 0; d < 3; ++d) ne[d] /= en;
+    double vn = dot3(vl, ne);
+    double ll[3];
+    for (int d = 0; d < 3; ++d) ll[d] = 2.0 * vn * ne[d] - vl[d];
+    for (int d = 0; d < 3; ++d) l[d] = ll[0] * t[d] + ll[1] * b[d] + ll[2] * n[d];
+}
+
+/* stratified uniforms of sample k out of M (same strata as the cosine sampler) */
+static void strat_uniforms(uint64_t seed, uint32_t pid, uint32_t k, uint32_t tag, int M, double *s1, double *s2)
+{
+    double u1, u2;
+    uniforms(seed, pid, 0u, k, tag, &u1, &u2);
+    int na = 1 << (ilog2(M) / 2);
+    int nb = M / na;
+    *s1 = ((int)k / nb + u1) / na;
+    *s2 = ((int)k % nb + u2) / nb;
+}
+
+/* direction i of a primary point under MIS: returns w and the scalar
+   2 (n.w) / (p_env + p_ggx) that multiplies f_r (0 below the horizon, and 0
+   in the measure-zero case where both densities vanish) */
+static double mis_direction(const env_dist *D, const or_sampling *S, uint32_t pid, int i, const double n[3],
+                            const double v[3], double r, double w[3])
+{
+    const int M = S->n_dirs / 2;
+    double s1, s2;
+    if (i < M) {
+        strat_uniforms(S->seed, pid, (uint32_t)i, 2u, M, &s1, &s2);
+        double pe = env_sample(D, s1, s2, w);
+        double nl = dot3(n, w), den = pe + ggx_density(n, v, r, w);
+        return (nl > 0.0 && den > 0.0) ? 2.0 * nl / den : 0.0;
+    }
+    strat_uniforms(S->seed, pid, (uint32_t)(i - M), 3u, M, &s1, &s2);
+    ggx_sample(n, v, r, s1, s2, w);
+    double nl = dot3(n, w), den = env_density(D, w) + ggx_density(n, v, r, w);
+    return (nl > 0.0 && den > 0.0) ? 2.0 * nl / den : 0.0;
+}
+
+void or_env_dist(const or_env *E, double *ct, double *marg, double *cond, double *dens)
+{
+    env_dist D;
+    env_dist_build(E, &D);
+    const int H = E->H, W = E->W;
+    memcpy(ct, D.ct, (size_t)(H + 1) * sizeof(double));
+    memcpy(marg, D.marg, (size_t)(H + 1) * sizeof(double));
+    memcpy(cond, D.cond, (size_t)H * (W + 1) * sizeof(double));
+    memcpy(dens, D.dens, (size_t)H * W * sizeof(double));
+    env_dist_free(&D);
+}
+
+void or_env_sample(const or_env *E, const double *s, int64_t n, double *w, double *pdf)
+{
+    env_dist D;
+    env_dist_build(E, &D);
+    for (int64_t i = 0; i < n; ++i) pdf[i] = env_sample(&D, s[2 * i], s[2 * i + 1], w + 3 * i);
+    env_dist_free(&D);
+}
+
+void or_env_density(const or_env *E, const double *w, int64_t n, double *pdf)
+{
+    env_dist D;
+    env_dist_build(E, &D);
+    for (int64_t i = 0; i < n; ++i) pdf[i] = env_density(&D, w + 3 * i);
+    env_dist_free(&D);
+}
+
+void or_ggx_sample(const double *n, const double *v, const double *r, const double *s, int64_t cnt, double *l)
+{
+    for (int64_t i = 0; i < cnt; ++i) ggx_sample(n + 3 * i, v + 3 * i, r[i], s[2 * i], s[2 * i + 1], l + 3 * i);
+}
+
+void or_ggx_density(const double *n, const double *v, const double *r, const double *l, int64_t cnt, double *pdf)
+{
+    for (int64_t i = 0; i < cnt; ++i) pdf[i] = ggx_density(n + 3 * i, v + 3 * i, r[i], l + 3 * i);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Incoming radiance along (x, w): Eq. (2).                                 */
 /*   V, d from I(f(x), w); x' = x + t w (Sec. 3.1).                          */
 /*   Bounce (Sec. 3.2 "Overview"): f' = H(x'), (a', r', m') = B(f'), N'     */
@@ -571,6 +851,7 @@ static void incoming(const or_model *M, const or_env *E, const or_sampling *S, i
 /* Shade mode (P->dir == NULL): Eq. (1) at each primary point with N        */
 /* cosine-distributed directions; with pdf = cos/pi every sample carries    */
 /* the weight pi f_r.  (a, r, m) = B(H(x)), normal and view from the input. */
+/* With OR_MIS the N directions and their weights come from mis_direction. */
 /*   rgb[p] = 1/N sum_i pi f_r(n, w_o, w_i) L_in(x, w_i);                    */
 /*   vis/depth (optional) [p][N] hold V and d of each direction.            */
 /* Query mode (P->dir != NULL): rgb[p] = L_in(x_p, dir_p), vis[p] = V,       */
@@ -582,6 +863,9 @@ void or_render(const or_model *M, const or_env *E, const or_sampling *S, const o
     const or_grid *g = &M->grid;
     const int nf = g->L * g->F;
     const int query = P->dir != NULL;
+    const int mis = !query && (S->flags & OR_MIS) != 0;
+    env_dist D;
+    if (mis) env_dist_build(E, &D);
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t p = 0; p < P->n; ++p) {
         double f[OR_MAXF], u[3];
@@ -608,15 +892,20 @@ void or_render(const or_model *M, const or_env *E, const or_sampling *S, const o
         const int N = S->n_dirs;
         for (int i = 0; i < N; ++i) {
             double w[3], Lin[3], V, d, fr[3], t1[3], t2[3], t3[3];
-            sample_dir(S->seed, point_id(P, p), 0u, (uint32_t)i, 0u, N, n, w);
+            double wt = M_PI; /* cosine sampling: pi f_r per sample */
+            if (mis)
+                wt = mis_direction(&D, S, point_id(P, p), i, n, v, r, w);
+            else
+                sample_dir(S->seed, point_id(P, p), 0u, (uint32_t)i, 0u, N, n, w);
             incoming(M, E, S, indirect, f, x, w, point_id(P, p), (uint32_t)i, Lin, &V, &d);
             brdf_eval(n, v, w, a, r, m, M->f0, (S->flags & OR_DIFFUSE_ONLY) != 0, fr, t1, t2, t3);
-            for (int c = 0; c < 3; ++c) Lo[c] += M_PI * fr[c] * Lin[c];
+            for (int c = 0; c < 3; ++c) Lo[c] += wt * fr[c] * Lin[c];
             if (vis) vis[p * N + i] = V;
             if (depth) depth[p * N + i] = d;
         }
         for (int c = 0; c < 3; ++c) rgb[3 * p + c] = Lo[c] / N;
     }
+    if (mis) env_dist_free(&D);
     (void)nf;
 }
 

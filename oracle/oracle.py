@@ -22,6 +22,7 @@ GCC_FLAGS = ["-O2", "-fopenmp", "-ffp-contract=off", "-std=c11", "-Wall", "-shar
 
 DIFFUSE_ONLY = 1
 HARD_VIS = 2
+MIS = 4
 
 
 def build(force: bool = True) -> str:
@@ -218,6 +219,48 @@ def env_lookup(oe: OracleEnv, dirs):
     dirs = _f64(dirs)
     out = np.empty_like(dirs)
     lib().or_env_lookup(C.byref(oe.c), _p(dirs), C.c_int64(dirs.shape[0]), _p(out))
+    return out
+
+
+def env_dist(oe: OracleEnv):
+    """Light-sampling distribution of an environment map: (cos theta at the
+    row edges [H+1], marginal CDF [H+1], conditional CDFs [H][W+1], texel
+    solid-angle densities [H][W])."""
+    H, W = oe.c.H, oe.c.W
+    ct, marg = np.empty(H + 1), np.empty(H + 1)
+    cond, dens = np.empty((H, W + 1)), np.empty((H, W))
+    lib().or_env_dist(C.byref(oe.c), _p(ct), _p(marg), _p(cond), _p(dens))
+    return ct, marg, cond, dens
+
+
+def env_sample(oe: OracleEnv, s):
+    """Light samples for uniforms s [n][2] in (0,1): directions [n][3], densities [n]."""
+    s = _f64(s)
+    n = s.shape[0]
+    w, pdf = np.empty((n, 3)), np.empty(n)
+    lib().or_env_sample(C.byref(oe.c), _p(s), C.c_int64(n), _p(w), _p(pdf))
+    return w, pdf
+
+
+def env_density(oe: OracleEnv, w):
+    w = _f64(w)
+    pdf = np.empty(w.shape[0])
+    lib().or_env_density(C.byref(oe.c), _p(w), C.c_int64(w.shape[0]), _p(pdf))
+    return pdf
+
+
+def ggx_sample(n, v, r, s):
+    """GGX visible-normal samples: reflected directions [cnt][3]."""
+    n, v, r, s = _f64(n), _f64(v), _f64(r), _f64(s)
+    out = np.empty((n.shape[0], 3))
+    lib().or_ggx_sample(_p(n), _p(v), _p(r), _p(s), C.c_int64(n.shape[0]), _p(out))
+    return out
+
+
+def ggx_density(n, v, r, l):
+    n, v, r, l = _f64(n), _f64(v), _f64(r), _f64(l)
+    out = np.empty(n.shape[0])
+    lib().or_ggx_density(_p(n), _p(v), _p(r), _p(l), C.c_int64(n.shape[0]), _p(out))
     return out
 
 

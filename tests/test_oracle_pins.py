@@ -754,3 +754,141 @@ def test_denoise_single_pixel_is_identity():
     img = np.array([[[0.3, 2.0, 7.5]]], np.float32)
     out = O.denoise(img, np.array([[2.5]], np.float32), np.array([[[0.0, 0.6, 0.8]]], np.float32))
     assert np.array_equal(out, img.astype(np.float64))
+
+
+# --------------------------------------------------- multiple importance sampling --
+def _sphere_grid(nt, npp):
+    th = (np.arange(nt) + 0.5) / nt * np.pi
+    ph = (np.arange(npp) + 0.5) / npp * 2 * np.pi - np.pi
+    TH, PH = np.meshgrid(th, ph, indexing="ij")
+    d = np.stack([np.sin(TH) * np.cos(PH), np.cos(TH), np.sin(TH) * np.sin(PH)], -1).reshape(-1, 3)
+    dw = (np.pi / nt) * (2 * np.pi / npp) * np.sin(TH).ravel()
+    return d, dw
+
+
+def _grid_uniforms(k):
+    u = (np.arange(k) + 0.5) / k
+    U1, U2 = np.meshgrid(u, u, indexing="ij")
+    return np.stack([U1.ravel(), U2.ravel()], 1)
+
+
+def test_env_sampling_of_a_constant_map_is_the_uniform_sphere():
+    """Equal texels: every texel's probability is its solid angle, so the
+    CDF inversion is linear in cos(theta) and phi: w_y = 1 - 2 s1 and
+    phi = -pi + 2 pi s2 exactly, with density 1/(4 pi)."""
+    oe = O.OracleEnv(np.full((8, 16, 3), 2.5, np.float32))
+    s = np.random.default_rng(0).uniform(0, 1, (2000, 2))
+    w, pdf = O.env_sample(oe, s)
+    assert np.allclose(w[:, 1], 1 - 2 * s[:, 0], rtol=0, atol=1e-12)
+    assert np.allclose(np.arctan2(w[:, 2], w[:, 0]), -np.pi + 2 * np.pi * s[:, 1], rtol=0, atol=1e-11)
+    assert np.allclose(np.linalg.norm(w, axis=1), 1, atol=1e-14)
+    assert np.allclose(pdf, 1 / (4 * np.pi), rtol=1e-12)
+    # an all-black map falls back to the same uniform distribution
+    w0, pdf0 = O.env_sample(O.OracleEnv(np.zeros((8, 16, 3), np.float32)), s)
+    assert np.allclose(w0, w, atol=1e-12) and np.allclose(pdf0, pdf, rtol=1e-12)
+
+
+def test_env_density_is_normalised_and_matches_the_sampler():
+    """Density of a random map (sun lobe included) integrates to 1 over the
+    sphere (fine quadrature); a regular grid of uniforms lands in every
+    texel in proportion to that texel's probability, and the density the
+    sampler returns equals the density looked up at the direction."""
+    Hh, Ww = 8, 16
+    oe = O.OracleEnv(H.make_env(Hh, Ww, seed=12))
+    d, dw = _sphere_grid(1600, 3200)
+    assert abs(np.sum(O.env_density(oe, d) * dw) - 1) < 2e-3
+    s = _grid_uniforms(1024)
+    w, pdf = O.env_sample(oe, s)
+    ct, marg, cond, dens = O.env_dist(oe)
+    th = np.arccos(np.clip(w[:, 1], -1, 1))
+    phi = np.arctan2(w[:, 2], w[:, 0])
+    y = np.clip(np.floor(th / np.pi * Hh).astype(int), 0, Hh - 1)
+    x = np.clip(np.floor((phi + np.pi) / (2 * np.pi) * Ww).astype(int), 0, Ww - 1)
+    freq = np.bincount(y * Ww + x, minlength=Hh * Ww) / len(s)
+    omega = (2 * np.pi / Ww) * (ct[:-1] - ct[1:])
+    prob = (dens * omega[:, None]).ravel()
+    assert abs(prob.sum() - 1) < 1e-12
+    assert np.max(np.abs(freq - prob)) < 4 / 1024
+    inside = (np.abs(th / np.pi * Hh - np.round(th / np.pi * Hh)) > 1e-6) & \
+             (np.abs((phi + np.pi) / (2 * np.pi) * Ww - np.round((phi + np.pi) / (2 * np.pi) * Ww)) > 1e-6)
+    assert np.allclose(pdf[inside], O.env_density(oe, w[inside]), rtol=1e-12)
+
+
+def test_vndf_at_normal_incidence_with_alpha_one_is_uniform():
+    """alpha = 1 and v = n: the visible normals are cosine distributed and
+    their reflections cover the sphere uniformly: l_z = 1 - 2 s1, azimuth
+    2 pi s2 (in the normal's frame), density 1/(4 pi) everywhere."""
+    k = 500
+    s = np.random.default_rng(1).uniform(0, 1, (k, 2))
+    n = np.tile([0.0, 0.0, 1.0], (k, 1))
+    l = O.ggx_sample(n, n, np.ones(k), s)
+    assert np.allclose(l[:, 2], 1 - 2 * s[:, 0], atol=1e-12)
+    az = np.mod(np.arctan2(l[:, 1], l[:, 0]), 2 * np.pi)
+    assert np.allclose(np.cos(az - 2 * np.pi * s[:, 1]), 1, atol=1e-10)
+    d, _ = _sphere_grid(40, 80)
+    nn = np.tile([0.0, 0.0, 1.0], (len(d), 1))
+    assert np.allclose(O.ggx_density(nn, nn, np.ones(len(d)), d), 1 / (4 * np.pi), rtol=1e-12)
+
+
+@pytest.mark.parametrize("r,vdeg", [(0.5, 0.0), (0.7, 50.0), (0.9, 80.0), (1.0, 30.0)])
+def test_vndf_density_is_normalised_and_matches_the_sampler(r, vdeg):
+    """The reflected-direction density integrates to one over the sphere,
+    and the expectations of test functions under the sampler (regular grid
+    of uniforms) equal their integrals against the density."""
+    nrm = np.array([0.0, 0.6, 0.8])
+    t = np.array([1.0, 0.0, 0.0])
+    a = math.radians(vdeg)
+    v = math.cos(a) * nrm + math.sin(a) * t
+    d, dw = _sphere_grid(1600, 3200)
+    cnt = len(d)
+    pdf = O.ggx_density(np.tile(nrm, (cnt, 1)), np.tile(v, (cnt, 1)), np.full(cnt, r), d)
+    assert abs(np.sum(pdf * dw) - 1) < 2e-3
+    s = _grid_uniforms(512)
+    k = len(s)
+    l = O.ggx_sample(np.tile(nrm, (k, 1)), np.tile(v, (k, 1)), np.full(k, r), s)
+    assert np.allclose(np.linalg.norm(l, axis=1), 1, atol=1e-12)
+    for g in (lambda q: q @ nrm, lambda q: (q @ t) ** 2, lambda q: (q @ v > 0.9).astype(float)):
+        assert abs(np.mean(g(l)) - np.sum(g(d) * pdf * dw)) < 3e-3
+
+
+def test_mis_estimate_converges_to_the_rendering_integral():
+    """V = 1, specular metallic BRDF under the sun-lobe environment: the
+    balance-heuristic estimator (light + GGX rays) converges to the
+    quadrature of f_r L cos over the hemisphere (8 replicas, within 4
+    standard errors).  A sampler that disagreed with its own density would
+    bias it."""
+    Hh, Ww = 16, 32
+    env = H.make_env(Hh, Ww, seed=10)
+    oe = O.OracleEnv(env)
+    rr_logit, mm_logit = logit((0.45 - 0.09) / 0.91), logit(0.6)
+    m = small_model()
+    m["brdf"] = const_mlp(8, 5, [logit(0.3), logit(0.6), logit(0.9), rr_logit, mm_logit])
+    m["irt"] = const_mlp(11, 2, [40.0, 0.0])
+    om = O.OracleModel(m, LO, EXT)
+    normals = np.array([[0, 1, 0], [0.6, 0.8, 0], [0.48, 0.6, 0.64]], np.float64)
+    normals /= np.linalg.norm(normals, axis=1, keepdims=True)
+    views = np.array([[0.3, 0.9, 0.3], [0.0, 1.0, 0.0], [-0.2, 0.5, 0.84]], np.float64)
+    views /= np.linalg.norm(views, axis=1, keepdims=True)
+    pos = np.zeros((3, 3), np.float32)
+    reps = []
+    for seed in range(8):
+        s = O.sampling(2 * 4096, 8, 200 + seed, O.MIS)
+        reps.append(O.render(om, oe, s, pos, normals.astype(np.float32), views.astype(np.float32),
+                             indirect=False, want_vis=False)[0])
+    reps = np.array(reps)
+    mean, sem = reps.mean(0), reps.std(0, ddof=1) / math.sqrt(len(reps))
+    d, dw = _sphere_grid(1600, 3200)
+    Ld = O.env_lookup(oe, d)
+    sig = lambda z: 1 / (1 + math.exp(-float(np.float32(z))))
+    alb = np.array([sig(logit(0.3)), sig(logit(0.6)), sig(logit(0.9))])
+    rough, metal = 0.09 + 0.91 * sig(rr_logit), sig(mm_logit)
+    for p in range(3):
+        n32, v32 = normals[p].astype(np.float32).astype(np.float64), views[p].astype(np.float32).astype(np.float64)
+        cnt = len(d)
+        f = O.brdf(np.tile(n32, (cnt, 1)), np.tile(v32, (cnt, 1)), d, np.tile(alb, (cnt, 1)),
+                   np.full(cnt, rough), np.full(cnt, metal))
+        f = f[0] if isinstance(f, tuple) else f
+        cos = np.maximum(d @ n32, 0)
+        ref = (f * Ld * (cos * dw)[:, None]).sum(0)
+        assert np.all(np.abs(mean[p] - ref) <= 4 * sem[p] + 2e-3 * ref), (p, mean[p], sem[p], ref)
+        assert np.all(sem[p] < 2e-2 * ref)
