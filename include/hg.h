@@ -59,6 +59,9 @@ typedef enum { HG_F32 = 0, HG_F16 = 1, HG_BF16 = 2 } hg_dtype;
 #define HG_HARD_VIS 2u     /* binary visibility v = [o0 > 0]; the bounce runs only for shadow
                               rays and sums visible secondary rays only (Sec. 3.2 "Overview");
                               forward only */
+#define HG_MIS 4u          /* shade mode: the n_dirs = 2M primary directions are M light-importance
+                              rays and M GGX visible-normal rays, weighted by the balance heuristic
+                              (Sec. 4.1); needs hg_env.dist; forward only */
 
 /* Multi-resolution hash grid (Sec. 3.2, InstantNGP layout).
  * table: [L][T][F], T = 2^log2_T, entries FP32 or FP16.
@@ -100,17 +103,44 @@ typedef struct {
 
 /* Equirectangular HDR map [H][W][3] FP32; y is up, row 0 at the zenith,
  * azimuth atan2(w_z, w_x) from -pi at column 0; bilinear lookup at texel
- * centres, columns wrap, rows clamp (Sec. 2.2, image-based lighting). */
+ * centres, columns wrap, rows clamp (Sec. 2.2, image-based lighting).
+ * dist: the map's light-sampling distribution written by
+ * hg_env_build_sampling (device memory); read only under HG_MIS, may be NULL
+ * otherwise. */
 typedef struct {
     int32_t H, W;
     const float *rgb;
+    const void *dist;
 } hg_env;
+
+/* Light-importance distribution of an environment map for HG_MIS (Sec. 4.1:
+ * one light-importance ray per primary point).  Piecewise constant in solid
+ * angle: texel (y, x) covers theta in [pi y/H, pi (y+1)/H] and phi in
+ * [-pi + 2 pi x/W, -pi + 2 pi (x+1)/W]; its probability is proportional to
+ * its Rec. 709 luminance times its solid angle, and inside a texel the
+ * direction is uniform in solid angle.  An all-black map gives the uniform
+ * sphere.  The distribution holds (8-byte aligned) cos(theta) at the row
+ * edges [H+1] and the marginal CDF [H+1] and conditional CDFs [H][W+1] in
+ * FP64, then the texel densities (per steradian) [H][W] in FP32;
+ * hg_env_sampling_size(H, W) bytes.  Building it reads env->rgb on `stream`
+ * and writes `dist`; it must be rebuilt when the map changes.
+ * Errors (HG_E_INVALID, nothing launched): NULL pointers, H or W < 1 or
+ * above 8192, dist not 8-byte aligned, bytes too small. */
+size_t hg_env_sampling_size(int32_t H, int32_t W);
+hg_status hg_env_build_sampling(const hg_env *env, void *dist, size_t bytes, hipStream_t stream);
 
 /* Light sampling: n_dirs stratified cosine-weighted directions per primary
  * point and n_dirs2 per secondary point (8 in the paper's renderer,
  * supplementary "Rendering Details").  The uniforms come from
  * Philox4x32-10 (key = seed, counter = (point, primary direction index or 0,
- * sample >> 2, 0 primary / 1 secondary), 16-bit halves of word sample & 3). */
+ * sample >> 2, 0 primary / 1 secondary), 16-bit halves of word sample & 3).
+ * Under HG_MIS, primary direction i < M is light sample k = i (counter tag
+ * 2) and direction i >= M GGX sample k = i - M (tag 3), each strategy
+ * stratified over its M samples like the cosine sampler; direction i
+ * carries the weight 2 f_r (n.w_i) / (p_env(w_i) + p_ggx(w_i)) in place of
+ * pi f_r.  The GGX rays sample the visible normals of the decoder's
+ * roughness (alpha = r^2; Heitz, JCGT 2018) for the view w_o with its
+ * normal component clamped to 1e-4. */
 typedef struct {
     int32_t n_dirs, n_dirs2;
     uint64_t seed;

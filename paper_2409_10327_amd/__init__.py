@@ -19,6 +19,7 @@ HG_OK, HG_E_INVALID, HG_E_UNSUPPORTED, HG_E_WORKSPACE, HG_E_HIP = range(5)
 HG_F32, HG_F16, HG_BF16 = 0, 1, 2
 HG_DIFFUSE_ONLY = 1
 HG_HARD_VIS = 2
+HG_MIS = 4
 
 BOX_LO = -8.0
 BOX_EXTENT = 16.0
@@ -46,7 +47,7 @@ class Model(C.Structure):
 
 
 class Env(C.Structure):
-    _fields_ = [("H", C.c_int32), ("W", C.c_int32), ("rgb", C.c_void_p)]
+    _fields_ = [("H", C.c_int32), ("W", C.c_int32), ("rgb", C.c_void_p), ("dist", C.c_void_p)]
 
 
 class Sampling(C.Structure):
@@ -63,7 +64,8 @@ class Points(C.Structure):
 
 
 EXPORTS = ["hg_encode", "hg_encode_index", "hg_render_direct", "hg_render_indirect", "hg_backward", "hg_l2_loss",
-           "hg_adam_step", "hg_denoise", "hg_denoise_workspace_size", "hg_last_error"]
+           "hg_adam_step", "hg_denoise", "hg_denoise_workspace_size", "hg_env_build_sampling",
+           "hg_env_sampling_size", "hg_last_error"]
 
 _lib = None
 
@@ -78,6 +80,9 @@ def lib():
         L.hg_last_error.restype = C.c_char_p
         for name in EXPORTS[:-1]:
             getattr(L, name).restype = C.c_int
+        L.hg_env_sampling_size.restype = C.c_size_t
+        L.hg_env_sampling_size.argtypes = [C.c_int32, C.c_int32]
+        L.hg_env_build_sampling.argtypes = [C.POINTER(Env), C.c_void_p, C.c_size_t, C.c_void_p]
         L.hg_denoise_workspace_size.restype = C.c_size_t
         L.hg_denoise_workspace_size.argtypes = [C.c_int32, C.c_int32]
         L.hg_denoise.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.POINTER(DenoiseParams),
@@ -194,11 +199,25 @@ class HashRenderer:
         return m
 
 
-def env_struct(env: torch.Tensor):
+def env_struct(env: torch.Tensor, dist: torch.Tensor | None = None):
     e = Env()
     e.H, e.W = env.shape[0], env.shape[1]
     e.rgb = env.data_ptr()
+    e.dist = None if dist is None else dist.data_ptr()
     return e
+
+
+def env_sampling(env: torch.Tensor) -> torch.Tensor:
+    """Light-importance distribution of an environment map [H,W,3] (needed
+    by flags=HG_MIS); an opaque FP64 device buffer."""
+    H, W = env.shape[0], env.shape[1]
+    nbytes = lib().hg_env_sampling_size(H, W)
+    if nbytes == 0:
+        raise HGError(HG_E_INVALID, f"environment map {H}x{W} is outside [1, 8192]^2")
+    dist = torch.empty((nbytes + 7) // 8, device=env.device, dtype=torch.float64)
+    _check(lib().hg_env_build_sampling(C.byref(env_struct(env)), _ptr(dist), dist.numel() * 8,
+                                       _stream(env.device)))
+    return dist
 
 
 def sampling_struct(n_dirs=1, n_dirs2=8, seed=7, flags=0):
@@ -244,9 +263,10 @@ def encode_index(r: HashRenderer, pos: torch.Tensor):
 
 
 def render(r: HashRenderer, env: torch.Tensor, pos, nrm=None, wo=None, dirs=None, n_dirs=32, n_dirs2=8, seed=7,
-           flags=0, indirect=True, want_vis=False, precision="fp32", out=None):
+           flags=0, indirect=True, want_vis=False, precision="fp32", out=None, env_dist=None):
     """Shade mode (dirs None): rgb [n,3] (+ vis/depth [n,N] if want_vis).
-    Query mode: rgb [n,3] = L_in, vis [n], depth [n]."""
+    Query mode: rgb [n,3] = L_in, vis [n], depth [n].  flags=HG_MIS needs
+    env_dist = env_sampling(env)."""
     n = pos.shape[0]
     dev = pos.device
     if out is None:
@@ -262,7 +282,7 @@ def render(r: HashRenderer, env: torch.Tensor, pos, nrm=None, wo=None, dirs=None
     else:
         rgb, vis, dep = out
     m = r.model_struct(precision)
-    e = env_struct(env)
+    e = env_struct(env, env_dist)
     s = sampling_struct(n_dirs, n_dirs2, seed, flags)
     p = points_struct(pos, nrm, wo, dirs)
     fn = lib().hg_render_indirect if indirect else lib().hg_render_direct

@@ -15,7 +15,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhg.so")
 
-SOURCES = ["hg_api.hip", "hg_render.hip", "hg_render_mfma.hip", "hg_backward.hip", "hg_train.hip", "hg_denoise.hip"]
+SOURCES = ["hg_api.hip", "hg_render.hip", "hg_render_mfma.hip", "hg_backward.hip", "hg_train.hip", "hg_denoise.hip", "hg_mis.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -140,7 +140,21 @@ hg_status check_env(const hg_env *e, hg::EnvK &k) {
     k.W = e->W;
     k.Hf = (float)e->H;
     k.Wf = (float)e->W;
+    k.ct = k.marg = k.cond = nullptr;
+    k.dens = nullptr;
+    if (e->dist) {
+        REQUIRE(aligned(e->dist, 8), "env.dist is not 8-byte aligned");
+        const double *d = static_cast<const double *>(e->dist);
+        k.ct = d;
+        k.marg = d + (e->H + 1);
+        k.cond = k.marg + (e->H + 1);
+        k.dens = reinterpret_cast<const float *>(k.cond + (size_t)e->H * (e->W + 1));
+    }
     return HG_OK;
+}
+
+size_t env_sampling_bytes(int32_t H, int32_t W) {
+    return (size_t)(2 * (H + 1) + (size_t)H * (W + 1)) * sizeof(double) + (size_t)H * W * sizeof(float);
 }
 
 hg_status check_sampling(const hg_sampling *s, bool need_primary, hg::SampK &k) {
@@ -148,7 +162,12 @@ hg_status check_sampling(const hg_sampling *s, bool need_primary, hg::SampK &k) 
     if (need_primary)
         REQUIRE(pow2(s->n_dirs) && s->n_dirs <= 1024, "n_dirs = %d is not a power of two in [1, 1024]", s->n_dirs);
     REQUIRE(pow2(s->n_dirs2) && s->n_dirs2 <= 64, "n_dirs2 = %d is not a power of two in [1, 64]", s->n_dirs2);
-    REQUIRE((s->flags & ~(HG_DIFFUSE_ONLY | HG_HARD_VIS)) == 0, "unknown sampling flags 0x%x", s->flags);
+    REQUIRE((s->flags & ~(HG_DIFFUSE_ONLY | HG_HARD_VIS | HG_MIS)) == 0, "unknown sampling flags 0x%x", s->flags);
+    const bool mis = (s->flags & HG_MIS) != 0;
+    if (mis) {
+        SUPPORT(need_primary, "HG_MIS applies to shade mode only");
+        REQUIRE(s->n_dirs >= 2, "HG_MIS needs n_dirs = 2M >= 2");
+    }
     const int N = need_primary ? s->n_dirs : 1;
     const int na = 1 << (ilog2(N) / 2), nb = N / na;
     const int N2 = s->n_dirs2;
@@ -165,6 +184,13 @@ hg_status check_sampling(const hg_sampling *s, bool need_primary, hg::SampK &k) 
     k.inv_na2 = 1.0f / (float)na2;
     k.inv_nb2 = 1.0f / (float)nb2;
     k.g_shift = (uint32_t)ilog2(N < 64 ? N : 64);
+    // strata of the M samples of each MIS strategy
+    const int M = mis ? N / 2 : 1;
+    const int nam = 1 << (ilog2(M) / 2), nbm = M / nam;
+    k.m_half = (uint32_t)M;
+    k.nbm_shift = (uint32_t)ilog2(nbm);
+    k.inv_nam = 1.0f / (float)nam;
+    k.inv_nbm = 1.0f / (float)nbm;
     return HG_OK;
 }
 
@@ -195,6 +221,8 @@ hg_status render(const hg_model *model, const hg_env *env, const hg_sampling *sa
     CHECK(check_sampling(samp, !query, k.s));
     SUPPORT(prec != Prec::F16TableF32Mlp, "rendering needs (F32 table, F32 MLP) or (F16 table, BF16 MLP)");
     SUPPORT(prec != Prec::Mixed || query || samp->n_dirs >= 16, "the mixed path needs n_dirs >= 16 in shade mode");
+    REQUIRE((samp->flags & HG_MIS) == 0 || env->dist != nullptr,
+            "HG_MIS needs env.dist (hg_env_build_sampling)");
     if (pts->n == 0) return HG_OK;
     CHECK(check_ptr(rgb, "rgb"));
     if (query) {
@@ -277,7 +305,7 @@ hg_status hg_backward(const hg_model *model, const hg_env *env, const hg_samplin
     REQUIRE(query || pts->n == 0, "hg_backward needs query-mode points (dir != NULL)");
     CHECK(check_sampling(samp, false, k.r.s));
     SUPPORT(prec != Prec::Mixed, "hg_backward needs FP32 MLP weights (the masters)");
-    SUPPORT((samp->flags & HG_HARD_VIS) == 0, "hard visibility is a forward-only mode");
+    SUPPORT((samp->flags & (HG_HARD_VIS | HG_MIS)) == 0, "hard visibility and MIS are forward-only modes");
     REQUIRE(indirect == 0 || indirect == 1, "indirect must be 0 or 1");
     if (pts->n == 0) return HG_OK;
     CHECK(check_ptr(g_rgb, "g_rgb"));
@@ -349,6 +377,24 @@ hg_status hg_adam_step(float *param, const float *grad, float *m, float *v, int6
     return hip_status(hg::launch_adam(param, grad, m, v, n, lr, beta1, beta2, eps, weight_decay, (float)bc1,
                                       (float)bc2, shadow, kind, stream),
                       "hg_adam_step");
+}
+
+size_t hg_env_sampling_size(int32_t H, int32_t W) {
+    if (H <= 0 || W <= 0 || H > 8192 || W > 8192) return 0;
+    return env_sampling_bytes(H, W);
+}
+
+hg_status hg_env_build_sampling(const hg_env *env, void *dist, size_t bytes, hipStream_t stream) {
+    g_err.clear();
+    REQUIRE(env != nullptr, "env is NULL");
+    REQUIRE(env->H >= 1 && env->W >= 1 && env->H <= 8192 && env->W <= 8192, "env size %dx%d outside [1, 8192]^2",
+            env->H, env->W);
+    CHECK(check_ptr(env->rgb, "env.rgb"));
+    CHECK(check_ptr(dist, "dist", 8));
+    REQUIRE(bytes >= env_sampling_bytes(env->H, env->W), "bytes %zu < %zu", bytes,
+            env_sampling_bytes(env->H, env->W));
+    return hip_status(hg::launch_env_dist(env->rgb, env->H, env->W, static_cast<double *>(dist), stream),
+                      "hg_env_build_sampling");
 }
 
 size_t hg_denoise_workspace_size(int32_t H, int32_t W) {

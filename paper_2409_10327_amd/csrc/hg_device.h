@@ -42,6 +42,10 @@ struct EnvK {
     const float *rgb;  // [H][W][3]
     int32_t H, W;
     float Hf, Wf;
+    // light-sampling distribution (MIS): cos(theta) at row edges [H+1],
+    // marginal CDF [H+1], conditional CDFs [H][W+1], densities [H][W]
+    const double *ct, *marg, *cond;
+    const float *dens;
 };
 
 struct SampK {
@@ -50,6 +54,8 @@ struct SampK {
     uint32_t nb_shift, nb2_shift;   // log2 of the azimuth strata count
     float inv_na, inv_nb, inv_na2, inv_nb2;
     uint32_t g_shift;               // log2(min(n_dirs, 64)) (shade reduction)
+    uint32_t m_half, nbm_shift;     // MIS: M = n_dirs / 2 samples per strategy, their strata
+    float inv_nam, inv_nbm;
 };
 
 struct RenderK {
@@ -492,6 +498,137 @@ __device__ __forceinline__ void mlp_fwd(const MlpK &m, const float (&in)[NIN], f
         for (int i = 0; i < kH; ++i) acc = fmaf(W2[o * kH + i], h[i], acc);
         out[o] = acc;
     }
+}
+
+// --------------------------------------------------------------------------
+// Multiple importance sampling of the primary directions (Sec. 4.1): light
+// samples from the environment's piecewise-constant distribution and GGX
+// samples of the visible normals (Heitz, JCGT 2018), balance heuristic.
+// The inversion of the FP64 CDFs and the placement inside the texel run in
+// FP64, so texel choices and in-texel offsets do not depend on FP32
+// rounding of the CDFs; the rest runs in FP32.
+// --------------------------------------------------------------------------
+// largest i in [0, n-1] with c[i] <= u (c nondecreasing, c[0] = 0 <= u)
+__device__ __forceinline__ int cdf_find(const double *c, int n, double u) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (c[mid] <= u) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// light sample for the stratified uniforms (s1, s2); returns the direction
+// and its density (per steradian)
+__device__ __forceinline__ float3 env_light_sample(const EnvK &e, double s1, double s2, float &dens) {
+    const int H = e.H, W = e.W;
+    const int y = cdf_find(e.marg, H, s1);
+    const double fv = (s1 - e.marg[y]) / (e.marg[y + 1] - e.marg[y]);
+    const double *c = e.cond + (size_t)y * (W + 1);
+    const int x = cdf_find(c, W, s2);
+    const double fu = (s2 - c[x]) / (c[x + 1] - c[x]);
+    const double cth = e.ct[y] - fv * (e.ct[y] - e.ct[y + 1]);
+    const float sth = (float)sqrt((1.0 - cth) * (1.0 + cth));
+    // phi / pi in [-1, 1]
+    const float t = (float)(-1.0 + 2.0 * ((double)x + fu) / (double)W);
+    float sn, cs;
+    sincospif(t, &sn, &cs);
+    dens = e.dens[(size_t)y * W + x];
+    return make_float3(sth * cs, (float)cth, sth * sn);
+}
+
+// density of the light distribution at a direction (texel lookup)
+__device__ __forceinline__ float env_light_density(const EnvK &e, float3 w) {
+    const float phi = atan2_poly(w.z, w.x);
+    const float th = atan2_poly(sqrtf(w.x * w.x + w.z * w.z), w.y);
+    int x = (int)floorf((phi + kPi) * (e.Wf * (0.5f / kPi)));
+    int y = (int)floorf(th * (e.Hf * (1.0f / kPi)));
+    x = min(max(x, 0), e.W - 1);
+    y = min(max(y, 0), e.H - 1);
+    return e.dens[(size_t)y * e.W + x];
+}
+
+// view in the frame of the normal, normal component clamped to 1e-4, unit
+__device__ __forceinline__ float3 ggx_view(const Frame &fr, float3 v) {
+    float3 vl = make_float3(dot3(v, fr.t), dot3(v, fr.b), fmaxf(dot3(v, fr.n), 1e-4f));
+    const float inv = rsqrtf(dot3(vl, vl));
+    return make_float3(vl.x * inv, vl.y * inv, vl.z * inv);
+}
+
+// density of the GGX visible-normal reflection at world direction l
+__device__ __forceinline__ float ggx_density(const Frame &fr, float3 vl, float r, float3 l) {
+    const float3 ll = make_float3(dot3(l, fr.t), dot3(l, fr.b), dot3(l, fr.n));
+    float3 h = make_float3(vl.x + ll.x, vl.y + ll.y, vl.z + ll.z);
+    const float hh = dot3(h, h);
+    if (!(hh > 0.0f)) return 0.0f;
+    const float inv = rsqrtf(hh);
+    h = make_float3(h.x * inv, h.y * inv, h.z * inv);
+    if (!(dot3(vl, h) > 0.0f) || !(h.z > 0.0f)) return 0.0f;
+    const float al = r * r, a2 = al * al;
+    const float Q = fmaf(h.z * h.z, a2 - 1.0f, 1.0f);
+    const float D = a2 / (kPi * Q * Q);
+    const float G1 = 2.0f * vl.z / (vl.z + sqrtf(fmaf(1.0f - a2, vl.z * vl.z, a2)));
+    return G1 * D / (4.0f * vl.z);
+}
+
+// GGX visible-normal sample, reflected about the sampled normal; world space
+__device__ __forceinline__ float3 ggx_sample(const Frame &fr, float3 vl, float r, float s1, float s2) {
+    const float al = r * r;
+    float3 vh = make_float3(al * vl.x, al * vl.y, vl.z);
+    const float iv = rsqrtf(dot3(vh, vh));
+    vh = make_float3(vh.x * iv, vh.y * iv, vh.z * iv);
+    const float lensq = vh.x * vh.x + vh.y * vh.y;
+    float3 T1 = make_float3(1.0f, 0.0f, 0.0f);
+    if (lensq > 0.0f) {
+        const float il = rsqrtf(lensq);
+        T1 = make_float3(-vh.y * il, vh.x * il, 0.0f);
+    }
+    const float3 T2 = make_float3(vh.y * T1.z - vh.z * T1.y, vh.z * T1.x - vh.x * T1.z, vh.x * T1.y - vh.y * T1.x);
+    const float rr = sqrtf(s1);
+    float sn, cs;
+    sincospif(2.0f * s2, &sn, &cs);
+    const float t1 = rr * cs;
+    float t2 = rr * sn;
+    const float sv = 0.5f * (1.0f + vh.z);
+    t2 = (1.0f - sv) * sqrtf(fmaxf(1.0f - t1 * t1, 0.0f)) + sv * t2;
+    const float tz = sqrtf(fmaxf(1.0f - t1 * t1 - t2 * t2, 0.0f));
+    const float3 nh = make_float3(t1 * T1.x + t2 * T2.x + tz * vh.x, t1 * T1.y + t2 * T2.y + tz * vh.y,
+                                  t1 * T1.z + t2 * T2.z + tz * vh.z);
+    float3 ne = make_float3(al * nh.x, al * nh.y, fmaxf(nh.z, 0.0f));
+    const float ie = rsqrtf(dot3(ne, ne));
+    ne = make_float3(ne.x * ie, ne.y * ie, ne.z * ie);
+    const float vn2 = 2.0f * dot3(vl, ne);
+    const float3 ll = make_float3(vn2 * ne.x - vl.x, vn2 * ne.y - vl.y, vn2 * ne.z - vl.z);
+    return make_float3(ll.x * fr.t.x + ll.y * fr.b.x + ll.z * fr.n.x, ll.x * fr.t.y + ll.y * fr.b.y + ll.z * fr.n.y,
+                       ll.x * fr.t.z + ll.y * fr.b.z + ll.z * fr.n.z);
+}
+
+// Primary direction i of a point under MIS and the factor that turns pi f_r
+// into its balance-heuristic weight, 2 (n.w) / (pi (p_env + p_ggx)).
+__device__ __forceinline__ float3 mis_direction(const RenderK &a, const Frame &fr, float3 vl, float r, uint32_t pid,
+                                                uint32_t i, float &wfac) {
+    const uint32_t M = a.s.m_half;
+    const bool light = i < M;
+    const uint32_t k = light ? i : i - M;
+    const uint4 words = philox4x32_10(pid, 0u, k >> 2, light ? 2u : 3u, a.s.key0, a.s.key1);
+    const uint32_t w = pick4(words, k);
+    const uint32_t sa = k >> a.s.nbm_shift, sb = k & ((1u << a.s.nbm_shift) - 1u);
+    // (stratum + uniform at its bin centre) / strata: exact in FP32 and FP64
+    const float s1 = ((float)sa + ((float)(w & 0xffffu) + 0.5f) * (1.0f / 65536.0f)) * a.s.inv_nam;
+    const float s2 = ((float)sb + ((float)(w >> 16) + 0.5f) * (1.0f / 65536.0f)) * a.s.inv_nbm;
+    float3 d;
+    float pe;
+    if (light) {
+        d = env_light_sample(a.env, (double)s1, (double)s2, pe);
+    } else {
+        d = ggx_sample(fr, vl, r, s1, s2);
+        pe = env_light_density(a.env, d);
+    }
+    const float nl = dot3(fr.n, d);
+    const float den = pe + ggx_density(fr, vl, r, d);
+    wfac = (nl > 0.0f && den > 0.0f) ? 2.0f * nl / (kPi * den) : 0.0f;
+    return d;
 }
 
 // Compensated accumulation (Kahan) and exact pairwise combination (TwoSum).

@@ -167,7 +167,7 @@ __global__ __launch_bounds__(128) void k_render_query(const RenderK a) {
 // combine their (sum, compensation) pairs with TwoSum in a fixed butterfly.
 // The result is bit-reproducible run to run.
 // --------------------------------------------------------------------------
-template <bool INDIRECT>
+template <bool INDIRECT, bool MIS>
 __global__ __launch_bounds__(128) void k_render_shade(const RenderK a) {
     extern __shared__ float lds[];
     const int lane = threadIdx.x & 63;
@@ -192,18 +192,26 @@ __global__ __launch_bounds__(128) void k_render_shade(const RenderK a) {
     const float mm = sigmoidf_(ob[4]);
     const Frame fr = make_frame(n);
     const bool diffuse = (a.s.flags & 1u) != 0;
+    const float3 vl = MIS ? ggx_view(fr, v) : v;
     KSum sx{0.f, 0.f}, sy{0.f, 0.f}, sz{0.f, 0.f};
     uint4 words = make_uint4(0, 0, 0, 0);
     for (uint32_t i = i0; i < N; i += G) {
-        // four consecutive samples share one Philox call; with G >= 4 lanes
-        // per pixel each lane's samples are spaced G apart, so each call
-        // serves the lane's sample only.
-        words = philox4x32_10((uint32_t)p, 0u, i >> 2, 0u, a.s.key0, a.s.key1);
-        const float3 wi = sample_dir(pick4(words, i), i, a.s.nb_shift, a.s.inv_na, a.s.inv_nb, fr);
+        float3 wi;
+        float wfac = 1.0f;
+        if (MIS) {
+            wi = mis_direction(a, fr, vl, rr, (uint32_t)p, i, wfac);
+        } else {
+            // four consecutive samples share one Philox call; with G >= 4
+            // lanes per pixel each lane's samples are spaced G apart, so each
+            // call serves the lane's sample only.
+            words = philox4x32_10((uint32_t)p, 0u, i >> 2, 0u, a.s.key0, a.s.key1);
+            wi = sample_dir(pick4(words, i), i, a.s.nb_shift, a.s.inv_na, a.s.inv_nb, fr);
+        }
         float3 Lin;
         float V, d;
         incoming<INDIRECT>(a, f, x, wi, (uint32_t)p, i, hbuf, lane, Lin, V, d);
-        const float3 c = pi_brdf(n, v, wi, al, rr, mm, a.f0, diffuse);
+        float3 c = pi_brdf(n, v, wi, al, rr, mm, a.f0, diffuse);
+        if (MIS) c = make_float3(c.x * wfac, c.y * wfac, c.z * wfac);
         sx.add(c.x * Lin.x);
         sy.add(c.y * Lin.y);
         sz.add(c.z * Lin.z);
@@ -246,8 +254,14 @@ hipError_t launch_render_f32(const RenderK &a, bool indirect, bool query, hipStr
         const int64_t ppw = 64 >> a.s.g_shift;
         const int64_t waves = (a.n + ppw - 1) / ppw;
         const unsigned blocks = (unsigned)((waves + 1) / 2);
-        if (indirect) hipLaunchKernelGGL(k_render_shade<true>, dim3(blocks), dim3(128), lds, s, a);
-        else hipLaunchKernelGGL(k_render_shade<false>, dim3(blocks), dim3(128), lds, s, a);
+        const bool mis = (a.s.flags & 4u) != 0;
+        if (indirect) {
+            if (mis) hipLaunchKernelGGL((k_render_shade<true, true>), dim3(blocks), dim3(128), lds, s, a);
+            else hipLaunchKernelGGL((k_render_shade<true, false>), dim3(blocks), dim3(128), lds, s, a);
+        } else {
+            if (mis) hipLaunchKernelGGL((k_render_shade<false, true>), dim3(blocks), dim3(128), lds, s, a);
+            else hipLaunchKernelGGL((k_render_shade<false, false>), dim3(blocks), dim3(128), lds, s, a);
+        }
     }
     return hipGetLastError();
 }

@@ -449,7 +449,7 @@ __device__ __forceinline__ float3 bounce_lo(const RenderK &a, const typename PP:
 // ============================================================================
 constexpr int kMixThreads = 256;
 
-template <class PP, bool INDIRECT, bool QUERY>
+template <class PP, bool INDIRECT, bool QUERY, bool MIS>
 __global__ __launch_bounds__(kMixThreads) void k_render_mma(const RenderK a, int64_t n_items) {
     typedef typename PP::Table TT;
     __shared__ typename PP::Tile tiles[PP::N_TILES * 64];
@@ -545,6 +545,7 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mma(const RenderK a, int
             mm = sigmoidf_(W.mat[myslot][4]);
         }
         const Frame fr = make_frame(n_);
+        const float3 vl = MIS ? ggx_view(fr, v_) : v_;
         const uint32_t N = QUERY ? 1u : a.s.n_dirs;
         const uint32_t i0 = QUERY ? 0u : (uint32_t)(lane & (G - 1));
         const uint32_t step = QUERY ? 1u : G;
@@ -558,12 +559,14 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mma(const RenderK a, int
         while (true) {
             // ---------------- primary directions of the next chunk ----------------
             float3 w_own = make_float3(0.f, 0.f, 1.f), Le_own = w_own;
-            float V_own = 0.f, d_own = 0.f;
+            float V_own = 0.f, d_own = 0.f, wf_own = 1.0f;
             const uint32_t i_own = i_next;
             const bool had = more;
             if (more) {
                 if (QUERY) {
                     w_own = make_float3(a.dir[3 * p], a.dir[3 * p + 1], a.dir[3 * p + 2]);
+                } else if (MIS) {
+                    w_own = mis_direction(a, fr, vl, rr, (uint32_t)p, i_own, wf_own);
                 } else {
                     const uint4 words = philox4x32_10((uint32_t)p, 0u, i_own >> 2, 0u, a.s.key0, a.s.key1);
                     w_own = sample_dir(pick4(words, i_own), i_own, a.s.nb_shift, a.s.inv_na, a.s.inv_nb, fr);
@@ -603,7 +606,8 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mma(const RenderK a, int
                     // visible rays are finished here; shadow rays are queued
                     const bool vis1 = V_own == 1.0f;
                     if (vis1) {
-                        const float3 c = pi_brdf(n_, v_, w_own, alb, rr, mm, a.f0, diffuse);
+                        float3 c = pi_brdf(n_, v_, w_own, alb, rr, mm, a.f0, diffuse);
+                        if (MIS) c = make_float3(c.x * wf_own, c.y * wf_own, c.z * wf_own);
                         sx.add(c.x * Le_own.x);
                         sy.add(c.y * Le_own.y);
                         sz.add(c.z * Le_own.z);
@@ -627,7 +631,7 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mma(const RenderK a, int
             // ---------------- bounce for 64 lanes ----------------
             bool active = true;
             uint32_t ie = i_own;
-            float de = d_own, Ve = V_own;
+            float de = d_own, Ve = V_own, wfe = wf_own;
             float3 we = w_own;
             if (compact) {
                 wave_sync_lds();
@@ -636,8 +640,12 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mma(const RenderK a, int
                 ie = W.qi[slot];
                 de = W.qd[slot];
                 Ve = 0.0f;
-                const uint4 words = philox4x32_10((uint32_t)p, 0u, ie >> 2, 0u, a.s.key0, a.s.key1);
-                we = sample_dir(pick4(words, ie), ie, a.s.nb_shift, a.s.inv_na, a.s.inv_nb, fr);
+                if (MIS) {
+                    we = mis_direction(a, fr, vl, rr, (uint32_t)p, ie, wfe);
+                } else {
+                    const uint4 words = philox4x32_10((uint32_t)p, 0u, ie >> 2, 0u, a.s.key0, a.s.key1);
+                    we = sample_dir(pick4(words, ie), ie, a.s.nb_shift, a.s.inv_na, a.s.inv_nb, fr);
+                }
             }
             float3 Lin;
             if (!INDIRECT) {
@@ -660,7 +668,8 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mma(const RenderK a, int
                     }
                 }
             } else if (active) {
-                const float3 c = pi_brdf(n_, v_, we, alb, rr, mm, a.f0, diffuse);
+                float3 c = pi_brdf(n_, v_, we, alb, rr, mm, a.f0, diffuse);
+                if (MIS) c = make_float3(c.x * wfe, c.y * wfe, c.z * wfe);
                 sx.add(c.x * Lin.x);
                 sy.add(c.y * Lin.y);
                 sz.add(c.z * Lin.z);
@@ -726,12 +735,17 @@ static hipError_t launch_mma(const RenderK &a, bool indirect, bool query, hipStr
     const int64_t want = (items + 3) / 4;
     const int64_t cap = (int64_t)g_num_cus * 2;
     const unsigned blocks = (unsigned)(want < cap ? want : cap);
+    const dim3 grid(blocks), block(kMixThreads);
+    const bool mis = (a.s.flags & 4u) != 0;
     if (query) {
-        if (indirect) hipLaunchKernelGGL((k_render_mma<PP, true, true>), dim3(blocks), dim3(kMixThreads), 0, s, a, items);
-        else hipLaunchKernelGGL((k_render_mma<PP, false, true>), dim3(blocks), dim3(kMixThreads), 0, s, a, items);
+        if (indirect) hipLaunchKernelGGL((k_render_mma<PP, true, true, false>), grid, block, 0, s, a, items);
+        else hipLaunchKernelGGL((k_render_mma<PP, false, true, false>), grid, block, 0, s, a, items);
+    } else if (mis) {
+        if (indirect) hipLaunchKernelGGL((k_render_mma<PP, true, false, true>), grid, block, 0, s, a, items);
+        else hipLaunchKernelGGL((k_render_mma<PP, false, false, true>), grid, block, 0, s, a, items);
     } else {
-        if (indirect) hipLaunchKernelGGL((k_render_mma<PP, true, false>), dim3(blocks), dim3(kMixThreads), 0, s, a, items);
-        else hipLaunchKernelGGL((k_render_mma<PP, false, false>), dim3(blocks), dim3(kMixThreads), 0, s, a, items);
+        if (indirect) hipLaunchKernelGGL((k_render_mma<PP, true, false, false>), grid, block, 0, s, a, items);
+        else hipLaunchKernelGGL((k_render_mma<PP, false, false, false>), grid, block, 0, s, a, items);
     }
     return hipGetLastError();
 }

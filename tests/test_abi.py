@@ -19,7 +19,7 @@ def header_symbols():
 
 def test_library_exports_every_declared_symbol():
     syms = header_symbols()
-    assert len(syms) == 10, syms
+    assert len(syms) == 12, syms
     L = hg.lib()
     for s in syms:
         assert hasattr(L, s), s
@@ -102,7 +102,29 @@ def test_sampling_validation(n_dirs, n_dirs2):
 
 
 def test_unknown_flags_rejected():
-    assert call_render(samp=hg.sampling_struct(32, 8, 7, 4)) == hg.HG_E_INVALID
+    assert call_render(samp=hg.sampling_struct(32, 8, 7, 8)) == hg.HG_E_INVALID
+
+
+def test_mis_validation():
+    L = hg.lib()
+    env = hg.Env(); env.H, env.W, env.rgb, env.dist = 16, 32, FAKE, None
+    mis = hg.sampling_struct(32, 8, 7, hg.HG_MIS)
+    assert call_render(env=env, samp=mis) == hg.HG_E_INVALID               # no distribution
+    env.dist = FAKE + 4
+    assert call_render(env=env, samp=mis) == hg.HG_E_INVALID               # misaligned distribution
+    env.dist = FAKE
+    assert call_render(env=env, samp=hg.sampling_struct(1, 8, 7, hg.HG_MIS)) == hg.HG_E_INVALID  # n_dirs = 1
+    q = hg.Points(); q.n, q.pos, q.nrm, q.wo, q.dir = 10, FAKE, None, None, FAKE
+    assert call_render(env=env, samp=mis, pts=q) == hg.HG_E_UNSUPPORTED  # query mode
+    # distribution size: 2 (H+1) + H (W+1) doubles and H W floats
+    assert L.hg_env_sampling_size(16, 32) == (2 * 17 + 16 * 33) * 8 + 16 * 32 * 4
+    assert L.hg_env_sampling_size(0, 32) == 0 and L.hg_env_sampling_size(16, 9000) == 0
+    need = L.hg_env_sampling_size(16, 32)
+    assert L.hg_env_build_sampling(C.byref(env), None, need, None) == hg.HG_E_INVALID
+    assert L.hg_env_build_sampling(C.byref(env), C.c_void_p(FAKE), need - 1, None) == hg.HG_E_INVALID
+    assert L.hg_env_build_sampling(C.byref(env), C.c_void_p(FAKE + 4), need, None) == hg.HG_E_INVALID
+    big = hg.Env(); big.H, big.W, big.rgb = 9000, 16, FAKE
+    assert L.hg_env_build_sampling(C.byref(big), C.c_void_p(FAKE), 1 << 30, None) == hg.HG_E_INVALID
 
 
 def test_points_validation():
