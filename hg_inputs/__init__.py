@@ -80,6 +80,7 @@ class Config:
     precision: str = "fp32"          # "fp32" or "mixed"
     batch: int = 0                   # training batch (query mode), 0 = none
     teacher_log2_T: int = 20
+    brdf_out: int = 5                # 8: decoder with a normal head (paper shape)
     res: list = field(default_factory=list)
 
     def __post_init__(self):
@@ -104,6 +105,10 @@ def config(name: str) -> Config:
     c4: distillation training step: 2^18 query-mode samples, teacher T=2^20,
         student T=2^19.
     c5: mixed 800x800 frame at N=512 plus a training step over 2^20 samples.
+    paper: the paper's model shape (Sec. 4.1): 14 levels, T=2^17, res
+        16..131072 (growth 2, two dense levels), decoder with a normal head
+        (8 outputs), 800x800 frame, env 64x128, N=128.
+    paper_small: the same model shape on the 64x64 frame (parity sizes).
     """
     if name == "c1":
         return Config("c1")
@@ -116,6 +121,11 @@ def config(name: str) -> Config:
     if name == "c4":
         return Config("c4", img_h=0, img_w=0, log2_T=19, res_max=2048, env_h=64, env_w=128,
                       n_dirs=1, batch=1 << 18)
+    if name in ("paper", "paper_small"):
+        size = 800 if name == "paper" else 64
+        env = (64, 128) if name == "paper" else (16, 32)
+        return Config(name, img_h=size, img_w=size, n_levels=14, log2_T=17, res_min=16, res_max=131072,
+                      env_h=env[0], env_w=env[1], n_dirs=128 if name == "paper" else 32, brdf_out=8)
     if name == "c5":
         f = dict(frame)
         f["n_dirs"] = 512
@@ -210,13 +220,14 @@ def make_mlp(n_in: int, n_hidden: int, n_out: int, rng):
 
 def make_model(cfg: Config, seed_table: int = SEED_TABLE, seed_mlp: int = SEED_MLP,
                log2_T: int | None = None):
-    """Tables plus BRDF decoder B (L*F -> 64 -> 64 -> 5) and implicit ray
-    tracer I (L*F+3 -> 64 -> 64 -> 2) as float32 arrays."""
+    """Tables plus BRDF decoder B (L*F -> 64 -> 64 -> 5, or 8 with the normal
+    head) and implicit ray tracer I (L*F+3 -> 64 -> 64 -> 2) as float32
+    arrays."""
     lt = cfg.log2_T if log2_T is None else log2_T
     table = make_table(cfg.n_levels, lt, cfg.n_feat, seed_table)
     rng = np.random.Generator(np.random.PCG64(seed_mlp))
     nf = cfg.n_levels * cfg.n_feat
-    brdf = make_mlp(nf, cfg.hidden, 5, rng)
+    brdf = make_mlp(nf, cfg.hidden, cfg.brdf_out, rng)
     irt = make_mlp(nf + 3, cfg.hidden, 2, rng)
     return dict(table=table, brdf=brdf, irt=irt, res=list(cfg.res), log2_T=lt,
                 n_levels=cfg.n_levels, n_feat=cfg.n_feat)

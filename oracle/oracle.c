@@ -786,10 +786,12 @@ void or_ggx_density(const double *n, const double *v, const double *r, const dou
 /*   Bounce (Sec. 3.2 "Overview"): f' = H(x'), (a', r', m') = B(f'), N'     */
 /*   new directions about n' with visibility V'_j = sigmoid(I(f', w'_j)_0); */
 /*   L'_o = 1/N' sum_j pi f_r(n', v', w'_j) V'_j L_env(w'_j).               */
-/*   Reading: the decoder has no normal head, so the secondary surface      */
-/*   faces the tracer, n' = v' = -w; visibility is used soft (sigmoid) in    */
-/*   Eq. (2) and the bounce is evaluated for every direction, weighted by   */
-/*   (1 - V).                                                               */
+/*   Reading: a 5-output decoder has no normal head, so the secondary       */
+/*   surface faces the tracer, n' = v' = -w; an 8-output decoder (the       */
+/*   paper's model shape, Sec. 3.2) gives n' = o[5..7]/|o[5..7]| (the       */
+/*   facing normal if that vector is zero) with view v' = -w.  Visibility   */
+/*   is used soft (sigmoid) in Eq. (2) and the bounce is evaluated for every */
+/*   direction, weighted by (1 - V).                                        */
 /*   L_in = V L_env(w) + (1 - V) L'_o; direct-only: L_in = V L_env(w).       */
 /* ------------------------------------------------------------------------ */
 static void incoming(const or_model *M, const or_env *E, const or_sampling *S, int indirect,
@@ -825,7 +827,15 @@ static void incoming(const or_model *M, const or_env *E, const or_sampling *S, i
     double ab[3] = {sigmoid(ob[0]), sigmoid(ob[1]), sigmoid(ob[2])};
     double rb = 0.09 + 0.91 * sigmoid(ob[3]);
     double mb = sigmoid(ob[4]);
+    /* secondary view -w; normal: the decoder's normal head n/|n| when it has
+       one (outputs 5..7), else the facing normal -w (reading, see above) */
+    double vb[3] = {-w[0], -w[1], -w[2]};
     double nb[3] = {-w[0], -w[1], -w[2]};
+    if (M->brdf.n_out >= 8) {
+        double nn = sqrt(ob[5] * ob[5] + ob[6] * ob[6] + ob[7] * ob[7]);
+        if (nn > 0.0)
+            for (int k = 0; k < 3; ++k) nb[k] = ob[5 + k] / nn;
+    }
     double Lo[3] = {0, 0, 0};
     const int N2 = S->n_dirs2;
     for (int j = 0; j < N2; ++j) {
@@ -837,7 +847,7 @@ static void incoming(const or_model *M, const or_env *E, const or_sampling *S, i
         /* hard visibility: only visible secondary rays contribute */
         double vj = hard ? (o[0] > 0.0 ? 1.0 : 0.0) : sigmoid(o[0]);
         env_lookup(E, wj, Ej);
-        brdf_eval(nb, nb, wj, ab, rb, mb, M->f0, (S->flags & OR_DIFFUSE_ONLY) != 0, fr, t1, t2, t3);
+        brdf_eval(nb, vb, wj, ab, rb, mb, M->f0, (S->flags & OR_DIFFUSE_ONLY) != 0, fr, t1, t2, t3);
         for (int c = 0; c < 3; ++c) Lo[c] += M_PI * fr[c] * vj * Ej[c];
     }
     for (int c = 0; c < 3; ++c) {

@@ -314,7 +314,10 @@ def split_mlp_grad(flat, ws):
 def backward(om: OracleModel, oe: OracleEnv, samp: Sampling, pos, dirs, g_rgb, g_vis, g_dep,
              indirect=True, want_pos=False, pid=None):
     """Gradients of sum_p (g_rgb.rgb + g_vis*vis + g_dep*depth) in query mode.
-    Returns dict(table [L,T,F], brdf [6 arrays], irt [6 arrays], pos [n,3]|None)."""
+    Returns dict(table [L,T,F], brdf [6 arrays], irt [6 arrays], pos [n,3]|None).
+    Defined for the 5-output decoder (facing normal at the bounce point)."""
+    if om.c.brdf.n_out != 5:
+        raise ValueError("the oracle backward covers the 5-output decoder only")
     P, keep = _points(pos, None, None, dirs, pid)
     g_rgb, g_vis, g_dep = _f32(g_rgb), _f32(g_vis), _f32(g_dep)
     gt = np.zeros(om.table.shape)

@@ -892,3 +892,72 @@ def test_mis_estimate_converges_to_the_rendering_integral():
         ref = (f * Ld * (cos * dw)[:, None]).sum(0)
         assert np.all(np.abs(mean[p] - ref) <= 4 * sem[p] + 2e-3 * ref), (p, mean[p], sem[p], ref)
         assert np.all(sem[p] < 2e-2 * ref)
+
+
+# ------------------------------------------------------ decoder normal head --
+@pytest.mark.parametrize("n_raw", [(0.0, 2.5, 0.0), (0.0, -0.7, 0.0), (3.0, 0.0, 3.0), (0.0, 0.0, 0.0)])
+def test_decoder_normal_head_orients_the_bounce(n_raw):
+    """8-output decoder (the paper's model shape): the secondary normal is
+    o[5..7] normalised (the facing normal -w when that vector is zero).
+    Hard visibility with a tracer whose visibility logit is w_y, a constant
+    environment L and a diffuse decoder: a shadow ray (w_y < 0) returns
+    a L times the fraction of its 8 secondary rays, sampled about n', with
+    w_y > 0; with n' = +y that is all of them, with n' = -y none."""
+    L = 4
+    m = small_model(L=L, log2T=10)
+    nf, hid = 2 * L, 64
+    W0 = np.zeros((hid, nf + 3), np.float32); W0[0, nf + 1] = 1.0
+    b0 = np.full(hid, 10.0, np.float32)
+    W1 = np.eye(hid, dtype=np.float32); b1 = np.zeros(hid, np.float32)
+    W2 = np.zeros((2, hid), np.float32); W2[0, 0] = 1.0
+    m["irt"] = [W0, b0, W1, b1, W2, np.array([-10.0, 0.3], np.float32)]
+    alb = (0.3, 0.6, 0.9)
+    m["brdf"] = const_mlp(nf, 8, [logit(a) for a in alb] + [0.0, -40.0] + list(n_raw))
+    om = O.OracleModel(m, LO, EXT)
+    Lc = 1.5
+    oe = O.OracleEnv(np.full((8, 16, 3), Lc, np.float32))
+    n = 64
+    x = np.random.default_rng(5).uniform(-1, 1, (n, 3)).astype(np.float32)
+    w = rand_normals(n, 44)
+    w[:, 1] = -np.abs(w[:, 1]) - 0.05
+    w = (w / np.linalg.norm(w, axis=1, keepdims=True)).astype(np.float32)
+    rgb, vis, _ = O.render(om, oe, O.sampling(1, 8, 7, O.DIFFUSE_ONLY | O.HARD_VIS), x, dirs=w, indirect=True)
+    assert np.all(vis == 0)
+    aa = 1 / (1 + np.exp(-np.array([np.float32(logit(a)) for a in alb], np.float64)))
+    nr = np.array([np.float32(v) for v in n_raw], np.float64)
+    for p in range(n):
+        wd = w[p].astype(np.float64)
+        nb = nr / np.linalg.norm(nr) if np.linalg.norm(nr) > 0 else -wd
+        wj = O.sample_dirs(7, np.repeat(nb[None], 8, 0), p, 0, np.arange(8), 1, 8)
+        frac = np.mean(wj[:, 1] > 0)
+        if n_raw[1] > 0 and n_raw[0] == 0:
+            assert frac == 1.0
+        if n_raw[1] < 0:
+            assert frac == 0.0
+        assert np.allclose(rgb[p], aa * float(np.float32(Lc)) * frac, rtol=1e-12, atol=1e-15), (p, rgb[p])
+
+
+def test_paper_level_layout():
+    """The paper's encoder (Sec. 4.1): 14 levels from 16 to 131072 give the
+    growth factor 2 exactly, so N_l = 16 * 2^l; with T = 2^17 exactly the
+    first two levels are dense.  At the finest level a vertex position is
+    reproduced exactly (weights 0/1), and the hash of a vertex on an axis is
+    the coordinate times its prime, masked to T."""
+    res = H.level_resolutions(14, 16, 131072)
+    assert res == [16 << l for l in range(14)]
+    T = 1 << 17
+    assert [(N + 1) ** 3 <= T for N in res] == [True, True] + [False] * 12
+    m = small_model(L=14, log2T=17, res=res)
+    om = O.OracleModel(m, LO, EXT)
+    N = res[-1]
+    k = np.random.default_rng(6).integers(0, N + 1, (300, 3))
+    pos = (LO + EXT * k / N).astype(np.float32)
+    assert np.array_equal(pos.astype(np.float64), LO + EXT * k / N)   # exact in FP32
+    idx, w = O.encode_index(om, pos)
+    assert np.all(np.isin(w[:, 13], [0.0, 1.0]))
+    f = O.encode(om, pos)
+    corner = (w[:, 13, 0] == 1) * 1 + (w[:, 13, 1] == 1) * 2 + (w[:, 13, 2] == 1) * 4
+    assert np.array_equal(f[:, 26:28], m["table"][13][idx[np.arange(300), 13, corner]].astype(np.float64))
+    one = np.array([[LO + EXT * 7 / N, LO, LO], [LO, LO + EXT * 5 / N, LO]], np.float32)
+    i1, w1 = O.encode_index(om, one)
+    assert int(i1[0, 13, 0]) == 7 % T and int(i1[1, 13, 0]) == (5 * 2654435761 % 2 ** 32) % T
