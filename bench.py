@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--no-encode", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=3)
     ap.add_argument("--no-denoise", action="store_true")
+    ap.add_argument("--no-mis", action="store_true")
+    ap.add_argument("--no-paper", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -190,6 +192,51 @@ def main():
         mshm, _, _ = time_events(frame_hard("mixed"), args.steps, args.warmup, torch)
         out["hard_visibility"] = {"fp32_ms": msh32, "mixed_ms": mshm,
                                   "fp32_queries_per_s": S / (msh32 * 1e-3), "mixed_queries_per_s": S / (mshm * 1e-3)}
+
+    if not args.no_mis:
+        # MIS primary directions (light-importance + GGX visible-normal rays):
+        # the paper's one + one rays per pixel (vector-ALU kernel), and the
+        # 128-direction frame on the matrix cores
+        dist = hg.env_sampling(env_t)
+
+        def frame_mis(n, prec):
+            def f():
+                hg.render(r, env_t, pos_t, nrm_t, wo_t, n_dirs=n, n_dirs2=cfg.n_dirs2, seed=H.SEED_DIRS,
+                          indirect=True, flags=hg.HG_MIS, precision=prec, env_dist=dist, out=(rgb, None, None))
+            return f
+        print("[bench] MIS frames", file=sys.stderr, flush=True)
+        ms2, _, _ = time_events(frame_mis(2, "fp32"), args.steps, args.warmup, torch)
+        ms128, _, _ = time_events(frame_mis(cfg.n_dirs, "fp32"), args.steps, args.warmup, torch)
+        out["mis"] = {"paper_1plus1_fp32_ms": ms2, "paper_1plus1_fps": 1e3 / ms2,
+                      "paper_1plus1_queries_per_s": 2 * P / (ms2 * 1e-3),
+                      "n128_fp32_ms": ms128, "n128_fp32_queries_per_s": S / (ms128 * 1e-3)}
+        if not args.no_mixed:
+            ms128m, _, _ = time_events(frame_mis(cfg.n_dirs, "mixed"), args.steps, args.warmup, torch)
+            out["mis"]["n128_mixed_ms"] = ms128m
+            out["mis"]["n128_mixed_queries_per_s"] = S / (ms128m * 1e-3)
+        del dist
+
+    if not args.no_paper:
+        # the paper's model shape (14 levels, T = 2^17, res 16..131072, decoder
+        # normal head) on the same 800x800 frame
+        pcfg = H.config("paper")
+        rp = hg.HashRenderer(H.make_model(pcfg), dev)
+        rp.refresh_shadows()
+        pdist = hg.env_sampling(env_t)
+
+        def frame_paper(n, prec, flags=0):
+            def f():
+                hg.render(rp, env_t, pos_t, nrm_t, wo_t, n_dirs=n, n_dirs2=cfg.n_dirs2, seed=H.SEED_DIRS,
+                          indirect=True, flags=flags, precision=prec, env_dist=pdist, out=(rgb, None, None))
+            return f
+        print("[bench] paper-shape frames", file=sys.stderr, flush=True)
+        mp32, _, _ = time_events(frame_paper(cfg.n_dirs, "fp32"), args.steps, args.warmup, torch)
+        mpm, _, _ = time_events(frame_paper(cfg.n_dirs, "mixed"), args.steps, args.warmup, torch)
+        mpmis, _, _ = time_events(frame_paper(2, "fp32", hg.HG_MIS), args.steps, args.warmup, torch)
+        out["paper_shape"] = {"n128_fp32_ms": mp32, "n128_fp32_queries_per_s": S / (mp32 * 1e-3),
+                              "n128_mixed_ms": mpm, "n128_mixed_queries_per_s": S / (mpm * 1e-3),
+                              "mis_1plus1_fp32_ms": mpmis, "mis_1plus1_fps": 1e3 / mpmis}
+        del rp, pdist
 
     if not args.no_denoise:
         # spatial SVGF (5 a-trous iterations) on the FP32 frame, guided by the

@@ -64,7 +64,8 @@ typedef enum { HG_F32 = 0, HG_F16 = 1, HG_BF16 = 2 } hg_dtype;
                               (Sec. 4.1); needs hg_env.dist; forward only */
 
 /* Multi-resolution hash grid (Sec. 3.2, InstantNGP layout).
- * table: [L][T][F], T = 2^log2_T, entries FP32 or FP16.
+ * L in [1, 16] levels (16 in the benchmark model, 14 in the paper's, Sec. 4.1),
+ * F = 2, table: [L][T][F], T = 2^log2_T, entries FP32 or FP16.
  * res[l]: resolution N_l of level l (host-computed integers).
  * A position x maps to u = clamp((x - box_lo) / box_extent, 0, 1); the
  * subtraction is rounded to FP32 and box_extent is a power of two.  Level l
@@ -81,8 +82,13 @@ typedef struct {
     const void *table;
 } hg_grid;
 
-/* Three-layer ReLU MLP n_in -> n_hidden -> n_hidden -> n_out.
- * W[k]: [out][in] (FP32 or BF16), b[k]: [out] FP32. */
+/* Three-layer ReLU MLP n_in -> n_hidden -> n_hidden -> n_out (n_hidden = 64).
+ * W[k]: [out][in] (FP32 or BF16), b[k]: [out] FP32.
+ * Input layout: the renderer feeds the MLPs 16 level slots of F = 2 features
+ * whatever L is, so the decoder has n_in = 32 and the tracer n_in = 35
+ * (slots, then the direction).  With L < 16 the slots of levels L..15 carry
+ * zero features: the weight columns of those slots have no effect (callers
+ * store zeros there) and receive zero gradients. */
 typedef struct {
     int32_t n_in, n_hidden, n_out;
     hg_dtype dtype;
@@ -91,7 +97,9 @@ typedef struct {
 } hg_mlp;
 
 /* The hash renderer: grid, BRDF decoder B (outputs: albedo logits 0..2,
- * roughness logit 3 -> 0.09 + 0.91 sigmoid, metallic logit 4 -> sigmoid) and
+ * roughness logit 3 -> 0.09 + 0.91 sigmoid, metallic logit 4 -> sigmoid;
+ * n_out = 8 adds the paper's normal head, outputs 5..7 -> n / |n|, which
+ * orients the bounce point's hemisphere and BRDF, forward only) and
  * tracer I (input [f, w]; output 0 -> visibility sigmoid, output 1 -> depth
  * d = min(softplus, 1), t = t_near + (t_far - t_near) d).  f0 is the
  * dielectric Fresnel reflectance (0.04 in the paper, Sec. 5). */
@@ -181,7 +189,8 @@ hg_status hg_render_direct(const hg_model *model, const hg_env *env, const hg_sa
 /* Direct + one indirect bounce ("d+id" rows of Table 3): the incoming
  * radiance of Eq. (2), L_in = V L_env(w) + (1 - V) L'_o, with
  * L'_o = 1/N' sum_j pi f_r(x'; w'_j, -w) V'_j L_env(w'_j) at
- * x' = x + t w, (a', r', m') = B(H(x')), facing normal n' = -w,
+ * x' = x + t w, (a', r', m') = B(H(x')), normal n' = -w (facing) or the
+ * decoder's normal head, view -w,
  * V'_j = sigmoid(I(H(x'), w'_j)_0) (Sec. 3.1, Sec. 3.2 "Overview").
  * Outputs as for hg_render_direct; in query mode rgb = L_in. */
 hg_status hg_render_indirect(const hg_model *model, const hg_env *env, const hg_sampling *samp,

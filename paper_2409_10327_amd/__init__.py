@@ -134,8 +134,13 @@ class HashRenderer:
                  t_far=1.5, f0=0.04):
         self.device = torch.device(device)
         self.table = _f32c(params["table"], self.device)
+        L = self.table.shape[0]
+        # the kernels read 16 level slots: first-layer columns of the slots of
+        # missing levels are zero (the layout the C ABI documents)
         self.brdf = [_f32c(a, self.device) for a in params["brdf"]]
         self.irt = [_f32c(a, self.device) for a in params["irt"]]
+        self.brdf[0] = self._slot_cols(self.brdf[0], L, 0)
+        self.irt[0] = self._slot_cols(self.irt[0], L, 3)
         self.res = [int(r) for r in params["res"]]
         self.box_lo, self.box_extent = float(box_lo), float(box_extent)
         self.t_near, self.t_far, self.f0 = float(t_near), float(t_far), float(f0)
@@ -146,6 +151,27 @@ class HashRenderer:
     @property
     def L(self):
         return self.table.shape[0]
+
+    @staticmethod
+    def _slot_cols(W0, L, n_dir):
+        """[64][2L + n_dir] -> [64][32 + n_dir]: features into their level
+        slots, the direction columns after the 32 slots."""
+        if W0.shape[1] == 32 + n_dir:
+            return W0.contiguous()
+        out = torch.zeros((W0.shape[0], 32 + n_dir), device=W0.device, dtype=W0.dtype)
+        out[:, :2 * L] = W0[:, :2 * L]
+        out[:, 32:] = W0[:, 2 * L:]
+        return out
+
+    def natural(self, mlp_list, which):
+        """Undo the slot layout of a first-layer weight (or its gradient):
+        returns the list with W0 as [64][2L (+3)]."""
+        L = self.L
+        W0 = mlp_list[0]
+        n_dir = 3 if which == "irt" else 0
+        if W0.shape[1] == 2 * L + n_dir:
+            return list(mlp_list)
+        return [torch.cat([W0[:, :2 * L], W0[:, 32:]], 1)] + list(mlp_list[1:])
 
     def refresh_shadows(self):
         self.table16 = self.table.to(torch.float16)

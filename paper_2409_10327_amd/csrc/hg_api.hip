@@ -62,7 +62,7 @@ hg_status check_ptr(const void *p, const char *name, size_t align = 16) {
 hg_status check_grid(const hg_grid *g, hg::GridK &k) {
     REQUIRE(g != nullptr, "grid is NULL");
     SUPPORT(g->F == hg::kF, "F = %d (only F = 2 is built)", g->F);
-    SUPPORT(g->L == hg::kL, "L = %d (only L = 16 is built)", g->L);
+    SUPPORT(g->L >= 1 && g->L <= hg::kL, "L = %d outside [1, 16]", g->L);
     REQUIRE(g->log2_T >= 10 && g->log2_T <= 24, "log2_T = %d outside [10, 24]", g->log2_T);
     REQUIRE(std::isfinite(g->box_lo), "box_lo is not finite");
     int ex = 0;
@@ -72,6 +72,7 @@ hg_status check_grid(const hg_grid *g, hg::GridK &k) {
     CHECK(check_ptr(g->table, "grid.table"));
     const uint64_t T = uint64_t(1) << g->log2_T;
     k.table = g->table;
+    k.L = (uint32_t)g->L;
     k.log2T = (uint32_t)g->log2_T;
     k.Tmask = (uint32_t)(T - 1);
     k.lo = g->box_lo;
@@ -87,6 +88,12 @@ hg_status check_grid(const hg_grid *g, hg::GridK &k) {
         k.stride[l] = (uint32_t)(N + 1);
         const uint64_t s = (uint64_t)N + 1;
         if (s * s * s <= T) k.dense_mask |= 1u << l;
+    }
+    for (int l = g->L; l < hg::kL; ++l) {  // unused slots
+        k.resf[l] = 2.0f;
+        k.nm1f[l] = 1.0f;
+        k.dscale[l] = 0.0f;
+        k.stride[l] = 3;
     }
     return HG_OK;
 }
@@ -114,7 +121,10 @@ enum class Prec { F32, Mixed, F16TableF32Mlp };
 hg_status check_model(const hg_model *m, hg::RenderK &k, Prec &prec) {
     REQUIRE(m != nullptr, "model is NULL");
     CHECK(check_grid(&m->grid, k.g));
-    CHECK(check_mlp(&m->brdf, "brdf", hg::kNF, 5, k.brdf));
+    SUPPORT(m->brdf.n_out == 5 || m->brdf.n_out == 8, "brdf n_out = %d (5, or 8 with the normal head)",
+            m->brdf.n_out);
+    CHECK(check_mlp(&m->brdf, "brdf", hg::kNF, m->brdf.n_out, k.brdf));
+    k.brdf_out = m->brdf.n_out;
     CHECK(check_mlp(&m->irt, "irt", hg::kNI, 2, k.irt));
     REQUIRE(m->brdf.dtype == m->irt.dtype, "brdf and irt must share a dtype");
     if (m->grid.dtype == HG_F32 && m->brdf.dtype == HG_F32) prec = Prec::F32;
@@ -306,6 +316,7 @@ hg_status hg_backward(const hg_model *model, const hg_env *env, const hg_samplin
     CHECK(check_sampling(samp, false, k.r.s));
     SUPPORT(prec != Prec::Mixed, "hg_backward needs FP32 MLP weights (the masters)");
     SUPPORT((samp->flags & (HG_HARD_VIS | HG_MIS)) == 0, "hard visibility and MIS are forward-only modes");
+    SUPPORT(model->brdf.n_out == 5, "the decoder's normal head is forward-only (hg_backward needs n_out = 5)");
     REQUIRE(indirect == 0 || indirect == 1, "indirect must be 0 or 1");
     if (pts->n == 0) return HG_OK;
     CHECK(check_ptr(g_rgb, "g_rgb"));

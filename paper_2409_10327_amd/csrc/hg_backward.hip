@@ -143,6 +143,7 @@ __device__ __forceinline__ void encode_bwd(const GridK &g, float x, float y, flo
     float gxx = 0.f, gxy = 0.f, gxz = 0.f;
 #pragma unroll
     for (int l = 0; l < kL; ++l) {
+        if (l >= (int)g.L) break;  // wave-uniform
         uint32_t c[3];
         float w[3];
 #pragma unroll

@@ -23,6 +23,7 @@ constexpr float kPi = 3.14159265358979323846f;
 // --------------------------------------------------------------------------
 struct GridK {
     const void *table;      // [L][T][F] FP32 or FP16
+    uint32_t L;             // levels (<= kL); feature slots of levels >= L are zero
     uint32_t log2T, Tmask;
     float lo, inv_ext;      // u = (x - lo) * inv_ext, inv_ext = 2^-k
     float resf[kL];         // N_l as float (exact)
@@ -64,6 +65,7 @@ struct RenderK {
     EnvK env;
     SampK s;
     float t_near, t_span, f0;
+    int32_t brdf_out;       // 5, or 8 with the decoder's normal head
     const float *pos, *nrm, *wo, *dir;
     float *rgb, *vis, *depth;
     int64_t n;
@@ -271,23 +273,26 @@ __device__ __forceinline__ void encode(const GridK &g, float x, float y, float z
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int l = l0; l < l0 + 4; ++l) {
-            uint32_t c[3];
-            float w[3];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) cell_of(u[d], g.resf[l], g.nm1f[l], c[d], w[d]);
-            uint32_t idx[8];
-            corner_idx(g, l, c, idx);
-            const void *lvl = TabLoad<TT>::level(g.table, l, g.log2T);
-            float2 e[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) e[k] = TabLoad<TT>::ld(lvl, idx[k]);
-            const float wx0 = 1.0f - w[0], wy0 = 1.0f - w[1], wz0 = 1.0f - w[2];
             float f0 = 0.0f, f1 = 0.0f;
+            if (l < (int)g.L) {  // wave-uniform
+                uint32_t c[3];
+                float w[3];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const float wt = ((k & 1) ? w[0] : wx0) * (((k >> 1) & 1) ? w[1] : wy0) * (((k >> 2) & 1) ? w[2] : wz0);
-                f0 = fmaf(wt, e[k].x, f0);
-                f1 = fmaf(wt, e[k].y, f1);
+                for (int d = 0; d < 3; ++d) cell_of(u[d], g.resf[l], g.nm1f[l], c[d], w[d]);
+                uint32_t idx[8];
+                corner_idx(g, l, c, idx);
+                const void *lvl = TabLoad<TT>::level(g.table, l, g.log2T);
+                float2 e[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) e[k] = TabLoad<TT>::ld(lvl, idx[k]);
+                const float wx0 = 1.0f - w[0], wy0 = 1.0f - w[1], wz0 = 1.0f - w[2];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const float wt =
+                        ((k & 1) ? w[0] : wx0) * (((k >> 1) & 1) ? w[1] : wy0) * (((k >> 2) & 1) ? w[2] : wz0);
+                    f0 = fmaf(wt, e[k].x, f0);
+                    f1 = fmaf(wt, e[k].y, f1);
+                }
             }
             f[2 * l] = f0;
             f[2 * l + 1] = f1;
@@ -412,6 +417,15 @@ __device__ __forceinline__ float3 pi_brdf(float3 n, float3 v, float3 l, float3 a
                        (1.0f - m) * a.z + s * (F0z * q + t.P));
 }
 
+// Unit normal from the decoder's normal head (n / |n|); `fallback` when the
+// head outputs the zero vector.
+__device__ __forceinline__ float3 head_normal(float x, float y, float z, float3 fallback) {
+    const float nn = x * x + y * y + z * z;
+    if (!(nn > 0.0f)) return fallback;
+    const float inv = rsqrtf(nn);
+    return make_float3(x * inv, y * inv, z * inv);
+}
+
 // pi * f_r at a surface seen along its own normal (v = n, the bounce point's
 // facing reading): NdotV = 1, |l + n|^2 = 2 (1 + NdotL), so
 // NdotH^2 = VdotH^2 = (1 + NdotL) / 2 and the view term of the
@@ -484,7 +498,7 @@ __device__ __forceinline__ void load_col(const float *hbuf, int lane, float (&h)
 // Returns the last hidden layer in h (registers) and the outputs in out.
 template <int NIN, int NOUT, typename WT>
 __device__ __forceinline__ void mlp_fwd(const MlpK &m, const float (&in)[NIN], float *h1buf, float *h2buf, int lane,
-                                        float (&h)[kH], float (&out)[NOUT]) {
+                                        float (&h)[kH], float (&out)[NOUT], int nout = NOUT) {
     layer_to_lds<NIN, WT, true>(m.W0, m.b0, kH, in, h1buf, lane);
     load_col(h1buf, lane, h);
     layer_to_lds<kH, WT, true>(m.W1, m.b1, kH, h, h2buf, lane);
@@ -493,9 +507,12 @@ __device__ __forceinline__ void mlp_fwd(const MlpK &m, const float (&in)[NIN], f
     const BPtr b2(m.b2);
 #pragma unroll
     for (int o = 0; o < NOUT; ++o) {
-        float acc = b2[o];
+        float acc = 0.0f;
+        if (o < nout) {  // wave-uniform: rows past the weight matrix are zero
+            acc = b2[o];
 #pragma unroll
-        for (int i = 0; i < kH; ++i) acc = fmaf(W2[o * kH + i], h[i], acc);
+            for (int i = 0; i < kH; ++i) acc = fmaf(W2[o * kH + i], h[i], acc);
+        }
         out[o] = acc;
     }
 }

@@ -15,8 +15,8 @@ template <typename TT>
 __global__ __launch_bounds__(256) void k_encode(const GridK g, const float *__restrict__ pos, int64_t n,
                                                 float *__restrict__ feat) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t p = t >> 4;
-    const int l = (int)(t & 15);
+    const int64_t p = g.L == 16 ? (t >> 4) : t / g.L;
+    const int l = (int)(t - p * g.L);
     if (p >= n) return;
     float u[3];
     bool in[3];
@@ -39,11 +39,11 @@ __global__ __launch_bounds__(256) void k_encode(const GridK g, const float *__re
         f0 = fmaf(wt, e[k].x, f0);
         f1 = fmaf(wt, e[k].y, f1);
     }
-    reinterpret_cast<float2 *>(feat)[p * kL + l] = make_float2(f0, f1);
+    reinterpret_cast<float2 *>(feat)[t] = make_float2(f0, f1);
 }
 
 hipError_t launch_encode(const GridK &g, bool f16, const float *pos, int64_t n, float *feat, hipStream_t s) {
-    const int64_t threads = n * kL;
+    const int64_t threads = n * g.L;
     const unsigned blocks = (unsigned)((threads + 255) / 256);
     if (f16)
         hipLaunchKernelGGL(k_encode<__half>, dim3(blocks), dim3(256), 0, s, g, pos, n, feat);
@@ -56,8 +56,8 @@ hipError_t launch_encode(const GridK &g, bool f16, const float *pos, int64_t n, 
 __global__ __launch_bounds__(256) void k_encode_index(const GridK g, const float *__restrict__ pos, int64_t n,
                                                       uint32_t *__restrict__ idx, float *__restrict__ wout) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t p = t >> 4;
-    const int l = (int)(t & 15);
+    const int64_t p = g.L == 16 ? (t >> 4) : t / g.L;
+    const int l = (int)(t - p * g.L);
     if (p >= n) return;
     float u[3];
     bool in[3];
@@ -69,15 +69,15 @@ __global__ __launch_bounds__(256) void k_encode_index(const GridK g, const float
     uint32_t ix[8];
     corner_idx(g, l, c, ix);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) idx[(p * kL + l) * 8 + k] = ix[k];
+    for (int k = 0; k < 8; ++k) idx[t * 8 + k] = ix[k];
     if (wout) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) wout[(p * kL + l) * 3 + d] = w[d];
+        for (int d = 0; d < 3; ++d) wout[t * 3 + d] = w[d];
     }
 }
 
 hipError_t launch_encode_index(const GridK &g, const float *pos, int64_t n, uint32_t *idx, float *w, hipStream_t s) {
-    const int64_t threads = n * kL;
+    const int64_t threads = n * g.L;
     const unsigned blocks = (unsigned)((threads + 255) / 256);
     hipLaunchKernelGGL(k_encode_index, dim3(blocks), dim3(256), 0, s, g, pos, n, idx, w);
     return hipGetLastError();
@@ -106,12 +106,16 @@ __device__ __forceinline__ void incoming(const RenderK &a, const float (&f)[kNF]
     const float3 xb = make_float3(fmaf(t, w.x, x.x), fmaf(t, w.y, x.y), fmaf(t, w.z, x.z));
     float fb[kNF];
     encode<float>(a.g, xb.x, xb.y, xb.z, fb);
-    float ob[5];
-    mlp_fwd<kNF, 5, float>(a.brdf, fb, hbuf, hbuf, lane, h, ob);
+    float ob[8];
+    mlp_fwd<kNF, 8, float>(a.brdf, fb, hbuf, hbuf, lane, h, ob, a.brdf_out);
     const float3 ab = make_float3(sigmoidf_(ob[0]), sigmoidf_(ob[1]), sigmoidf_(ob[2]));
     const float rb = 0.09f + 0.91f * sigmoidf_(ob[3]);
     const float mb = sigmoidf_(ob[4]);
-    const float3 nb = make_float3(-w.x, -w.y, -w.z);
+    // secondary view -w; normal from the decoder's normal head if it has one,
+    // else the facing normal -w
+    const float3 vb = make_float3(-w.x, -w.y, -w.z);
+    const bool nhead = a.brdf_out == 8;
+    const float3 nb = nhead ? head_normal(ob[5], ob[6], ob[7], vb) : vb;
     const Frame fr = make_frame(nb);
     const bool diffuse = (a.s.flags & 1u) != 0;
     FacingBrdf fb_;
@@ -127,7 +131,7 @@ __device__ __forceinline__ void incoming(const RenderK &a, const float (&f)[kNF]
         mlp_fwd<kNI, 2, float>(a.irt, z, hbuf, hbuf, lane, h, o);
         const float vj = hard ? (o[0] > 0.0f ? 1.0f : 0.0f) : sigmoidf_(o[0]);
         const float3 Ej = env_lookup(a.env, wj.x, wj.y, wj.z);
-        const float3 c = fb_.eval(dot3(nb, wj));
+        const float3 c = nhead ? pi_brdf(nb, vb, wj, ab, rb, mb, a.f0, diffuse) : fb_.eval(dot3(nb, wj));
         Lx = fmaf(c.x * vj, Ej.x, Lx);
         Ly = fmaf(c.y * vj, Ej.y, Ly);
         Lz = fmaf(c.z * vj, Ej.z, Lz);

@@ -138,7 +138,7 @@ struct Bf16Path {
             return wbf(a.brdf.W1, (16 * m + i) * kH + unit_bf16(s, g, e));
         }
         if (t < B_W2B) return wbf(a.brdf.W2, (i & 3) * kH + unit_bf16(t - B_W2A, g, e));
-        return (i & 3) == 0 ? wbf(a.brdf.W2, 4 * kH + unit_bf16(t - B_W2B, g, e)) : 0.0f;
+        return 4 + (i & 3) < a.brdf_out ? wbf(a.brdf.W2, (4 + (i & 3)) * kH + unit_bf16(t - B_W2B, g, e)) : 0.0f;
     }
 
     static __device__ void build_tiles(const RenderK &a, Tile *tiles) {
@@ -210,7 +210,7 @@ struct Bf16Path {
         const uint4 k0 = act_pack(d[0], d[1]), k1 = act_pack(d[2], d[3]);
         oa = mfma_bf16(tiles[B_W2A * 64 + lane], k0, head_bias(a.brdf.b2, 5, 0));
         oa = mfma_bf16(tiles[(B_W2A + 1) * 64 + lane], k1, oa);
-        ob = mfma_bf16(tiles[B_W2B * 64 + lane], k0, head_bias(a.brdf.b2, 5, 4));
+        ob = mfma_bf16(tiles[B_W2B * 64 + lane], k0, head_bias(a.brdf.b2, a.brdf_out, 4));
         ob = mfma_bf16(tiles[(B_W2B + 1) * 64 + lane], k1, ob);
     }
 
@@ -345,14 +345,15 @@ struct F32Path {
             for (int m = 0; m < 4; ++m) e[m] = mfma_f32(W1[(16 * m + i) * kH + u], b, e[m]);
         }
         oa = head_bias(a.brdf.b2, 5, 0);
-        ob = head_bias(a.brdf.b2, 5, 4);
+        ob = head_bias(a.brdf.b2, a.brdf_out, 4);
         const int r = i & 3;
+        const bool rb = 4 + r < a.brdf_out;
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
             const float b = fmaxf(e[s >> 2][s & 3], 0.0f);
             const int u = unit_f32(s, g);
             oa = mfma_f32(W2[r * kH + u], b, oa);
-            ob = mfma_f32(r == 0 ? W2[4 * kH + u] : 0.0f, b, ob);
+            ob = mfma_f32(rb ? W2[(4 + r) * kH + u] : 0.0f, b, ob);
         }
     }
 
@@ -395,7 +396,7 @@ __device__ __forceinline__ float3 bounce_lo(const RenderK &a, const typename PP:
     PP::store_feat(W, lane, fb);
     wave_sync_lds();
     f32x4 bpt[4][4];
-    float ob0 = 0.f, ob1 = 0.f, ob2 = 0.f, ob3 = 0.f, ob4 = 0.f;
+    float ob0 = 0.f, ob1 = 0.f, ob2 = 0.f, ob3 = 0.f, ob4 = 0.f, on0 = 0.f, on1 = 0.f, on2 = 0.f;
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
         f32x4 d[4];
@@ -406,12 +407,17 @@ __device__ __forceinline__ float3 bounce_lo(const RenderK &a, const typename PP:
         PP::decoder(tiles, a, W, nt, lane, g, oa, obb);
         if (g == nt) {
             ob0 = oa[0]; ob1 = oa[1]; ob2 = oa[2]; ob3 = oa[3]; ob4 = obb[0];
+            on0 = obb[1]; on1 = obb[2]; on2 = obb[3];
         }
     }
     const float3 ab = make_float3(sigmoidf_(ob0), sigmoidf_(ob1), sigmoidf_(ob2));
     const float rb = 0.09f + 0.91f * sigmoidf_(ob3);
     const float mb = sigmoidf_(ob4);
-    const float3 nb = make_float3(-w.x, -w.y, -w.z);
+    // secondary view -w; normal from the decoder's normal head if it has one,
+    // else the facing normal -w
+    const float3 vb = make_float3(-w.x, -w.y, -w.z);
+    const bool nhead = a.brdf_out == 8;
+    const float3 nb = nhead ? head_normal(on0, on1, on2, vb) : vb;
     const Frame frb = make_frame(nb);
     FacingBrdf fb_;
     fb_.set(ab, rb, mb, a.f0, diffuse);
@@ -433,7 +439,7 @@ __device__ __forceinline__ float3 bounce_lo(const RenderK &a, const typename PP:
         // hard visibility: only visible secondary rays contribute
         const float vj = hard ? (vo > 0.0f ? 1.0f : 0.0f) : sigmoidf_(vo);
         const float3 Ej = env_lookup(a.env, wj.x, wj.y, wj.z);
-        const float3 c = fb_.eval(dot3(nb, wj));
+        const float3 c = nhead ? pi_brdf(nb, vb, wj, ab, rb, mb, a.f0, diffuse) : fb_.eval(dot3(nb, wj));
         Lx = fmaf(c.x * vj, Ej.x, Lx);
         Ly = fmaf(c.y * vj, Ej.y, Ly);
         Lz = fmaf(c.z * vj, Ej.z, Lz);
@@ -499,7 +505,7 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mma(const RenderK a, int
             const int slot = lane >> 4, lvl = lane & 15;
             const int64_t ps_raw = item * ppw + slot;
             const int64_t ps = ps_raw < a.n ? ps_raw : a.n - 1;
-            if (slot < ppw) {
+            if (slot < ppw && lvl < (int)a.g.L) {
                 float u[3];
                 bool in[3];
                 pos_to_u(a.g, a.pos[3 * ps], a.pos[3 * ps + 1], a.pos[3 * ps + 2], u, in);
@@ -520,6 +526,8 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mma(const RenderK a, int
                     f1 = fmaf(wt, e.y, f1);
                 }
                 PP::store_level(W, slot, lvl, f0, f1);
+            } else if (slot < ppw) {
+                PP::store_level(W, slot, lvl, 0.0f, 0.0f);  // slot of a level the grid does not have
             }
             wave_sync_lds();
             f32x4 oa, ob, ax[4];

@@ -61,7 +61,8 @@ def call_render(m=None, env=None, samp=None, pts=None, rgb=FAKE):
 
 @pytest.mark.parametrize("field,value,status", [
     ("grid.F", 3, hg.HG_E_UNSUPPORTED),
-    ("grid.L", 14, hg.HG_E_UNSUPPORTED),
+    ("grid.L", 17, hg.HG_E_UNSUPPORTED),
+    ("grid.L", 0, hg.HG_E_UNSUPPORTED),
     ("grid.log2_T", 9, hg.HG_E_INVALID),
     ("grid.log2_T", 25, hg.HG_E_INVALID),
     ("grid.box_extent", 12.0, hg.HG_E_INVALID),
@@ -73,6 +74,22 @@ def call_render(m=None, env=None, samp=None, pts=None, rgb=FAKE):
 def test_model_validation(field, value, status):
     assert call_render(fake_model(**{field: value})) == status
     assert hg.lib().hg_last_error().decode() != ""
+
+
+def test_brdf_outputs_and_normal_head():
+    m = fake_model()
+    m.brdf.n_out = 6
+    assert call_render(m) == hg.HG_E_UNSUPPORTED
+    m = fake_model()
+    m.brdf.n_out = 8
+    env = hg.Env(); env.H, env.W, env.rgb = 16, 32, FAKE
+    s = hg.sampling_struct(1, 8, 7, 0)
+    q = hg.Points(); q.n, q.pos, q.nrm, q.wo, q.dir = 10, FAKE, None, None, FAKE
+    gb = (C.c_void_p * 6)(*[FAKE] * 6)
+    f = C.c_void_p(FAKE)
+    # the normal head is forward only
+    assert hg.lib().hg_backward(C.byref(m), C.byref(env), C.byref(s), C.byref(q), 1, f, f, f, f, gb, gb, None,
+                                None) == hg.HG_E_UNSUPPORTED
 
 
 def test_mlp_shape_and_dtype_pairs():
