@@ -96,6 +96,18 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Weight pointers the tile builders read, copied out of the kernel argument
+// once: selecting among them then selects values, never addresses inside
+// the argument block (which would make the compiler copy the whole block to
+// private memory).
+struct WSrc {
+    const void *iW0, *iW1, *iW2, *bW0, *bW1, *bW2;
+    int nout;
+};
+__device__ __forceinline__ WSrc wsrc(const RenderK &a) {
+    return WSrc{a.irt.W0, a.irt.W1, a.irt.W2, a.brdf.W0, a.brdf.W1, a.brdf.W2, a.brdf_out};
+}
+
 // ============================================================================
 // Mixed path: BF16 operands, K = 32 per matrix-core step.
 // ============================================================================
@@ -117,31 +129,32 @@ struct Bf16Path {
         float qd[128];    // and normalised depth
     };
 
-    static __device__ float tile_value(const RenderK &a, int t, int i, int g, int e) {
+    static __device__ __forceinline__ float tile_value(const WSrc &a, int t, int i, int g, int e) {
         if (t < T_W0F) {
             const int m = t - T_W0W;
             if (g != 0 || e >= 6) return 0.0f;
-            return wbf(a.irt.W0, (16 * m + i) * kNI + kNF + (e % 3));
+            return wbf(a.iW0, (16 * m + i) * kNI + kNF + (e % 3));
         }
-        if (t < T_W1) return wbf(a.irt.W0, (16 * (t - T_W0F) + i) * kNI + 8 * g + e);
+        if (t < T_W1) return wbf(a.iW0, (16 * (t - T_W0F) + i) * kNI + 8 * g + e);
         if (t < T_W2) {
             const int m = (t - T_W1) >> 1, s = (t - T_W1) & 1;
-            return wbf(a.irt.W1, (16 * m + i) * kH + unit_bf16(s, g, e));
+            return wbf(a.iW1, (16 * m + i) * kH + unit_bf16(s, g, e));
         }
         if (t < B_W0) {
             const int s = t - T_W2, r = i & 3;
-            return r < 2 ? wbf(a.irt.W2, r * kH + unit_bf16(s, g, e)) : 0.0f;
+            return r < 2 ? wbf(a.iW2, r * kH + unit_bf16(s, g, e)) : 0.0f;
         }
-        if (t < B_W1) return wbf(a.brdf.W0, (16 * (t - B_W0) + i) * kNF + 8 * g + e);
+        if (t < B_W1) return wbf(a.bW0, (16 * (t - B_W0) + i) * kNF + 8 * g + e);
         if (t < B_W2A) {
             const int m = (t - B_W1) >> 1, s = (t - B_W1) & 1;
-            return wbf(a.brdf.W1, (16 * m + i) * kH + unit_bf16(s, g, e));
+            return wbf(a.bW1, (16 * m + i) * kH + unit_bf16(s, g, e));
         }
-        if (t < B_W2B) return wbf(a.brdf.W2, (i & 3) * kH + unit_bf16(t - B_W2A, g, e));
-        return 4 + (i & 3) < a.brdf_out ? wbf(a.brdf.W2, (4 + (i & 3)) * kH + unit_bf16(t - B_W2B, g, e)) : 0.0f;
+        if (t < B_W2B) return wbf(a.bW2, (i & 3) * kH + unit_bf16(t - B_W2A, g, e));
+        return 4 + (i & 3) < a.nout ? wbf(a.bW2, (4 + (i & 3)) * kH + unit_bf16(t - B_W2B, g, e)) : 0.0f;
     }
 
-    static __device__ void build_tiles(const RenderK &a, Tile *tiles) {
+    static __device__ __forceinline__ void build_tiles(const RenderK &ka, Tile *tiles) {
+        const WSrc a = wsrc(ka);
         for (int q = threadIdx.x; q < N_TILES * 64; q += blockDim.x) {
             const int t = q >> 6, l = q & 63, i = l & 15, g = l >> 4;
             uint32_t w[4];
@@ -259,24 +272,25 @@ struct F32Path {
         float qd[128];
     };
 
-    static __device__ float tile_value(const RenderK &a, int t, int i, int g) {
+    static __device__ __forceinline__ float tile_value(const WSrc &a, int t, int i, int g) {
         if (t < T_W0F) {
             const int m = t - T_W0W;
-            return g < 3 ? wf(a.irt.W0, (16 * m + i) * kNI + kNF + g) : 0.0f;
+            return g < 3 ? wf(a.iW0, (16 * m + i) * kNI + kNF + g) : 0.0f;
         }
         if (t < T_W1) {
             const int m = (t - T_W0F) >> 3, s = (t - T_W0F) & 7;
-            return wf(a.irt.W0, (16 * m + i) * kNI + 4 * s + g);
+            return wf(a.iW0, (16 * m + i) * kNI + 4 * s + g);
         }
         if (t < T_W2) {
             const int m = (t - T_W1) >> 4, s = (t - T_W1) & 15;
-            return wf(a.irt.W1, (16 * m + i) * kH + unit_f32(s, g));
+            return wf(a.iW1, (16 * m + i) * kH + unit_f32(s, g));
         }
         const int s = t - T_W2, r = i & 3;
-        return r < 2 ? wf(a.irt.W2, r * kH + unit_f32(s, g)) : 0.0f;
+        return r < 2 ? wf(a.iW2, r * kH + unit_f32(s, g)) : 0.0f;
     }
 
-    static __device__ void build_tiles(const RenderK &a, Tile *tiles) {
+    static __device__ __forceinline__ void build_tiles(const RenderK &ka, Tile *tiles) {
+        const WSrc a = wsrc(ka);
         for (int q = threadIdx.x; q < N_TILES * 64; q += blockDim.x) {
             const int t = q >> 6, l = q & 63;
             tiles[q] = tile_value(a, t, l & 15, l >> 4);

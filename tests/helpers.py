@@ -48,3 +48,46 @@ def adversarial_positions(res, n_random=20000, seed=0):
         pts.append(np.nextafter(v.astype(np.float32), np.float32(np.inf)))
     pts.append(np.array([[H.BOX_LO] * 3, [H.BOX_LO + H.BOX_EXTENT] * 3, [0.0, 0.0, 0.0]]))
     return np.concatenate([np.asarray(p, np.float32) for p in pts]).astype(np.float32)
+
+
+def kink_margin(model, pos, dirs, dep, indirect, seed=7, n_dirs2=8):
+    """Per query-mode sample, the smallest relative distance to a kink of the
+    network in FP64: every ReLU pre-activation p over |W||z| + |b| (for the
+    tracer at (x, w), and with the bounce the decoder at x' and the tracer at
+    (x', w'_j)), and the depth clamp |softplus - 1|.  Where it is within FP32
+    rounding (~1e-5) the FP32 and FP64 sides may take different branches and
+    the gradient jumps, so gradient parity excludes those samples.  Uses the
+    oracle's encodings and depths (dep) and the 5-output decoder's facing
+    normal."""
+    import hg_inputs as H
+    from oracle import oracle as O
+    om = O.OracleModel(model, H.BOX_LO, H.BOX_EXTENT)
+    irt = [a.astype(np.float64) for a in model["irt"]]
+    brdf = [a.astype(np.float64) for a in model["brdf"]]
+
+    def margins(m, z):  # z [n, k]
+        p1 = z @ m[0].T + m[1]
+        s1 = np.abs(z) @ np.abs(m[0]).T + np.abs(m[1]) + 1e-300
+        h1 = np.maximum(p1, 0)
+        p2 = h1 @ m[2].T + m[3]
+        s2 = h1 @ np.abs(m[2]).T + np.abs(m[3]) + 1e-300
+        out = np.maximum(h1 @ m[2].T + m[3], 0) @ m[4].T + m[5]
+        return np.minimum((np.abs(p1) / s1).min(1), (np.abs(p2) / s2).min(1)), out
+
+    n = pos.shape[0]
+    w = dirs.astype(np.float64)
+    f = O.encode(om, pos)
+    mg, o = margins(irt, np.concatenate([f, w], 1))
+    sp = np.logaddexp(0.0, o[:, 1])
+    mg = np.minimum(mg, np.abs(sp - 1.0))
+    if indirect:
+        t = 0.05 + 1.45 * np.asarray(dep, np.float64)
+        xb = pos.astype(np.float64) + t[:, None] * w
+        fb = O.encode_f64(om, xb)
+        m2, _ = margins(brdf, fb)
+        mg = np.minimum(mg, m2)
+        for j in range(n_dirs2):
+            wj = O.sample_dirs(seed, -w, np.arange(n), np.zeros(n), np.full(n, j), 1, n_dirs2)
+            m3, _ = margins(irt, np.concatenate([fb, wj], 1))
+            mg = np.minimum(mg, m3)
+    return mg

@@ -12,7 +12,7 @@ import torch
 import hg_inputs as H
 import paper_2409_10327_amd as hg
 from oracle import oracle as O
-from helpers import psnr, relerr
+from helpers import kink_margin, psnr, relerr
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -94,9 +94,18 @@ def test_full_batch_gradients(frame, B):
     tf, ta, tb = [[g["table"]] + g["brdf"] + g["irt"] for g in (full, ga, gb)]
     for a, b, c in zip(tf, ta, tb):
         assert relerr(a.cpu().numpy(), (b + c).cpu().numpy()) < 1e-5
-    ref = O.backward(frame["om"], frame["oe"], O.sampling(1, 8, H.SEED_DIRS, 0), pos[:k], dirs[:k], g_rgb[:k],
-                     g_vis[:k], g_dep[:k], indirect=True)
-    assert relerr(ga["table"].cpu().numpy(), ref["table"]) < 3e-5
+    # oracle on the head, without the samples within FP32 rounding of a
+    # network kink (their FP32 and FP64 gradients take different branches)
+    dep = O.render(frame["om"], frame["oe"], O.sampling(1, 8, H.SEED_DIRS, 0), pos[:k], dirs[:k])[2]
+    keep = (kink_margin(frame["model"], pos[:k], dirs[:k], dep, True) >= 1e-5).astype(np.float32)
+    gk = [g_rgb[:k] * keep[:, None], g_vis[:k] * keep, g_dep[:k] * keep]
+    gh = hg.zero_grads(r)
+    hg.backward(r, env_t, pos_t, dirs_t, T(np.concatenate([gk[0], np.zeros_like(g_rgb[k:])])),
+                T(np.concatenate([gk[1], np.zeros_like(g_vis[k:])])), T(np.concatenate([gk[2], np.zeros_like(g_dep[k:])])),
+                gh)
+    ref = O.backward(frame["om"], frame["oe"], O.sampling(1, 8, H.SEED_DIRS, 0), pos[:k], dirs[:k], *gk,
+                     indirect=True)
+    assert relerr(gh["table"].cpu().numpy(), ref["table"]) < 3e-5
     for kk in ("brdf", "irt"):
         for i in range(6):
-            assert relerr(ga[kk][i].cpu().numpy(), ref[kk][i]) < 3e-5
+            assert relerr(gh[kk][i].cpu().numpy(), ref[kk][i]) < 3e-5

@@ -7,7 +7,7 @@ import torch
 import hg_inputs as H
 import paper_2409_10327_amd as hg
 from oracle import oracle as O
-from helpers import relerr
+from helpers import kink_margin, relerr
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -36,6 +36,12 @@ def test_backward_parity(setup, indirect, n):
     g_rgb = rng.standard_normal((n, 3)).astype(np.float32)
     g_vis = rng.standard_normal(n).astype(np.float32)
     g_dep = rng.standard_normal(n).astype(np.float32)
+    # samples within FP32 rounding of a ReLU kink (or the depth clamp) take
+    # different branches in FP32 and FP64: their gradients are excluded
+    dep = O.render(setup["om"], setup["oe"], O.sampling(1, 8, 7, 0), pos, dirs=dirs, indirect=indirect)[2]
+    keep = (kink_margin(setup["model"], pos, dirs, dep, indirect) >= 1e-5).astype(np.float32)
+    print(f"{int(n - keep.sum())} of {n} samples within FP32 rounding of a kink")
+    g_rgb, g_vis, g_dep = g_rgb * keep[:, None], g_vis * keep, g_dep * keep
     grads = hg.zero_grads(setup["r"])
     g_pos = torch.empty((n, 3), device=DEV)
     hg.backward(setup["r"], setup["env_t"], t(pos), t(dirs), t(g_rgb), t(g_vis), t(g_dep), grads,
@@ -50,7 +56,8 @@ def test_backward_parity(setup, indirect, n):
                 assert np.all(a == 0) and np.all(b == 0)
                 continue
             assert relerr(a, b) < 1e-5, (k, i, relerr(a, b))
-    assert relerr(g_pos.cpu().numpy(), ref["pos"]) < 1e-5
+    k = keep > 0
+    assert relerr(g_pos.cpu().numpy()[k], ref["pos"][k]) < 1e-5
 
 
 def test_gpu_gradients_vs_central_differences(setup):
