@@ -279,6 +279,8 @@ def render(om: OracleModel, oe: OracleEnv, samp: Sampling, pos, nrm=None, wo=Non
     """Shade mode (dirs None): rgb [n,3], vis/depth [n,N].  Query mode:
     rgb [n,3], vis [n], depth [n].  pid: the points' ids in the sampler's
     counter (default 0..n-1), for evaluating a subset of a larger batch."""
+    if dirs is None and (nrm is None or wo is None):
+        raise ValueError("shade mode needs nrm and wo (pass dirs= for query mode)")
     P, keep = _points(pos, nrm, wo, dirs, pid)
     n = P.n
     rgb = np.empty((n, 3))

@@ -96,7 +96,7 @@ def test_full_batch_gradients(frame, B):
         assert relerr(a.cpu().numpy(), (b + c).cpu().numpy()) < 1e-5
     # oracle on the head, without the samples within FP32 rounding of a
     # network kink (their FP32 and FP64 gradients take different branches)
-    dep = O.render(frame["om"], frame["oe"], O.sampling(1, 8, H.SEED_DIRS, 0), pos[:k], dirs[:k])[2]
+    dep = O.render(frame["om"], frame["oe"], O.sampling(1, 8, H.SEED_DIRS, 0), pos[:k], dirs=dirs[:k])[2]
     keep = (kink_margin(frame["model"], pos[:k], dirs[:k], dep, True) >= 1e-5).astype(np.float32)
     gk = [g_rgb[:k] * keep[:, None], g_vis[:k] * keep, g_dep[:k] * keep]
     gh = hg.zero_grads(r)
