@@ -56,7 +56,9 @@ def kink_margin(model, pos, dirs, dep, indirect, seed=7, n_dirs2=8):
     tracer at (x, w), and with the bounce the decoder at x' and the tracer at
     (x', w'_j)), and the depth clamp |softplus - 1|.  Where it is within FP32
     rounding (~1e-5) the FP32 and FP64 sides may take different branches and
-    the gradient jumps, so gradient parity excludes those samples.  Uses the
+    the gradient jumps, so gradient parity excludes those samples.  With the
+    bounce, x' within 2e-4 cells of a cell face of any level also counts
+    (the FP32 x' is uncertain by ~1e-6 of the domain).  Uses the
     oracle's encodings and depths (dep) and the 5-output decoder's facing
     normal."""
     import hg_inputs as H
@@ -83,6 +85,13 @@ def kink_margin(model, pos, dirs, dep, indirect, seed=7, n_dirs2=8):
     if indirect:
         t = 0.05 + 1.45 * np.asarray(dep, np.float64)
         xb = pos.astype(np.float64) + t[:, None] * w
+        # the trilinear interpolation's spatial derivative (which carries the
+        # depth head's gradient) jumps at cell faces: distance of x' to the
+        # nearest face in cells, scaled so that 2e-4 cells maps to 1e-5
+        u = np.clip((xb - H.BOX_LO) / H.BOX_EXTENT, 0.0, 1.0)
+        for N in model["res"]:
+            p = u * N
+            mg = np.minimum(mg, np.abs(p - np.round(p)).min(1) * (1e-5 / 2e-4))
         fb = O.encode_f64(om, xb)
         m2, _ = margins(brdf, fb)
         mg = np.minimum(mg, m2)

@@ -94,10 +94,15 @@ def test_full_batch_gradients(frame, B):
     tf, ta, tb = [[g["table"]] + g["brdf"] + g["irt"] for g in (full, ga, gb)]
     for a, b, c in zip(tf, ta, tb):
         assert relerr(a.cpu().numpy(), (b + c).cpu().numpy()) < 1e-5
-    # oracle on the head, without the samples within FP32 rounding of a
-    # network kink (their FP32 and FP64 gradients take different branches)
+    # oracle on the head.  With the finest level at 2048 the depth path of the
+    # gradient carries the encoding's spatial derivative (2048/16 per unit),
+    # so the FP32 depth (a few 1e-7 relative) moves the gradients by ~3e-5
+    # even between kinks, and samples within 1e-4 of a kink can cross it:
+    # those are left out (margin 1e-4) and the bar is 5e-4: perturbing the
+    # depth by a relative 4e-7 / 1e-6 in a copy of the oracle moves the worst
+    # array by 1.9e-4 / 4.7e-4.
     dep = O.render(frame["om"], frame["oe"], O.sampling(1, 8, H.SEED_DIRS, 0), pos[:k], dirs=dirs[:k])[2]
-    keep = (kink_margin(frame["model"], pos[:k], dirs[:k], dep, True) >= 1e-5).astype(np.float32)
+    keep = (kink_margin(frame["model"], pos[:k], dirs[:k], dep, True) >= 1e-4).astype(np.float32)
     gk = [g_rgb[:k] * keep[:, None], g_vis[:k] * keep, g_dep[:k] * keep]
     gh = hg.zero_grads(r)
     hg.backward(r, env_t, pos_t, dirs_t, T(np.concatenate([gk[0], np.zeros_like(g_rgb[k:])])),
@@ -105,7 +110,7 @@ def test_full_batch_gradients(frame, B):
                 gh)
     ref = O.backward(frame["om"], frame["oe"], O.sampling(1, 8, H.SEED_DIRS, 0), pos[:k], dirs[:k], *gk,
                      indirect=True)
-    assert relerr(gh["table"].cpu().numpy(), ref["table"]) < 3e-5
+    assert relerr(gh["table"].cpu().numpy(), ref["table"]) < 5e-4
     for kk in ("brdf", "irt"):
         for i in range(6):
-            assert relerr(gh[kk][i].cpu().numpy(), ref[kk][i]) < 3e-5
+            assert relerr(gh[kk][i].cpu().numpy(), ref[kk][i]) < 5e-4

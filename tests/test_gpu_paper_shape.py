@@ -138,7 +138,11 @@ def test_backward_14_levels(ps, res_max, indirect):
     g_dep = rng.standard_normal(n).astype(np.float32)
     om5 = O.OracleModel(m5, H.BOX_LO, H.BOX_EXTENT)
     dep = O.render(om5, ps["oe"], O.sampling(1, 8, 7, 0), pos, dirs=dirs, indirect=indirect)[2]
-    keep = (kink_margin(m5, pos, dirs, dep, indirect) >= 1e-5).astype(np.float32)
+    # indirect with the finest level at 2048: margin 1e-4 and bar 3e-4 (a
+    # relative depth perturbation of 4e-7 / 1e-6 in a copy of the oracle
+    # moves the worst array by 8.5e-5 / 2.1e-4); the direct path keeps 1e-5
+    thr = 1e-4 if indirect else 1e-5
+    keep = (kink_margin(m5, pos, dirs, dep, indirect) >= thr).astype(np.float32)
     g_rgb, g_vis, g_dep = g_rgb * keep[:, None], g_vis * keep, g_dep * keep
     t = ps["t"]
     grads = hg.zero_grads(r5)
@@ -151,7 +155,7 @@ def test_backward_14_levels(ps, res_max, indirect):
     if indirect and res_max > 2048:
         assert e < 0.25
         return
-    tol = TOL_DIRECT
+    tol = 3e-4 if indirect else TOL_DIRECT
     assert e < tol
     for k in ("brdf", "irt"):
         for i in range(6):
