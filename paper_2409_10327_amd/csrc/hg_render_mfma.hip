@@ -440,6 +440,8 @@ __device__ __forceinline__ float3 bounce_lo(const RenderK &a, const typename PP:
     for (uint32_t j = 0; j < a.s.n_dirs2; ++j) {
         if ((j & 3u) == 0) words2 = philox4x32_10(pid, q, j >> 2, 1u, a.s.key0, a.s.key1);
         const float3 wj = sample_dir(pick4(words2, j), j, a.s.nb2_shift, a.s.inv_na2, a.s.inv_nb2, frb);
+        // texel loads issued here overlap the tracer's matrix-core work
+        const float3 Ej = env_lookup(a.env, wj.x, wj.y, wj.z);
         wave_sync_lds();
         PP::store_dir(W, lane, wj);
         wave_sync_lds();
@@ -452,7 +454,6 @@ __device__ __forceinline__ float3 bounce_lo(const RenderK &a, const typename PP:
         }
         // hard visibility: only visible secondary rays contribute
         const float vj = hard ? (vo > 0.0f ? 1.0f : 0.0f) : sigmoidf_(vo);
-        const float3 Ej = env_lookup(a.env, wj.x, wj.y, wj.z);
         const float3 c = nhead ? pi_brdf(nb, vb, wj, ab, rb, mb, a.f0, diffuse) : fb_.eval(dot3(nb, wj));
         Lx = fmaf(c.x * vj, Ej.x, Lx);
         Ly = fmaf(c.y * vj, Ej.y, Ly);
@@ -593,6 +594,7 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mma(const RenderK a, int
                     const uint4 words = philox4x32_10((uint32_t)p, 0u, i_own >> 2, 0u, a.s.key0, a.s.key1);
                     w_own = sample_dir(pick4(words, i_own), i_own, a.s.nb_shift, a.s.inv_na, a.s.inv_nb, fr);
                 }
+                Le_own = env_lookup(a.env, w_own.x, w_own.y, w_own.z);  // overlaps the tracer
                 wave_sync_lds();
                 PP::store_dir(W, lane, w_own);
                 wave_sync_lds();
@@ -619,7 +621,6 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mma(const RenderK a, int
                 }
                 V_own = hard ? (o0 > 0.0f ? 1.0f : 0.0f) : sigmoidf_(o0);
                 d_own = fminf(softplusf_(o1), 1.0f);
-                Le_own = env_lookup(a.env, w_own.x, w_own.y, w_own.z);
                 if (!QUERY && live && a.vis) {
                     a.vis[p * N + i_own] = V_own;
                     a.depth[p * N + i_own] = d_own;
