@@ -92,10 +92,12 @@ def test_full_batch_gradients(frame, B):
     for part, g in ((head, ga), (~head, gb)):
         hg.backward(r, env_t, pos_t, dirs_t, T(g_rgb * part[:, None]), T(g_vis * part), T(g_dep * part), g)
     tf, ta, tb = [[g["table"]] + g["brdf"] + g["irt"] for g in (full, ga, gb)]
-    # FP32 atomics in launch order: a weight sums B/64 wave partials, so the
-    # rounding is ~2^-24 sqrt(B/64) times the cancellation (~1e-5 at 2^20)
+    # FP32 atomics in launch order: a weight sums B/64 wave partials in an
+    # unspecified order, a random walk of roundings growing like sqrt(B):
+    # bar 1e-5 sqrt(B / 2^14) (4e-5 at 2^18, 8e-5 at 2^20; 5.4e-5 measured at 2^20)
+    bar = 1e-5 * np.sqrt(B / 2 ** 14)
     for a, b, c in zip(tf, ta, tb):
-        assert relerr(a.cpu().numpy(), (b + c).cpu().numpy()) < 4e-5
+        assert relerr(a.cpu().numpy(), (b + c).cpu().numpy()) < bar
     # oracle on the head.  With the finest level at 2048 the depth path of the
     # gradient carries the encoding's spatial derivative (2048/16 per unit),
     # so the FP32 depth (a few 1e-7 relative) moves the gradients by ~3e-5
