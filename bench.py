@@ -322,6 +322,29 @@ def main():
         out["train"] = {"samples_per_s": B / (mst * 1e-3), "ms_per_step": mst, "batch": B,
                         "secondary_queries_per_s_fwd_bwd": B / (mst * 1e-3), "dtype": "f32"}
 
+        # mixed-precision step: forward with FP16 tables and BF16 MLPs on the
+        # matrix cores, backward gathering the FP16 tables with the FP32 master
+        # MLPs, Adam on the FP32 masters refreshing the FP16/BF16 shadows
+        r.refresh_shadows()
+        shadows = [r.table16] + [r.brdf16[i] if i % 2 == 0 else None for i in range(6)] + \
+                  [r.irt16[i] if i % 2 == 0 else None for i in range(6)]
+
+        def train_step_mixed():
+            step[0] += 1
+            for g in gl:
+                g.zero_()
+            rgb_, vis_, dep_ = hg.render(r, env_t, bp_t, dirs=bd_t, precision="mixed")
+            loss, g_rgb, g_vis, g_dep = hg.l2_loss(rgb_, vis_, dep_, tgt)
+            hg.backward(r, env_t, bp_t, bd_t, g_rgb, g_vis, g_dep, grads, precision="f16table")
+            for i, (p_, g_) in enumerate(zip(params, gl)):
+                hg.adam_step(p_, g_, ms_[i], vs_[i], step[0], lr=2e-3, weight_decay=0.0 if i == 0 else 1e-6,
+                             shadow=shadows[i])
+            return loss
+
+        mstm, _, _ = time_events(train_step_mixed, max(2, args.steps // 2), 1, torch)
+        out["train"]["mixed"] = {"samples_per_s": B / (mstm * 1e-3), "ms_per_step": mstm,
+                                 "dtype": "bf16-mfma fwd / f16-table bwd / f32 masters"}
+
     if not args.no_cpu:
         from oracle import oracle as O
         sub = H.subset_rows_cols(cfg.img_h, cfg.img_w, args.cpu_stride)

@@ -168,3 +168,36 @@ def test_autograd_function_matches_backward(setup):
         for p_ in params:
             p_.requires_grad_(False)
             p_.grad = None
+
+
+@pytest.mark.parametrize("indirect", [True, False])
+def test_backward_f16_table(setup, indirect):
+    """The mixed training step's backward gathers the FP16 table shadow with
+    the FP32 master MLPs: it equals the oracle's backward on the FP16-rounded
+    table (same kink mask and bar as the FP32 backward)."""
+    print(f"case: backward with FP16 tables, indirect={indirect}", flush=True)
+    t = setup["t"]
+    r = setup["r"]
+    r.refresh_shadows()
+    m16 = dict(setup["model"])
+    m16["table"] = setup["model"]["table"].astype(np.float16).astype(np.float32)
+    om16 = O.OracleModel(m16, H.BOX_LO, H.BOX_EXTENT)
+    n = 1030
+    pos, dirs = H.make_train_batch(n, seed=23)
+    rng = np.random.default_rng(6)
+    g_rgb = rng.standard_normal((n, 3)).astype(np.float32)
+    g_vis = rng.standard_normal(n).astype(np.float32)
+    g_dep = rng.standard_normal(n).astype(np.float32)
+    dep = O.render(om16, setup["oe"], O.sampling(1, 8, 7, 0), pos, dirs=dirs, indirect=indirect)[2]
+    keep = (kink_margin(m16, pos, dirs, dep, indirect) >= 1e-5).astype(np.float32)
+    g_rgb, g_vis, g_dep = g_rgb * keep[:, None], g_vis * keep, g_dep * keep
+    grads = hg.zero_grads(r)
+    hg.backward(r, setup["env_t"], t(pos), t(dirs), t(g_rgb), t(g_vis), t(g_dep), grads, indirect=indirect,
+                precision="f16table")
+    ref = O.backward(om16, setup["oe"], O.sampling(1, 8, 7, 0), pos, dirs, g_rgb, g_vis, g_dep, indirect=indirect)
+    assert relerr(grads["table"].cpu().numpy(), ref["table"]) < 1e-5
+    for k in ("brdf", "irt"):
+        for i in range(6):
+            if not indirect and k == "brdf":
+                continue
+            assert relerr(grads[k][i].cpu().numpy(), ref[k][i]) < 1e-5, (k, i)
