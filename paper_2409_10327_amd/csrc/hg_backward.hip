@@ -5,7 +5,8 @@
 // the two MLPs are reduced over the 64 queries of a wave through LDS
 // (each lane owns one input column of a layer) and then added to global
 // memory with FP32 atomics; table gradients are scattered with FP32 atomics
-// through the trilinear weights.
+// through the trilinear weights, summed first over the lanes of a wave that
+// share a cell (coarse levels).
 #include "hg_device.h"
 #include "hg_launch.h"
 
@@ -132,6 +133,60 @@ __device__ __forceinline__ void mlp_bwd_wave(const MlpK &m, float *const *gp, co
     }
 }
 
+// Adds this lane's 16 contributions v[2k + f] (corner k, feature f) into the
+// table gradient of one level (gl = level base, idx = corner entries of the
+// lane's cell c).  Lanes of the wave that share a cell are summed first, so
+// at coarse levels -- where a wave's queries fall into a handful of cells --
+// one atomic per value and cell reaches memory instead of one per lane (the
+// per-address serialisation of those atomics dominated the backward).  A
+// group's 16 values are summed over the wave with a transposed butterfly
+// (17 lane exchanges) that leaves value q = lane >> 2 on lanes with
+// lane % 4 == 0.  Once the next group has a single lane (fine levels), the
+// remaining lanes add directly.  All lanes of the wave call this together.
+__device__ __forceinline__ void scatter_cell(float *gl, const uint32_t (&idx)[8], const uint32_t (&c)[3],
+                                             const float (&v)[16], bool live, int lane) {
+    uint64_t pending = __ballot(live);
+    while (pending) {
+        const int leader = __builtin_ctzll(pending);  // wave-uniform
+        const uint32_t l0 = __builtin_amdgcn_readlane(c[0], leader);
+        const uint32_t l1 = __builtin_amdgcn_readlane(c[1], leader);
+        const uint32_t l2 = __builtin_amdgcn_readlane(c[2], leader);
+        const bool same = ((pending >> lane) & 1ull) && c[0] == l0 && c[1] == l1 && c[2] == l2;
+        const uint64_t grp = __ballot(same);
+        if (__popcll(grp) < 2) break;
+        float b8[8], b4[4], b2[2];
+        const bool h32 = lane & 32, h16 = lane & 16, h8 = lane & 8, h4 = lane & 4;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const float lo = same ? v[i] : 0.0f, hi = same ? v[i + 8] : 0.0f;
+            b8[i] = (h32 ? hi : lo) + __shfl_xor(h32 ? lo : hi, 32);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) b4[i] = (h16 ? b8[i + 4] : b8[i]) + __shfl_xor(h16 ? b8[i] : b8[i + 4], 16);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) b2[i] = (h8 ? b4[i + 2] : b4[i]) + __shfl_xor(h8 ? b4[i] : b4[i + 2], 8);
+        float b1 = (h4 ? b2[1] : b2[0]) + __shfl_xor(h4 ? b2[0] : b2[1], 4);
+        b1 += __shfl_xor(b1, 2);
+        b1 += __shfl_xor(b1, 1);
+        const int q = lane >> 2;  // value index held by this lane group
+        uint32_t e = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t ik = __builtin_amdgcn_readlane(idx[k], leader);
+            e = (q >> 1) == k ? ik : e;
+        }
+        if ((lane & 3) == 0) atomic_addf(gl + 2 * (size_t)e + (q & 1), b1);
+        pending &= ~grp;
+    }
+    if ((pending >> lane) & 1ull) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            atomic_addf(gl + 2 * (size_t)idx[k], v[2 * k]);
+            atomic_addf(gl + 2 * (size_t)idx[k] + 1, v[2 * k + 1]);
+        }
+    }
+}
+
 // Scatter gf through the trilinear weights of the cell of x into the table
 // gradient, and (optionally) return d/dx of the encoding contracted with gf.
 template <typename TT>
@@ -153,16 +208,15 @@ __device__ __forceinline__ void encode_bwd(const GridK &g, float x, float y, flo
         corner_idx(g, l, c, idx);
         const float w0[3] = {1.0f - w[0], 1.0f - w[1], 1.0f - w[2]};
         const float sc = g.dscale[l];
+        float v[16];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int dx = k & 1, dy = (k >> 1) & 1, dzz = (k >> 2) & 1;
             const size_t e = base + idx[k];
             const float fx = dx ? w[0] : w0[0], fy = dy ? w[1] : w0[1], fz = dzz ? w[2] : w0[2];
             const float wt = fx * fy * fz;
-            if (live) {
-                atomic_addf(g_table + 2 * e, wt * gf[2 * l]);
-                atomic_addf(g_table + 2 * e + 1, wt * gf[2 * l + 1]);
-            }
+            v[2 * k] = wt * gf[2 * l];
+            v[2 * k + 1] = wt * gf[2 * l + 1];
             if (want_dx) {
                 const float2 te = TabLoad<TT>::ld(g.table, e);
                 const float ge = (gf[2 * l] * te.x + gf[2 * l + 1] * te.y) * sc;
@@ -171,6 +225,7 @@ __device__ __forceinline__ void encode_bwd(const GridK &g, float x, float y, flo
                 gxz = fmaf(ge, fx * fy * (dzz ? 1.0f : -1.0f), gxz);
             }
         }
+        scatter_cell(g_table + 2 * base, idx, c, v, live, (int)(threadIdx.x & 63));
     }
     gx = make_float3(in[0] ? gxx : 0.f, in[1] ? gxy : 0.f, in[2] ? gxz : 0.f);
 }
