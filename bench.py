@@ -307,13 +307,30 @@ def main():
         vs_ = [torch.zeros_like(p) for p in params]
         step = [0]
 
+        def morton_order(p):
+            # batch order along a Morton curve (10 bits per axis over the batch's
+            # box): queries of a wave then share cells down to finer levels and
+            # the backward's per-cell summation replaces more atomics
+            lo, hi = p.min(0).values, p.max(0).values
+            q = ((p - lo) / (hi - lo).clamp_min(1e-12) * 1023.0).long().clamp_(0, 1023)
+
+            def spread(v):
+                v = (v | (v << 16)) & 0x030000FF
+                v = (v | (v << 8)) & 0x0300F00F
+                v = (v | (v << 4)) & 0x030C30C3
+                return (v | (v << 2)) & 0x09249249
+            return torch.argsort(spread(q[:, 0]) | (spread(q[:, 1]) << 1) | (spread(q[:, 2]) << 2))
+
         def train_step():
+            # a training loop draws a new batch each step: its ordering is part of the step
             step[0] += 1
+            order = morton_order(bp_t)
+            sp, sd, st = bp_t[order], bd_t[order], tgt[order]
             for g in gl:
                 g.zero_()
-            rgb_, vis_, dep_ = hg.render(r, env_t, bp_t, dirs=bd_t)
-            loss, g_rgb, g_vis, g_dep = hg.l2_loss(rgb_, vis_, dep_, tgt)
-            hg.backward(r, env_t, bp_t, bd_t, g_rgb, g_vis, g_dep, grads)
+            rgb_, vis_, dep_ = hg.render(r, env_t, sp, dirs=sd)
+            loss, g_rgb, g_vis, g_dep = hg.l2_loss(rgb_, vis_, dep_, st)
+            hg.backward(r, env_t, sp, sd, g_rgb, g_vis, g_dep, grads)
             for i, (p_, g_) in enumerate(zip(params, gl)):
                 hg.adam_step(p_, g_, ms_[i], vs_[i], step[0], lr=2e-3, weight_decay=0.0 if i == 0 else 1e-6)
             return loss
@@ -331,11 +348,13 @@ def main():
 
         def train_step_mixed():
             step[0] += 1
+            order = morton_order(bp_t)
+            sp, sd, st = bp_t[order], bd_t[order], tgt[order]
             for g in gl:
                 g.zero_()
-            rgb_, vis_, dep_ = hg.render(r, env_t, bp_t, dirs=bd_t, precision="mixed")
-            loss, g_rgb, g_vis, g_dep = hg.l2_loss(rgb_, vis_, dep_, tgt)
-            hg.backward(r, env_t, bp_t, bd_t, g_rgb, g_vis, g_dep, grads, precision="f16table")
+            rgb_, vis_, dep_ = hg.render(r, env_t, sp, dirs=sd, precision="mixed")
+            loss, g_rgb, g_vis, g_dep = hg.l2_loss(rgb_, vis_, dep_, st)
+            hg.backward(r, env_t, sp, sd, g_rgb, g_vis, g_dep, grads, precision="f16table")
             for i, (p_, g_) in enumerate(zip(params, gl)):
                 hg.adam_step(p_, g_, ms_[i], vs_[i], step[0], lr=2e-3, weight_decay=0.0 if i == 0 else 1e-6,
                              shadow=shadows[i])

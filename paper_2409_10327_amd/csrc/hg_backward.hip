@@ -74,13 +74,13 @@ __device__ __forceinline__ void store_row(float *del, int lane, const float (&v)
 }
 
 // Backward of one MLP evaluation for every lane of the wave (all lanes call
-// it together).  Recomputes the forward, accumulates parameter gradients
+// it together), given the forward just run by mlp_fwd into h1buf / h2buf
+// with h = the last hidden layer: accumulates parameter gradients
 // (gp = W0,b0,W1,b1,W2,b2) and returns d/d(input) for the first kNF inputs.
 template <int NIN, int NOUT>
-__device__ __forceinline__ void mlp_bwd_wave(const MlpK &m, float *const *gp, const float (&z)[NIN], const float (&gout)[NOUT],
-                             float *h1buf, float *h2buf, float *del, int lane, float (&dz)[kNF]) {
-    float h[kH], o[NOUT];
-    mlp_fwd<NIN, NOUT, float>(m, z, h1buf, h2buf, lane, h, o);  // h = h2
+__device__ __forceinline__ void mlp_bwd_stored(const MlpK &m, float *const *gp, const float (&z)[NIN],
+                                               const float (&gout)[NOUT], float (&h)[kH], float *h1buf, float *h2buf,
+                                               float *del, int lane, float (&dz)[kNF]) {
     // ---- layer 2: out = W2 h2 + b2
 #pragma unroll
     for (int k = 0; k < NOUT; ++k) del[lane * kDelStride + k] = gout[k];
@@ -131,6 +131,16 @@ __device__ __forceinline__ void mlp_bwd_wave(const MlpK &m, float *const *gp, co
 #pragma unroll
         for (int i = 0; i < kNF; ++i) dz[i] = fmaf(W0[j * NIN + i], g1, dz[i]);
     }
+}
+
+// Forward recompute plus backward of one MLP evaluation (see mlp_bwd_stored).
+template <int NIN, int NOUT>
+__device__ __forceinline__ void mlp_bwd_wave(const MlpK &m, float *const *gp, const float (&z)[NIN],
+                                             const float (&gout)[NOUT], float *h1buf, float *h2buf, float *del, int lane,
+                                             float (&dz)[kNF]) {
+    float h[kH], o[NOUT];
+    mlp_fwd<NIN, NOUT, float>(m, z, h1buf, h2buf, lane, h, o);  // h = h2
+    mlp_bwd_stored<NIN, NOUT>(m, gp, z, gout, h, h1buf, h2buf, del, lane, dz);
 }
 
 // Adds this lane's 16 contributions v[2k + f] (corner k, feature f) into the
@@ -323,40 +333,30 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(const BwdK a) {
         const float invN2 = 1.0f / (float)N2;
 #pragma unroll
         for (int i = 0; i < kNF; ++i) z[i] = fb[i];
-        // pass 1: L'_o
+        // one pass over the secondary directions: the forward of tracer j gives
+        // V'_j for L'_o and, since d L / d V'_j needs only (1 - V) G, its
+        // backward runs on the activations just computed
         float Lx = 0.f, Ly = 0.f, Lz = 0.f;
-        uint4 words = make_uint4(0, 0, 0, 0);
-        for (uint32_t j = 0; j < N2; ++j) {
-            if ((j & 3u) == 0) words = philox4x32_10((uint32_t)p, 0u, j >> 2, 1u, r.s.key0, r.s.key1);
-            const float3 wj = sample_dir(pick4(words, j), j, r.s.nb2_shift, r.s.inv_na2, r.s.inv_nb2, fr);
-            z[kNF] = wj.x; z[kNF + 1] = wj.y; z[kNF + 2] = wj.z;
-            mlp_fwd<kNI, 2, float>(r.irt, z, h1buf, h1buf, lane, h, o);
-            const float vj = sigmoidf_(o[0]);
-            const float3 Ej = env_lookup(r.env, wj.x, wj.y, wj.z);
-            const float3 c = pi_brdf(nb, nb, wj, ab, rb, mb, r.f0, diffuse);
-            Lx = fmaf(c.x * vj, Ej.x, Lx);
-            Ly = fmaf(c.y * vj, Ej.y, Ly);
-            Lz = fmaf(c.z * vj, Ej.z, Lz);
-        }
-        Lx *= invN2; Ly *= invN2; Lz *= invN2;
-        gV += G.x * (Le.x - Lx) + G.y * (Le.y - Ly) + G.z * (Le.z - Lz);
         const float3 gLo = make_float3((1.0f - V) * G.x, (1.0f - V) * G.y, (1.0f - V) * G.z);
         float gfb[kNF];
 #pragma unroll
         for (int i = 0; i < kNF; ++i) gfb[i] = 0.f;
         float gax = 0.f, gay = 0.f, gaz = 0.f, gr = 0.f, gm = 0.f;
-        // pass 2: tracer backward at every secondary direction
+        uint4 words = make_uint4(0, 0, 0, 0);
         for (uint32_t j = 0; j < N2; ++j) {
             if ((j & 3u) == 0) words = philox4x32_10((uint32_t)p, 0u, j >> 2, 1u, r.s.key0, r.s.key1);
             const float3 wj = sample_dir(pick4(words, j), j, r.s.nb2_shift, r.s.inv_na2, r.s.inv_nb2, fr);
             z[kNF] = wj.x; z[kNF + 1] = wj.y; z[kNF + 2] = wj.z;
-            mlp_fwd<kNI, 2, float>(r.irt, z, h1buf, h1buf, lane, h, o);
+            mlp_fwd<kNI, 2, float>(r.irt, z, h1buf, h2buf, lane, h, o);
             const float vj = sigmoidf_(o[0]);
             const float3 Ej = env_lookup(r.env, wj.x, wj.y, wj.z);
             const BrdfGrad bg = pi_brdf_grad(nb, nb, wj, ab, rb, mb, r.f0, diffuse);
+            Lx = fmaf(bg.c.x * vj, Ej.x, Lx);
+            Ly = fmaf(bg.c.y * vj, Ej.y, Ly);
+            Lz = fmaf(bg.c.z * vj, Ej.z, Lz);
             const float gvj = (gLo.x * bg.c.x * Ej.x + gLo.y * bg.c.y * Ej.y + gLo.z * bg.c.z * Ej.z) * invN2;
             const float go[2] = {gvj * vj * (1.0f - vj), 0.0f};
-            mlp_bwd_wave<kNI, 2>(r.irt, a.gi, z, go, h1buf, h2buf, del, lane, dz);
+            mlp_bwd_stored<kNI, 2>(r.irt, a.gi, z, go, h, h1buf, h2buf, del, lane, dz);
 #pragma unroll
             for (int i = 0; i < kNF; ++i) gfb[i] += dz[i];
             const float kx = gLo.x * vj * Ej.x * invN2, ky = gLo.y * vj * Ej.y * invN2, kz = gLo.z * vj * Ej.z * invN2;
@@ -366,6 +366,8 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(const BwdK a) {
             gr += kx * bg.dcr.x + ky * bg.dcr.y + kz * bg.dcr.z;
             gm += kx * bg.dcm.x + ky * bg.dcm.y + kz * bg.dcm.z;
         }
+        Lx *= invN2; Ly *= invN2; Lz *= invN2;
+        gV += G.x * (Le.x - Lx) + G.y * (Le.y - Ly) + G.z * (Le.z - Lz);
         const float gob[5] = {gax * ab.x * (1.0f - ab.x), gay * ab.y * (1.0f - ab.y), gaz * ab.z * (1.0f - ab.z),
                               gr * 0.91f * s3 * (1.0f - s3), gm * mb * (1.0f - mb)};
         mlp_bwd_wave<kNF, 5>(r.brdf, a.gb, fb, gob, h1buf, h2buf, del, lane, dz);

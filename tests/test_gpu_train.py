@@ -201,3 +201,46 @@ def test_backward_f16_table(setup, indirect):
             if not indirect and k == "brdf":
                 continue
             assert relerr(grads[k][i].cpu().numpy(), ref[k][i]) < 1e-5, (k, i)
+
+
+def morton_sorted(pos, dirs):
+    """Batch reordered along a Morton curve (what the benchmark's training
+    step does): lanes of a wave then share cells at most levels."""
+    lo, hi = pos.min(0), pos.max(0)
+    q = np.clip(((pos - lo) / (hi - lo) * 1023).astype(np.int64), 0, 1023)
+
+    def spread(v):
+        v = (v | (v << 16)) & 0x030000FF
+        v = (v | (v << 8)) & 0x0300F00F
+        v = (v | (v << 4)) & 0x030C30C3
+        return (v | (v << 2)) & 0x09249249
+    order = np.argsort(spread(q[:, 0]) | (spread(q[:, 1]) << 1) | (spread(q[:, 2]) << 2), kind="stable")
+    return pos[order], dirs[order]
+
+
+@pytest.mark.parametrize("indirect", [True, False])
+def test_backward_parity_spatially_sorted_batch(setup, indirect):
+    """A Morton-ordered batch drives the backward's per-cell summation of the
+    table gradient at most levels (groups of lanes sharing a cell); gradients
+    still match the oracle at the FP32 bar."""
+    print(f"case: backward on a Morton-ordered batch, indirect={indirect}", flush=True)
+    t = setup["t"]
+    n = 4096
+    pos, dirs = morton_sorted(*H.make_train_batch(n, seed=29))
+    rng = np.random.default_rng(8)
+    g_rgb = rng.standard_normal((n, 3)).astype(np.float32)
+    g_vis = rng.standard_normal(n).astype(np.float32)
+    g_dep = rng.standard_normal(n).astype(np.float32)
+    dep = O.render(setup["om"], setup["oe"], O.sampling(1, 8, 7, 0), pos, dirs=dirs, indirect=indirect)[2]
+    keep = (kink_margin(setup["model"], pos, dirs, dep, indirect) >= 1e-5).astype(np.float32)
+    g_rgb, g_vis, g_dep = g_rgb * keep[:, None], g_vis * keep, g_dep * keep
+    grads = hg.zero_grads(setup["r"])
+    hg.backward(setup["r"], setup["env_t"], t(pos), t(dirs), t(g_rgb), t(g_vis), t(g_dep), grads, indirect=indirect)
+    ref = O.backward(setup["om"], setup["oe"], O.sampling(1, 8, 7, 0), pos, dirs, g_rgb, g_vis, g_dep,
+                     indirect=indirect)
+    assert relerr(grads["table"].cpu().numpy(), ref["table"]) < 1e-5
+    for k in ("brdf", "irt"):
+        for i in range(6):
+            if not indirect and k == "brdf":
+                continue
+            assert relerr(grads[k][i].cpu().numpy(), ref[k][i]) < 1e-5, (k, i)
