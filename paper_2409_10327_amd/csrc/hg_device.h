@@ -136,9 +136,12 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
     return make_uint4(c0, c1, c2, c3);
 }
 
+// Word k % 4 of a Philox block, without a branch when k is wave-uniform.
 __device__ __forceinline__ uint32_t pick4(const uint4 &w, uint32_t k) {
     const uint32_t s = k & 3u;
-    return s == 0 ? w.x : (s == 1 ? w.y : (s == 2 ? w.z : w.w));
+    const uint32_t m0 = 0u - (uint32_t)(s == 0u), m1 = 0u - (uint32_t)(s == 1u);
+    const uint32_t m2 = 0u - (uint32_t)(s == 2u), m3 = 0u - (uint32_t)(s == 3u);
+    return (w.x & m0) | (w.y & m1) | (w.z & m2) | (w.w & m3);
 }
 
 // Orthonormal basis about a unit normal (Duff et al., JCGT 2017).
@@ -375,11 +378,10 @@ __device__ __forceinline__ BrdfTerms brdf_terms(float3 n, float3 v, float3 l, fl
     float NdotV = fmaxf(dot3(n, v), 1e-4f);
     float3 h = make_float3(l.x + v.x, l.y + v.y, l.z + v.z);
     const float hh = dot3(h, h);
-    if (hh > 0.0f) {
+    {
         const float inv = rsqrtf(hh);
-        h = make_float3(h.x * inv, h.y * inv, h.z * inv);
-    } else {
-        h = n;
+        const bool ok = hh > 0.0f;
+        h = make_float3(ok ? h.x * inv : n.x, ok ? h.y * inv : n.y, ok ? h.z * inv : n.z);
     }
     const float NdotH = fmaxf(dot3(n, h), 0.0f);
     const float VdotH = fmaxf(dot3(v, h), 0.0f);
@@ -404,17 +406,20 @@ __device__ __forceinline__ BrdfTerms brdf_terms(float3 n, float3 v, float3 l, fl
     return t;
 }
 
-// pi * f_r per channel.
+// pi * f_r per channel (zero where n.l <= 0).  Written with selects only, so
+// that it can share a basic block with matrix-core work.
 __device__ __forceinline__ float3 pi_brdf(float3 n, float3 v, float3 l, float3 a, float r, float m, float f0,
                                           bool diffuse_only) {
-    if (!(dot3(n, l) > 0.0f)) return make_float3(0.f, 0.f, 0.f);
-    if (diffuse_only) return a;
     const BrdfTerms t = brdf_terms(n, v, l, r, false);
-    const float s = kPi * t.D * t.Vis;
+    // diffuse only: metalness and specular factor zero, which returns a exactly
+    const float me = diffuse_only ? 0.0f : m;
+    const float s = diffuse_only ? 0.0f : kPi * t.D * t.Vis;
     const float q = 1.0f - t.P;
-    const float F0x = f0 * (1.0f - m) + a.x * m, F0y = f0 * (1.0f - m) + a.y * m, F0z = f0 * (1.0f - m) + a.z * m;
-    return make_float3((1.0f - m) * a.x + s * (F0x * q + t.P), (1.0f - m) * a.y + s * (F0y * q + t.P),
-                       (1.0f - m) * a.z + s * (F0z * q + t.P));
+    const float F0x = f0 * (1.0f - me) + a.x * me, F0y = f0 * (1.0f - me) + a.y * me,
+                F0z = f0 * (1.0f - me) + a.z * me;
+    const float3 o = make_float3((1.0f - me) * a.x + s * (F0x * q + t.P), (1.0f - me) * a.y + s * (F0y * q + t.P),
+                                 (1.0f - me) * a.z + s * (F0z * q + t.P));
+    return make_float3(t.live ? o.x : 0.f, t.live ? o.y : 0.f, t.live ? o.z : 0.f);
 }
 
 // Unit normal from the decoder's normal head (n / |n|); `fallback` when the
@@ -442,9 +447,8 @@ struct FacingBrdf {
         a2 = al * al;
         a2m1 = a2 - 1.0f;
     }
+    // selects only (no branch), zero where n.l <= 0
     __device__ __forceinline__ float3 eval(float NdotL) const {
-        if (!(NdotL > 0.0f)) return make_float3(0.f, 0.f, 0.f);
-        if (diffuse) return kd;
         const float h2 = 0.5f * (1.0f + NdotL);
         const float Q = fmaf(h2, a2m1, 1.0f);
         const float D = a2 / (kPi * Q * Q);
@@ -453,9 +457,12 @@ struct FacingBrdf {
         const float om = 1.0f - sqrtf(h2);
         const float om2 = om * om;
         const float P = om2 * om2 * om;
-        const float sp = kPi * D * Vis, q = 1.0f - P;
-        return make_float3(fmaf(sp, fmaf(F0.x, q, P), kd.x), fmaf(sp, fmaf(F0.y, q, P), kd.y),
-                           fmaf(sp, fmaf(F0.z, q, P), kd.z));
+        // diffuse only: specular factor zero, which returns kd exactly
+        const float sp = diffuse ? 0.0f : kPi * D * Vis, q = 1.0f - P;
+        const float3 o = make_float3(fmaf(sp, fmaf(F0.x, q, P), kd.x), fmaf(sp, fmaf(F0.y, q, P), kd.y),
+                                     fmaf(sp, fmaf(F0.z, q, P), kd.z));
+        const bool live = NdotL > 0.0f;
+        return make_float3(live ? o.x : 0.f, live ? o.y : 0.f, live ? o.z : 0.f);
     }
 };
 

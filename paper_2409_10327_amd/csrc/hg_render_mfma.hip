@@ -122,7 +122,7 @@ struct Bf16Path {
 
     struct Wave {
         uint4 x[64][4];   // per-query input features (32 BF16)
-        uint4 om[64];     // per-query direction operand (w_hi, w_lo)
+        uint4 om[2][64];  // per-query direction operand (w_hi, w_lo), two buffers
         float ax[4][kH];  // per-pixel tracer point part (shade mode)
         float mat[4][8];  // per-pixel decoder outputs (shade mode)
         uint16_t qi[128]; // queued shadow rays (hard visibility): direction index
@@ -192,10 +192,10 @@ struct Bf16Path {
     static __device__ __forceinline__ void store_level(Wave &W, int row, int lvl, float f0, float f1) {
         reinterpret_cast<uint32_t *>(&W.x[row][0])[lvl] = pack_bf16(f0, f1);
     }
-    static __device__ __forceinline__ void store_dir(Wave &W, int lane, float3 w) {
+    static __device__ __forceinline__ void store_dir(Wave &W, int buf, int lane, float3 w) {
         const __bf16 hx = (__bf16)w.x, hy = (__bf16)w.y, hz = (__bf16)w.z;
         const float lx = w.x - (float)hx, ly = w.y - (float)hy, lz = w.z - (float)hz;
-        W.om[lane] = make_uint4(pack_bf16((float)hx, (float)hy), pack_bf16((float)hz, lx), pack_bf16(ly, lz), 0u);
+        W.om[buf][lane] = make_uint4(pack_bf16((float)hx, (float)hy), pack_bf16((float)hz, lx), pack_bf16(ly, lz), 0u);
     }
 
     // tracer point part W0f x + b0 of N-tile nt
@@ -228,9 +228,9 @@ struct Bf16Path {
     }
 
     // tracer for N-tile nt from the point part c: returns the head tile
-    static __device__ __forceinline__ f32x4 tracer(const Tracer &T, const Tile *, const Wave &W, int nt, int lane,
-                                                   const f32x4 (&c)[4]) {
-        const uint4 ob_ = W.om[16 * nt + (lane & 15)];
+    static __device__ __forceinline__ f32x4 tracer(const Tracer &T, const Tile *, const Wave &W, int buf, int nt,
+                                                   int lane, const f32x4 (&c)[4]) {
+        const uint4 ob_ = W.om[buf][16 * nt + (lane & 15)];
         f32x4 d[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) d[m] = mfma_bf16(T.w0w[m], ob_, c[m]);
@@ -252,20 +252,24 @@ struct Bf16Path {
 // ============================================================================
 struct F32Path {
     typedef float Table;
-    // tracer tiles in LDS (decoder operands are read from the FP32 weights)
+    // tracer and decoder operand tiles in LDS (62.5 KB)
     enum : int {
-        T_W0W = 0,       // 4 M-tiles, one K-step (w_x, w_y, w_z, 0)
+        T_W0W = 0,       // tracer: 4 M-tiles, one K-step (w_x, w_y, w_z, 0)
         T_W0F = 4,       // 4 M-tiles x 8 K-steps (m*8 + s)
         T_W1 = 36,       // 4 M-tiles x 16 K-steps (m*16 + s)
         T_W2 = 100,      // 16 K-steps
-        N_TILES = 116
+        D_W0 = 116,      // decoder: 4 M-tiles x 8 K-steps (m*8 + s)
+        D_W1 = 148,      // 4 M-tiles x 16 K-steps (m*16 + s)
+        D_W2A = 212,     // outputs 0..3, 16 K-steps
+        D_W2B = 228,     // outputs 4..7, 16 K-steps
+        N_TILES = 244
     };
     typedef float Tile;
     static constexpr int kXS = 36;  // row stride of the feature rows (16-byte aligned, 2-way banks)
 
     struct Wave {
         float x[64][kXS];
-        float4 om[64];
+        float4 om[2][64];
         float ax[4][kH];
         float mat[4][8];
         uint16_t qi[128];
@@ -285,8 +289,21 @@ struct F32Path {
             const int m = (t - T_W1) >> 4, s = (t - T_W1) & 15;
             return wf(a.iW1, (16 * m + i) * kH + unit_f32(s, g));
         }
-        const int s = t - T_W2, r = i & 3;
-        return r < 2 ? wf(a.iW2, r * kH + unit_f32(s, g)) : 0.0f;
+        if (t < D_W0) {
+            const int s = t - T_W2, r = i & 3;
+            return r < 2 ? wf(a.iW2, r * kH + unit_f32(s, g)) : 0.0f;
+        }
+        if (t < D_W1) {
+            const int m = (t - D_W0) >> 3, s = (t - D_W0) & 7;
+            return wf(a.bW0, (16 * m + i) * kNF + 4 * s + g);
+        }
+        if (t < D_W2A) {
+            const int m = (t - D_W1) >> 4, s = (t - D_W1) & 15;
+            return wf(a.bW1, (16 * m + i) * kH + unit_f32(s, g));
+        }
+        const int r = i & 3;
+        if (t < D_W2B) return wf(a.bW2, r * kH + unit_f32(t - D_W2A, g));
+        return 4 + r < a.nout ? wf(a.bW2, (4 + r) * kH + unit_f32(t - D_W2B, g)) : 0.0f;
     }
 
     static __device__ __forceinline__ void build_tiles(const RenderK &ka, Tile *tiles) {
@@ -314,8 +331,8 @@ struct F32Path {
     static __device__ __forceinline__ void store_level(Wave &W, int row, int lvl, float f0, float f1) {
         *reinterpret_cast<float2 *>(&W.x[row][2 * lvl]) = make_float2(f0, f1);
     }
-    static __device__ __forceinline__ void store_dir(Wave &W, int lane, float3 w) {
-        W.om[lane] = make_float4(w.x, w.y, w.z, 0.0f);
+    static __device__ __forceinline__ void store_dir(Wave &W, int buf, int lane, float3 w) {
+        W.om[buf][lane] = make_float4(w.x, w.y, w.z, 0.0f);
     }
 
     static __device__ __forceinline__ void point_part(const Tile *tiles, const RenderK &a, const Wave &W, int nt,
@@ -331,14 +348,9 @@ struct F32Path {
         }
     }
 
-    // decoder operands straight from the FP32 weights (L1/L2 resident)
-    static __device__ __forceinline__ void decoder(const Tile *, const RenderK &a, const Wave &W, int nt, int lane,
-                                                   int g, f32x4 &oa, f32x4 &ob) {
-        const int i = lane & 15;
-        const float *xr = W.x[16 * nt + i];
-        const float *W0 = static_cast<const float *>(a.brdf.W0);
-        const float *W1 = static_cast<const float *>(a.brdf.W1);
-        const float *W2 = static_cast<const float *>(a.brdf.W2);
+    static __device__ __forceinline__ void decoder(const Tile *tiles, const RenderK &a, const Wave &W, int nt,
+                                                   int lane, int g, f32x4 &oa, f32x4 &ob) {
+        const float *xr = W.x[16 * nt + (lane & 15)];
         f32x4 d[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) d[m] = bias_tile(a.brdf.b0, m, g);
@@ -346,7 +358,7 @@ struct F32Path {
         for (int s = 0; s < 8; ++s) {
             const float b = xr[4 * s + g];
 #pragma unroll
-            for (int m = 0; m < 4; ++m) d[m] = mfma_f32(W0[(16 * m + i) * kNF + 4 * s + g], b, d[m]);
+            for (int m = 0; m < 4; ++m) d[m] = mfma_f32(tiles[(D_W0 + 8 * m + s) * 64 + lane], b, d[m]);
         }
         f32x4 e[4];
 #pragma unroll
@@ -354,27 +366,23 @@ struct F32Path {
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
             const float b = fmaxf(d[s >> 2][s & 3], 0.0f);
-            const int u = unit_f32(s, g);
 #pragma unroll
-            for (int m = 0; m < 4; ++m) e[m] = mfma_f32(W1[(16 * m + i) * kH + u], b, e[m]);
+            for (int m = 0; m < 4; ++m) e[m] = mfma_f32(tiles[(D_W1 + 16 * m + s) * 64 + lane], b, e[m]);
         }
         oa = head_bias(a.brdf.b2, 5, 0);
         ob = head_bias(a.brdf.b2, a.brdf_out, 4);
-        const int r = i & 3;
-        const bool rb = 4 + r < a.brdf_out;
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
             const float b = fmaxf(e[s >> 2][s & 3], 0.0f);
-            const int u = unit_f32(s, g);
-            oa = mfma_f32(W2[r * kH + u], b, oa);
-            ob = mfma_f32(rb ? W2[(4 + r) * kH + u] : 0.0f, b, ob);
+            oa = mfma_f32(tiles[(D_W2A + s) * 64 + lane], b, oa);
+            ob = mfma_f32(tiles[(D_W2B + s) * 64 + lane], b, ob);
         }
     }
 
-    static __device__ __forceinline__ f32x4 tracer(const Tracer &T, const Tile *tiles, const Wave &W, int nt,
+    static __device__ __forceinline__ f32x4 tracer(const Tracer &T, const Tile *tiles, const Wave &W, int buf, int nt,
                                                    int lane, const f32x4 (&c)[4]) {
         const int g = lane >> 4;
-        const float b0 = reinterpret_cast<const float *>(&W.om[16 * nt + (lane & 15)])[g];
+        const float b0 = reinterpret_cast<const float *>(&W.om[buf][16 * nt + (lane & 15)])[g];
         f32x4 d[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) d[m] = mfma_f32(tiles[(T_W0W + m) * 64 + lane], b0, c[m]);
@@ -393,6 +401,68 @@ struct F32Path {
         return o;
     }
 };
+
+// BRDF at the bounce point for a secondary direction: the full microfacet
+// model about the decoder's normal (normal head), else the facing form.
+struct SecondaryBrdf {
+    float3 n, v, a;
+    float r, m, f0;
+    bool diffuse;
+    FacingBrdf facing;
+    template <bool NHEAD>
+    __device__ __forceinline__ float3 eval(float3 l) const {
+        return NHEAD ? pi_brdf(n, v, l, a, r, m, f0, diffuse) : facing.eval(dot3(n, l));
+    }
+};
+
+// (1/N') sum_j f_r(w_j) V(x', w_j) L_e(w_j) over the secondary directions of
+// every lane's bounce point, from the tracer's point part bpt at x'.
+// Software pipeline: while the matrix cores trace direction j (operand
+// buffer j & 1), the vector ALU samples direction j + 1, issues its texel
+// loads and evaluates its BRDF factor, all in one basic block (the sampler,
+// lookup and BRDF use selects, not branches); the new operand goes to the
+// other buffer after the tracer's reads.  The last iteration samples
+// direction j again and drops it.
+template <class PP, bool NHEAD>
+__device__ __forceinline__ float3 secondary_lo(const RenderK &a, const typename PP::Tile *tiles,
+                                               typename PP::Wave &W, const typename PP::Tracer &T,
+                                               const f32x4 (&bpt)[4][4], int lane, int g, const Frame &frb,
+                                               const SecondaryBrdf &sb, uint32_t pid, uint32_t q, bool hard) {
+    const uint32_t n2 = a.s.n_dirs2;
+    uint4 words2 = philox4x32_10(pid, q, 0u, 1u, a.s.key0, a.s.key1);
+    const float3 w0 = sample_dir(pick4(words2, 0u), 0u, a.s.nb2_shift, a.s.inv_na2, a.s.inv_nb2, frb);
+    float3 Ej = env_lookup(a.env, w0.x, w0.y, w0.z);
+    float3 cj = sb.eval<NHEAD>(w0);
+    wave_sync_lds();
+    PP::store_dir(W, 0, lane, w0);
+    wave_sync_lds();
+    float Lx = 0.f, Ly = 0.f, Lz = 0.f;
+    for (uint32_t j = 0; j < n2; ++j) {
+        const uint32_t jn = j + 1 < n2 ? j + 1 : j;
+        if ((jn & 3u) == 0) words2 = philox4x32_10(pid, q, jn >> 2, 1u, a.s.key0, a.s.key1);
+        const float3 wn = sample_dir(pick4(words2, jn), jn, a.s.nb2_shift, a.s.inv_na2, a.s.inv_nb2, frb);
+        const float3 En = env_lookup(a.env, wn.x, wn.y, wn.z);
+        const float3 cn = sb.eval<NHEAD>(wn);
+        float vo = 0.f;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const f32x4 c[4] = {bpt[0][nt], bpt[1][nt], bpt[2][nt], bpt[3][nt]};
+            const f32x4 h = PP::tracer(T, tiles, W, (int)(j & 1u), nt, lane, c);
+            if (g == nt) vo = h[0];
+        }
+        PP::store_dir(W, (int)((j + 1) & 1u), lane, wn);
+        // hard visibility: only visible secondary rays contribute
+        const float vj = hard ? (vo > 0.0f ? 1.0f : 0.0f) : sigmoidf_(vo);
+        Lx = fmaf(cj.x * vj, Ej.x, Lx);
+        Ly = fmaf(cj.y * vj, Ej.y, Ly);
+        Lz = fmaf(cj.z * vj, Ej.z, Lz);
+        Ej = En;
+        cj = cn;
+        wave_sync_lds();
+    }
+    const float inv = 1.0f / (float)n2;
+    return make_float3(Lx * inv, Ly * inv, Lz * inv);
+}
 
 // ============================================================================
 // Outgoing radiance L'_o at the bounce point x' = x + t w of each lane's query
@@ -435,32 +505,9 @@ __device__ __forceinline__ float3 bounce_lo(const RenderK &a, const typename PP:
     const Frame frb = make_frame(nb);
     FacingBrdf fb_;
     fb_.set(ab, rb, mb, a.f0, diffuse);
-    float Lx = 0.f, Ly = 0.f, Lz = 0.f;
-    uint4 words2 = make_uint4(0, 0, 0, 0);
-    for (uint32_t j = 0; j < a.s.n_dirs2; ++j) {
-        if ((j & 3u) == 0) words2 = philox4x32_10(pid, q, j >> 2, 1u, a.s.key0, a.s.key1);
-        const float3 wj = sample_dir(pick4(words2, j), j, a.s.nb2_shift, a.s.inv_na2, a.s.inv_nb2, frb);
-        // texel loads issued here overlap the tracer's matrix-core work
-        const float3 Ej = env_lookup(a.env, wj.x, wj.y, wj.z);
-        wave_sync_lds();
-        PP::store_dir(W, lane, wj);
-        wave_sync_lds();
-        float vo = 0.f;
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            const f32x4 c[4] = {bpt[0][nt], bpt[1][nt], bpt[2][nt], bpt[3][nt]};
-            const f32x4 h = PP::tracer(T, tiles, W, nt, lane, c);
-            if (g == nt) vo = h[0];
-        }
-        // hard visibility: only visible secondary rays contribute
-        const float vj = hard ? (vo > 0.0f ? 1.0f : 0.0f) : sigmoidf_(vo);
-        const float3 c = nhead ? pi_brdf(nb, vb, wj, ab, rb, mb, a.f0, diffuse) : fb_.eval(dot3(nb, wj));
-        Lx = fmaf(c.x * vj, Ej.x, Lx);
-        Ly = fmaf(c.y * vj, Ej.y, Ly);
-        Lz = fmaf(c.z * vj, Ej.z, Lz);
-    }
-    const float inv = 1.0f / (float)a.s.n_dirs2;
-    return make_float3(Lx * inv, Ly * inv, Lz * inv);
+    const SecondaryBrdf sb{nb, vb, ab, rb, mb, a.f0, diffuse, fb_};
+    return nhead ? secondary_lo<PP, true>(a, tiles, W, T, bpt, lane, g, frb, sb, pid, q, hard)
+                 : secondary_lo<PP, false>(a, tiles, W, T, bpt, lane, g, frb, sb, pid, q, hard);
 }
 
 // ============================================================================
@@ -596,7 +643,7 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mma(const RenderK a, int
                 }
                 Le_own = env_lookup(a.env, w_own.x, w_own.y, w_own.z);  // overlaps the tracer
                 wave_sync_lds();
-                PP::store_dir(W, lane, w_own);
+                PP::store_dir(W, 0, lane, w_own);
                 wave_sync_lds();
                 float o0 = 0.f, o1 = 0.f;
 #pragma unroll
@@ -613,7 +660,7 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mma(const RenderK a, int
                             c[m] = f32x4{v4.x, v4.y, v4.z, v4.w};
                         }
                     }
-                    const f32x4 h = PP::tracer(T, tiles, W, nt, lane, c);
+                    const f32x4 h = PP::tracer(T, tiles, W, 0, nt, lane, c);
                     if (g == nt) {
                         o0 = h[0];
                         o1 = h[1];
