@@ -1,23 +1,23 @@
 // hg_render_mfma.hip -- forward on the CDNA4 matrix cores, FP32 and mixed.
 //
 // Two precisions share one kernel body:
-//   FP32:  FP32 tables, FP32 weights, v_mfma_f32_16x16x4f32 (K = 4 per step);
+//   FP32:  FP32 tables, FP32 weights, v_mfma_f32_32x32x2f32 (K = 2 per step),
+//          output heads on the vector ALU;
 //   mixed: FP16 tables (FP32 interpolation), BF16 weights and activations,
 //          v_mfma_f32_16x16x32_bf16 (K = 32 per step), FP32 accumulation.
 // The light-direction sum is compensated FP32 in both.
 //
 // Work decomposition.  A wave owns 64 queries (one per lane) for the scalar
 // work: direction sampling, hash-grid gathers, environment lookups, BRDF.
-// Each MLP evaluation of the 64 queries is four 16-column N-tiles of
-// matrix-core products with the units of a layer as rows (M) and the
-// queries as columns (N):
-//   layer output D (16x16 per M-tile): lane l holds rows 4*(l/16)+r,
-//   column l%16 -- so the accumulators of one layer, after ReLU (and, mixed,
-//   conversion to BF16), are already the B operand of the next layer once
-//   the weight columns are permuted accordingly (no data movement between
-//   layers);
-//   head rows are replicated so that every lane group receives the outputs
-//   of its column; lane l keeps N-tile l/16, which is its own query.
+// Each MLP evaluation of the 64 queries is a set of matrix-core products
+// with the units of a layer as rows (M) and the queries as columns (N):
+// two 32-column N-tiles (FP32) or four 16-column N-tiles (mixed).  In both,
+// the accumulators of one layer, after ReLU (and, mixed, conversion to
+// BF16), are already the B operand of the next layer once the weight columns
+// are permuted accordingly (no data movement between layers).  Mixed: the
+// 16x16 output D of an M-tile gives lane l rows 4*(l/16)+r of column l%16,
+// head rows are replicated so that every lane group receives the outputs of
+// its column, and lane l keeps N-tile l/16, which is its own query.
 // Inputs that come from other lanes (features, directions) go through LDS.
 // The tracer's first layer is split into a per-point part (W0f f + b0,
 // computed once per point and used as the accumulator input) and a
@@ -67,12 +67,10 @@ __device__ __forceinline__ uint4 act_pack(const f32x4 &d0, const f32x4 &d1) {
     return r;
 }
 
-// Physical hidden unit feeding logical input k of a layer whose input is the
-// previous layer's accumulator tiles.  BF16 (K-step s of 32, lane group g,
-// element e): k = 32 s + 8 g + e.  FP32 (K-step s of 4, lane group g):
-// k = 4 s + g.
+// Physical hidden unit feeding logical input k = 32 s + 8 g + e of a BF16
+// layer (K-step s, lane group g, element e) whose input is the previous
+// layer's accumulator tiles.
 __device__ __forceinline__ int unit_bf16(int s, int g, int e) { return 16 * (2 * s + (e >> 2)) + 4 * g + (e & 3); }
-__device__ __forceinline__ int unit_f32(int s, int g) { return 16 * (s >> 2) + 4 * g + (s & 3); }
 
 __device__ __forceinline__ float wbf(const void *W, int idx) {
     return __uint_as_float((uint32_t) static_cast<const uint16_t *>(W)[idx] << 16);
@@ -119,6 +117,7 @@ struct Bf16Path {
         N_TILES = 34
     };
     typedef uint4 Tile;  // 8 BF16 per lane
+    static constexpr int kTileFloats = N_TILES * 64;  // LDS array length in Tiles
 
     struct Wave {
         uint4 x[64][4];   // per-query input features (32 BF16)
@@ -170,7 +169,8 @@ struct Bf16Path {
     struct Tracer {
         uint4 w0w[4], w1[8], w2[2];
         f32x4 b1[4], b2;
-        __device__ void load(const Tile *tiles, const RenderK &a, int lane, int g) {
+        __device__ void load(const Tile *tiles, const RenderK &a, int lane) {
+            const int g = lane >> 4;
 #pragma unroll
             for (int m = 0; m < 4; ++m) w0w[m] = tiles[(T_W0W + m) * 64 + lane];
 #pragma unroll
@@ -199,8 +199,8 @@ struct Bf16Path {
     }
 
     // tracer point part W0f x + b0 of N-tile nt
-    static __device__ __forceinline__ void point_part(const Tile *tiles, const RenderK &a, const Wave &W, int nt,
-                                                      int lane, int g, f32x4 (&d)[4]) {
+    static __device__ __forceinline__ void point_part_nt(const Tile *tiles, const RenderK &a, const Wave &W, int nt,
+                                                         int lane, int g, f32x4 (&d)[4]) {
         const uint4 xb = W.x[16 * nt + (lane & 15)][g];
 #pragma unroll
         for (int m = 0; m < 4; ++m) d[m] = mfma_bf16(tiles[(T_W0F + m) * 64 + lane], xb, bias_tile(a.irt.b0, m, g));
@@ -208,8 +208,8 @@ struct Bf16Path {
 
     // decoder on the features of N-tile nt: oa rows 0..3 = outputs 0..3,
     // ob row 0 = output 4
-    static __device__ __forceinline__ void decoder(const Tile *tiles, const RenderK &a, const Wave &W, int nt,
-                                                   int lane, int g, f32x4 &oa, f32x4 &ob) {
+    static __device__ __forceinline__ void decoder_nt(const Tile *tiles, const RenderK &a, const Wave &W, int nt,
+                                                      int lane, int g, f32x4 &oa, f32x4 &ob) {
         const uint4 xb = W.x[16 * nt + (lane & 15)][g];
         f32x4 d[4];
 #pragma unroll
@@ -228,8 +228,8 @@ struct Bf16Path {
     }
 
     // tracer for N-tile nt from the point part c: returns the head tile
-    static __device__ __forceinline__ f32x4 tracer(const Tracer &T, const Tile *, const Wave &W, int buf, int nt,
-                                                   int lane, const f32x4 (&c)[4]) {
+    static __device__ __forceinline__ f32x4 tracer_nt(const Tracer &T, const Tile *, const Wave &W, int buf, int nt,
+                                                      int lane, const f32x4 (&c)[4]) {
         const uint4 ob_ = W.om[buf][16 * nt + (lane & 15)];
         f32x4 d[4];
 #pragma unroll
@@ -245,81 +245,205 @@ struct Bf16Path {
         f32x4 o = mfma_bf16(T.w2[0], k0, T.b2);
         return mfma_bf16(T.w2[1], k1, o);
     }
+
+    // ---- whole-wave interface (four 16-column N-tiles) ----
+    struct PointPart {
+        f32x4 v[4][4];  // [M-tile][N-tile]
+    };
+    static __device__ __forceinline__ void point_part(const Tile *tiles, const RenderK &a, const Wave &W, int lane,
+                                                      PointPart &pp) {
+        const int g = lane >> 4;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            f32x4 d[4];
+            point_part_nt(tiles, a, W, nt, lane, g, d);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) pp.v[m][nt] = d[m];
+        }
+    }
+    // decoder outputs of the lane's own query (N-tile l / 16)
+    static __device__ __forceinline__ void decoder(const Tile *tiles, const RenderK &a, const Wave &W, int lane,
+                                                   float (&o)[8]) {
+        const int g = lane >> 4;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) o[k] = 0.0f;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            f32x4 oa, ob;
+            decoder_nt(tiles, a, W, nt, lane, g, oa, ob);
+            if (g == nt) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    o[r] = oa[r];
+                    o[4 + r] = ob[r];
+                }
+            }
+        }
+    }
+    // shade mode: decoder outputs and tracer point part of the pixel slots
+    // (feature rows 0 .. ppw - 1) into W.mat / W.ax
+    static __device__ __forceinline__ void pixel_setup(const Tile *tiles, const RenderK &a, Wave &W, int lane,
+                                                       int ppw) {
+        const int g = lane >> 4, jcol = lane & 15;
+        f32x4 oa, ob, ax[4];
+        decoder_nt(tiles, a, W, 0, lane, g, oa, ob);
+        point_part_nt(tiles, a, W, 0, lane, g, ax);
+        if (jcol < ppw) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) W.ax[jcol][16 * m + 4 * g + r] = ax[m][r];
+            if (g == 0) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) W.mat[jcol][r] = oa[r];
+                W.mat[jcol][4] = ob[0];
+            }
+        }
+    }
+    // shade mode: columns of N-tile nt belong to pixel slot (16 nt) >> gs
+    static __device__ __forceinline__ void pixel_point_part(const Wave &W, int lane, uint32_t gs, PointPart &pp) {
+        const int g = lane >> 4;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const float4 v4 = *reinterpret_cast<const float4 *>(&W.ax[(16 * nt) >> gs][16 * m + 4 * g]);
+                pp.v[m][nt] = f32x4{v4.x, v4.y, v4.z, v4.w};
+            }
+    }
+    template <bool DEPTH>
+    static __device__ __forceinline__ float2 tracer(const Tracer &T, const Tile *tiles, const Wave &W, int buf,
+                                                    int lane, const PointPart &pp) {
+        const int g = lane >> 4;
+        float o0 = 0.f, o1 = 0.f;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const f32x4 c[4] = {pp.v[0][nt], pp.v[1][nt], pp.v[2][nt], pp.v[3][nt]};
+            const f32x4 hh = tracer_nt(T, tiles, W, buf, nt, lane, c);
+            if (g == nt) {
+                o0 = hh[0];
+                o1 = hh[1];
+            }
+        }
+        return make_float2(o0, DEPTH ? o1 : 0.0f);
+    }
 };
 
 // ============================================================================
-// FP32 path: FP32 operands, K = 4 per matrix-core step.
+// FP32 path: FP32 operands on v_mfma_f32_32x32x2f32 (K = 2 per step).
+// One wave's 64 queries are two 32-column N-tiles; a 64-unit layer is two
+// 32-row M-tiles.  Lane l supplies A[l % 32][l / 32] and B[l / 32][l % 32]
+// and receives, in accumulator register r, row 8 (r / 4) + 4 (l / 32) +
+// r % 4 of column l % 32.  With only four accumulator chains per layer
+// (2 M-tiles x 2 N-tiles) this shape keeps the matrix pipe at its full rate
+// from one wave, where the 16x16x4 shape needs four times as many chains.
+// The output heads (2 tracer logits, 5 or 8 decoder outputs) are dot
+// products on the vector ALU over the 32 units a lane holds, completed by
+// one exchange between the two lane halves.
 // ============================================================================
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ f32x16 mfma32(float a, float b, const f32x16 &c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+// max(x, 0) in one instruction (median of x, 0 and +inf)
+__device__ __forceinline__ float relu1(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, __builtin_huge_valf()); }
+// row of accumulator register r in lane half h, within a 32-row M-tile
+__device__ __forceinline__ int row32(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
+// physical hidden unit fed by K-step s (0..31) in lane half h: M-tile s / 16,
+// accumulator register s % 16 of the previous layer
+__device__ __forceinline__ int unit32(int s, int h) { return 32 * (s >> 4) + row32(s & 15, h); }
+
 struct F32Path {
     typedef float Table;
-    // tracer and decoder operand tiles in LDS (62.5 KB)
+    // operand tiles (64 floats each: lane l holds A[l % 32][l / 32])
     enum : int {
-        T_W0W = 0,       // tracer: 4 M-tiles, one K-step (w_x, w_y, w_z, 0)
-        T_W0F = 4,       // 4 M-tiles x 8 K-steps (m*8 + s)
-        T_W1 = 36,       // 4 M-tiles x 16 K-steps (m*16 + s)
-        T_W2 = 100,      // 16 K-steps
-        D_W0 = 116,      // decoder: 4 M-tiles x 8 K-steps (m*8 + s)
-        D_W1 = 148,      // 4 M-tiles x 16 K-steps (m*16 + s)
-        D_W2A = 212,     // outputs 0..3, 16 K-steps
-        D_W2B = 228,     // outputs 4..7, 16 K-steps
-        N_TILES = 244
+        T_W0W = 0,    // tracer direction part: 2 M-tiles x 2 K-steps (m*2 + s), components 2s + h
+        T_W0F = 4,    // tracer point part: 2 x 16 K-steps (m*16 + s), feature 16h + s
+        T_W1 = 36,    // tracer hidden layer: 2 x 32 K-steps (m*32 + s)
+        D_W0 = 100,   // decoder first layer: 2 x 16 K-steps, feature 16h + s
+        D_W1 = 132,   // decoder hidden layer: 2 x 32 K-steps
+        N_TILES = 196
     };
+    // head weights for the vector ALU after the tiles: [half][output][16 m + r]
+    static constexpr int HT_OFF = N_TILES * 64;      // tracer: 2 halves x 2 outputs x 32
+    static constexpr int HD_OFF = HT_OFF + 128;      // decoder: 2 halves x 8 outputs x 32
+    static constexpr int N_FLOATS = HD_OFF + 512;
     typedef float Tile;
-    static constexpr int kXS = 36;  // row stride of the feature rows (16-byte aligned, 2-way banks)
+    static constexpr int kTileFloats = N_FLOATS;
+    static constexpr int kXS = 36;  // row stride of the feature rows (16-byte aligned)
 
     struct Wave {
-        float x[64][kXS];
-        float4 om[2][64];
-        float ax[4][kH];
-        float mat[4][8];
-        uint16_t qi[128];
-        float qd[128];
+        float x[64][kXS];   // per-query input features
+        float4 om[2][64];   // per-query direction (x, y, z, 0), two buffers
+        float ax[4][kH];    // per-pixel tracer point part (shade mode)
+        float mat[4][8];    // per-pixel decoder outputs (shade mode)
+        uint16_t qi[128];   // queued shadow rays (hard visibility): direction index
+        float qd[128];      // and normalised depth
     };
 
-    static __device__ __forceinline__ float tile_value(const WSrc &a, int t, int i, int g) {
+    struct PointPart {
+        f32x16 c[2][2];     // [M-tile][N-tile]
+    };
+
+    static __device__ __forceinline__ float tile_value(const WSrc &a, int q) {
+        if (q >= HD_OFF) {
+            const int t = q - HD_OFF, h = t >> 8, o = (t >> 5) & 7, mr = t & 31;
+            return o < a.nout ? wf(a.bW2, o * kH + 32 * (mr >> 4) + row32(mr & 15, h)) : 0.0f;
+        }
+        if (q >= HT_OFF) {
+            const int t = q - HT_OFF, h = t >> 6, o = (t >> 5) & 1, mr = t & 31;
+            return wf(a.iW2, o * kH + 32 * (mr >> 4) + row32(mr & 15, h));
+        }
+        const int t = q >> 6, l = q & 63, i = l & 31, h = l >> 5;
         if (t < T_W0F) {
-            const int m = t - T_W0W;
-            return g < 3 ? wf(a.iW0, (16 * m + i) * kNI + kNF + g) : 0.0f;
+            const int m = (t - T_W0W) >> 1, c = 2 * ((t - T_W0W) & 1) + h;
+            return c < 3 ? wf(a.iW0, (32 * m + i) * kNI + kNF + c) : 0.0f;
         }
         if (t < T_W1) {
-            const int m = (t - T_W0F) >> 3, s = (t - T_W0F) & 7;
-            return wf(a.iW0, (16 * m + i) * kNI + 4 * s + g);
-        }
-        if (t < T_W2) {
-            const int m = (t - T_W1) >> 4, s = (t - T_W1) & 15;
-            return wf(a.iW1, (16 * m + i) * kH + unit_f32(s, g));
+            const int m = (t - T_W0F) >> 4, st = (t - T_W0F) & 15;
+            return wf(a.iW0, (32 * m + i) * kNI + 16 * h + st);
         }
         if (t < D_W0) {
-            const int s = t - T_W2, r = i & 3;
-            return r < 2 ? wf(a.iW2, r * kH + unit_f32(s, g)) : 0.0f;
+            const int m = (t - T_W1) >> 5, st = (t - T_W1) & 31;
+            return wf(a.iW1, (32 * m + i) * kH + unit32(st, h));
         }
         if (t < D_W1) {
-            const int m = (t - D_W0) >> 3, s = (t - D_W0) & 7;
-            return wf(a.bW0, (16 * m + i) * kNF + 4 * s + g);
+            const int m = (t - D_W0) >> 4, st = (t - D_W0) & 15;
+            return wf(a.bW0, (32 * m + i) * kNF + 16 * h + st);
         }
-        if (t < D_W2A) {
-            const int m = (t - D_W1) >> 4, s = (t - D_W1) & 15;
-            return wf(a.bW1, (16 * m + i) * kH + unit_f32(s, g));
-        }
-        const int r = i & 3;
-        if (t < D_W2B) return wf(a.bW2, r * kH + unit_f32(t - D_W2A, g));
-        return 4 + r < a.nout ? wf(a.bW2, (4 + r) * kH + unit_f32(t - D_W2B, g)) : 0.0f;
+        const int m = (t - D_W1) >> 5, st = (t - D_W1) & 31;
+        return wf(a.bW1, (32 * m + i) * kH + unit32(st, h));
     }
 
     static __device__ __forceinline__ void build_tiles(const RenderK &ka, Tile *tiles) {
         const WSrc a = wsrc(ka);
-        for (int q = threadIdx.x; q < N_TILES * 64; q += blockDim.x) {
-            const int t = q >> 6, l = q & 63;
-            tiles[q] = tile_value(a, t, l & 15, l >> 4);
+        for (int q = threadIdx.x; q < N_FLOATS; q += blockDim.x) tiles[q] = tile_value(a, q);
+    }
+
+    // accumulator rows of M-tile m in lane half h, from a bias vector
+    static __device__ __forceinline__ f32x16 bias32(const float *b, int m, int h) {
+        f32x16 r;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 v = *reinterpret_cast<const float4 *>(b + 32 * m + 8 * q + 4 * h);
+            r[4 * q] = v.x;
+            r[4 * q + 1] = v.y;
+            r[4 * q + 2] = v.z;
+            r[4 * q + 3] = v.w;
         }
+        return r;
     }
 
     struct Tracer {
-        f32x4 b1[4], b2;
-        __device__ void load(const Tile *, const RenderK &a, int, int g) {
-#pragma unroll
-            for (int m = 0; m < 4; ++m) b1[m] = bias_tile(a.irt.b1, m, g);
-            b2 = head_bias(a.irt.b2, 2, 0);
+        f32x16 b1[2];
+        float hb0, hb1;
+        __device__ void load(const Tile *, const RenderK &a, int lane) {
+            const int h = lane >> 5;
+            b1[0] = bias32(a.irt.b1, 0, h);
+            b1[1] = bias32(a.irt.b1, 1, h);
+            hb0 = a.irt.b2[0];
+            hb1 = a.irt.b2[1];
         }
     };
 
@@ -335,70 +459,186 @@ struct F32Path {
         W.om[buf][lane] = make_float4(w.x, w.y, w.z, 0.0f);
     }
 
-    static __device__ __forceinline__ void point_part(const Tile *tiles, const RenderK &a, const Wave &W, int nt,
-                                                      int lane, int g, f32x4 (&d)[4]) {
-        const float *xr = W.x[16 * nt + (lane & 15)];
+    // features 16h .. 16h + 15 of query row 32 nt + lane % 32
+    static __device__ __forceinline__ void load_feat(const Wave &W, int nt, int lane, float (&xv)[16]) {
+        const float *xr = &W.x[32 * nt + (lane & 31)][16 * (lane >> 5)];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) d[m] = bias_tile(a.irt.b0, m, g);
-#pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            const float b = xr[4 * s + g];
-#pragma unroll
-            for (int m = 0; m < 4; ++m) d[m] = mfma_f32(tiles[(T_W0F + 8 * m + s) * 64 + lane], b, d[m]);
+        for (int q = 0; q < 4; ++q) {
+            const float4 v = *reinterpret_cast<const float4 *>(xr + 4 * q);
+            xv[4 * q] = v.x;
+            xv[4 * q + 1] = v.y;
+            xv[4 * q + 2] = v.z;
+            xv[4 * q + 3] = v.w;
         }
     }
 
-    static __device__ __forceinline__ void decoder(const Tile *tiles, const RenderK &a, const Wave &W, int nt,
-                                                   int lane, int g, f32x4 &oa, f32x4 &ob) {
-        const float *xr = W.x[16 * nt + (lane & 15)];
-        f32x4 d[4];
+    // first layer over the features: out[m][nt] = b + W x for NT N-tiles
+    template <int NT>
+    static __device__ __forceinline__ void feat_layer(const Tile *tiles, int base, const float *bias, const Wave &W,
+                                                      int lane, f32x16 (&out)[2][2]) {
+        const int h = lane >> 5;
+        float xv[2][16];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) d[m] = bias_tile(a.brdf.b0, m, g);
+        for (int nt = 0; nt < NT; ++nt) load_feat(W, nt, lane, xv[nt]);
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            const float b = xr[4 * s + g];
+        for (int m = 0; m < 2; ++m) {
+            const f32x16 b = bias32(bias, m, h);
 #pragma unroll
-            for (int m = 0; m < 4; ++m) d[m] = mfma_f32(tiles[(D_W0 + 8 * m + s) * 64 + lane], b, d[m]);
+            for (int nt = 0; nt < NT; ++nt) out[m][nt] = b;
         }
-        f32x4 e[4];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) e[m] = bias_tile(a.brdf.b1, m, g);
+        for (int st = 0; st < 16; ++st)
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            const float b = fmaxf(d[s >> 2][s & 3], 0.0f);
+            for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-            for (int m = 0; m < 4; ++m) e[m] = mfma_f32(tiles[(D_W1 + 16 * m + s) * 64 + lane], b, e[m]);
+                for (int m = 0; m < 2; ++m)
+                    out[m][nt] = mfma32(tiles[(base + 16 * m + st) * 64 + lane], xv[nt][st], out[m][nt]);
+    }
+
+    // hidden layer: out[m][nt] = bias + W relu(in)
+    template <int NT>
+    static __device__ __forceinline__ void hidden_layer(const Tile *tiles, int base, const f32x16 (&bias)[2],
+                                                        const f32x16 (&in)[2][2], int lane, f32x16 (&out)[2][2]) {
+#pragma unroll
+        for (int st = 0; st < 32; ++st)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const float b = relu1(in[st >> 4][nt][st & 15]);
+#pragma unroll
+                for (int m = 0; m < 2; ++m)
+                    out[m][nt] = mfma32(tiles[(base + 32 * m + st) * 64 + lane], b, st == 0 ? bias[m] : out[m][nt]);
+            }
+    }
+
+    // head output o of NT N-tiles: this lane's partial over its 32 units,
+    // completed across the lane halves.  NT = 2: the lane's own query
+    // (N-tile l / 32); NT = 1: query l % 32 of N-tile 0.
+    template <int NT>
+    static __device__ __forceinline__ float head(const float *hw, const float (&re)[2][32], int lane) {
+        float p[2] = {0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const float4 w = *reinterpret_cast<const float4 *>(hw + 4 * q);
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                p[nt] = fmaf(re[nt][4 * q], w.x, p[nt]);
+                p[nt] = fmaf(re[nt][4 * q + 1], w.y, p[nt]);
+                p[nt] = fmaf(re[nt][4 * q + 2], w.z, p[nt]);
+                p[nt] = fmaf(re[nt][4 * q + 3], w.w, p[nt]);
+            }
         }
-        oa = head_bias(a.brdf.b2, 5, 0);
-        ob = head_bias(a.brdf.b2, a.brdf_out, 4);
+        const bool hi = (lane >> 5) != 0;
+        const float own = (NT == 2 && hi) ? p[1] : p[0];
+        const float send = NT == 2 ? (hi ? p[0] : p[1]) : p[0];
+        return own + __shfl_xor(send, 32);
+    }
+
+    static __device__ __forceinline__ void relu_all(const f32x16 (&e)[2][2], int nt, float (&re)[32]) {
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            const float b = fmaxf(e[s >> 2][s & 3], 0.0f);
-            oa = mfma_f32(tiles[(D_W2A + s) * 64 + lane], b, oa);
-            ob = mfma_f32(tiles[(D_W2B + s) * 64 + lane], b, ob);
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) re[16 * m + r] = relu1(e[m][nt][r]);
+    }
+
+    // tracer point part W0f f + b0 of all 64 queries
+    static __device__ __forceinline__ void point_part(const Tile *tiles, const RenderK &a, const Wave &W, int lane,
+                                                      PointPart &pp) {
+        feat_layer<2>(tiles, T_W0F, a.irt.b0, W, lane, pp.c);
+    }
+
+    // decoder outputs (up to 8) of the lane's own query (NT = 2) or of query
+    // lane % 32 (NT = 1)
+    template <int NT>
+    static __device__ __forceinline__ void decoder_nt(const Tile *tiles, const RenderK &a, const Wave &W, int lane,
+                                                      float (&o)[8]) {
+        const int h = lane >> 5;
+        f32x16 d[2][2], e[2][2];
+        feat_layer<NT>(tiles, D_W0, a.brdf.b0, W, lane, d);
+        const f32x16 b1[2] = {bias32(a.brdf.b1, 0, h), bias32(a.brdf.b1, 1, h)};
+        hidden_layer<NT>(tiles, D_W1, b1, d, lane, e);
+        float re[2][32];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) relu_all(e, nt, re[nt]);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            o[k] = 0.0f;
+            if (k < a.brdf_out) o[k] = head<NT>(&tiles[HD_OFF + (8 * h + k) * 32], re, lane) + a.brdf.b2[k];
+        }
+    }
+    static __device__ __forceinline__ void decoder(const Tile *tiles, const RenderK &a, const Wave &W, int lane,
+                                                   float (&o)[8]) {
+        decoder_nt<2>(tiles, a, W, lane, o);
+    }
+
+    // shade mode: decoder outputs and tracer point part of the pixel slots
+    // (feature rows 0 .. ppw - 1) into W.mat / W.ax
+    static __device__ __forceinline__ void pixel_setup(const Tile *tiles, const RenderK &a, Wave &W, int lane,
+                                                       int ppw) {
+        const int h = lane >> 5, j = lane & 31;
+        float o[8];
+        decoder_nt<1>(tiles, a, W, lane, o);
+        f32x16 c[2][2];
+        feat_layer<1>(tiles, T_W0F, a.irt.b0, W, lane, c);
+        if (j < ppw) {
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) W.ax[j][32 * m + row32(r, h)] = c[m][0][r];
+            if (h == 0) {
+#pragma unroll
+                for (int k = 0; k < 5; ++k) W.mat[j][k] = o[k];
+            }
         }
     }
 
-    static __device__ __forceinline__ f32x4 tracer(const Tracer &T, const Tile *tiles, const Wave &W, int buf, int nt,
-                                                   int lane, const f32x4 (&c)[4]) {
-        const int g = lane >> 4;
-        const float b0 = reinterpret_cast<const float *>(&W.om[buf][16 * nt + (lane & 15)])[g];
-        f32x4 d[4];
+    // shade mode: the point part of each query's pixel slot ((32 nt + l % 32) >> gs)
+    static __device__ __forceinline__ void pixel_point_part(const Wave &W, int lane, uint32_t gs, PointPart &pp) {
+        const int h = lane >> 5, j = lane & 31;
 #pragma unroll
-        for (int m = 0; m < 4; ++m) d[m] = mfma_f32(tiles[(T_W0W + m) * 64 + lane], b0, c[m]);
-        f32x4 e[4];
+        for (int nt = 0; nt < 2; ++nt) {
+            const float *ar = W.ax[(32 * nt + j) >> gs];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) e[m] = T.b1[m];
+            for (int m = 0; m < 2; ++m)
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            const float b = fmaxf(d[s >> 2][s & 3], 0.0f);
-#pragma unroll
-            for (int m = 0; m < 4; ++m) e[m] = mfma_f32(tiles[(T_W1 + 16 * m + s) * 64 + lane], b, e[m]);
+                for (int q = 0; q < 4; ++q) {
+                    const float4 v = *reinterpret_cast<const float4 *>(ar + 32 * m + 8 * q + 4 * h);
+                    pp.c[m][nt][4 * q] = v.x;
+                    pp.c[m][nt][4 * q + 1] = v.y;
+                    pp.c[m][nt][4 * q + 2] = v.z;
+                    pp.c[m][nt][4 * q + 3] = v.w;
+                }
         }
-        f32x4 o = T.b2;
+    }
+
+    // tracer logits (visibility, and depth if DEPTH) of the lane's own query,
+    // direction operand buffer buf
+    template <bool DEPTH>
+    static __device__ __forceinline__ float2 tracer(const Tracer &T, const Tile *tiles, const Wave &W, int buf,
+                                                    int lane, const PointPart &pp) {
+        const int h = lane >> 5, j = lane & 31;
+        float bd[2][2];
 #pragma unroll
-        for (int s = 0; s < 16; ++s) o = mfma_f32(tiles[(T_W2 + s) * 64 + lane], fmaxf(e[s >> 2][s & 3], 0.0f), o);
-        return o;
+        for (int nt = 0; nt < 2; ++nt) {
+            const float4 w = W.om[buf][32 * nt + j];
+            bd[nt][0] = h ? w.y : w.x;
+            bd[nt][1] = h ? w.w : w.z;
+        }
+        f32x16 d[2][2];
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                d[m][nt] = mfma32(tiles[(T_W0W + 2 * m) * 64 + lane], bd[nt][0], pp.c[m][nt]);
+                d[m][nt] = mfma32(tiles[(T_W0W + 2 * m + 1) * 64 + lane], bd[nt][1], d[m][nt]);
+            }
+        f32x16 e[2][2];
+        hidden_layer<2>(tiles, T_W1, T.b1, d, lane, e);
+        float re[2][32];
+        relu_all(e, 0, re[0]);
+        relu_all(e, 1, re[1]);
+        const float o0 = head<2>(&tiles[HT_OFF + (2 * h) * 32], re, lane) + T.hb0;
+        const float o1 = DEPTH ? head<2>(&tiles[HT_OFF + (2 * h + 1) * 32], re, lane) + T.hb1 : 0.0f;
+        return make_float2(o0, o1);
     }
 };
 
@@ -426,7 +666,7 @@ struct SecondaryBrdf {
 template <class PP, bool NHEAD>
 __device__ __forceinline__ float3 secondary_lo(const RenderK &a, const typename PP::Tile *tiles,
                                                typename PP::Wave &W, const typename PP::Tracer &T,
-                                               const f32x4 (&bpt)[4][4], int lane, int g, const Frame &frb,
+                                               const typename PP::PointPart &bpt, int lane, const Frame &frb,
                                                const SecondaryBrdf &sb, uint32_t pid, uint32_t q, bool hard) {
     const uint32_t n2 = a.s.n_dirs2;
     uint4 words2 = philox4x32_10(pid, q, 0u, 1u, a.s.key0, a.s.key1);
@@ -443,13 +683,7 @@ __device__ __forceinline__ float3 secondary_lo(const RenderK &a, const typename 
         const float3 wn = sample_dir(pick4(words2, jn), jn, a.s.nb2_shift, a.s.inv_na2, a.s.inv_nb2, frb);
         const float3 En = env_lookup(a.env, wn.x, wn.y, wn.z);
         const float3 cn = sb.eval<NHEAD>(wn);
-        float vo = 0.f;
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            const f32x4 c[4] = {bpt[0][nt], bpt[1][nt], bpt[2][nt], bpt[3][nt]};
-            const f32x4 h = PP::tracer(T, tiles, W, (int)(j & 1u), nt, lane, c);
-            if (g == nt) vo = h[0];
-        }
+        const float vo = PP::template tracer<false>(T, tiles, W, (int)(j & 1u), lane, bpt).x;
         PP::store_dir(W, (int)((j + 1) & 1u), lane, wn);
         // hard visibility: only visible secondary rays contribute
         const float vj = hard ? (vo > 0.0f ? 1.0f : 0.0f) : sigmoidf_(vo);
@@ -470,7 +704,7 @@ __device__ __forceinline__ float3 secondary_lo(const RenderK &a, const typename 
 // ============================================================================
 template <class PP, class TT>
 __device__ __forceinline__ float3 bounce_lo(const RenderK &a, const typename PP::Tile *tiles, typename PP::Wave &W,
-                                            const typename PP::Tracer &T, int lane, int g, float3 x, float3 w,
+                                            const typename PP::Tracer &T, int lane, float3 x, float3 w,
                                             float dd, uint32_t pid, uint32_t q, bool hard, bool diffuse) {
     const float t = fmaf(a.t_span, dd, a.t_near);
     const float3 xb = make_float3(fmaf(t, w.x, x.x), fmaf(t, w.y, x.y), fmaf(t, w.z, x.z));
@@ -479,35 +713,24 @@ __device__ __forceinline__ float3 bounce_lo(const RenderK &a, const typename PP:
     wave_sync_lds();
     PP::store_feat(W, lane, fb);
     wave_sync_lds();
-    f32x4 bpt[4][4];
-    float ob0 = 0.f, ob1 = 0.f, ob2 = 0.f, ob3 = 0.f, ob4 = 0.f, on0 = 0.f, on1 = 0.f, on2 = 0.f;
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-        f32x4 d[4];
-        PP::point_part(tiles, a, W, nt, lane, g, d);
-#pragma unroll
-        for (int m = 0; m < 4; ++m) bpt[m][nt] = d[m];
-        f32x4 oa, obb;
-        PP::decoder(tiles, a, W, nt, lane, g, oa, obb);
-        if (g == nt) {
-            ob0 = oa[0]; ob1 = oa[1]; ob2 = oa[2]; ob3 = oa[3]; ob4 = obb[0];
-            on0 = obb[1]; on1 = obb[2]; on2 = obb[3];
-        }
-    }
-    const float3 ab = make_float3(sigmoidf_(ob0), sigmoidf_(ob1), sigmoidf_(ob2));
-    const float rb = 0.09f + 0.91f * sigmoidf_(ob3);
-    const float mb = sigmoidf_(ob4);
+    typename PP::PointPart bpt;
+    PP::point_part(tiles, a, W, lane, bpt);
+    float od[8];
+    PP::decoder(tiles, a, W, lane, od);
+    const float3 ab = make_float3(sigmoidf_(od[0]), sigmoidf_(od[1]), sigmoidf_(od[2]));
+    const float rb = 0.09f + 0.91f * sigmoidf_(od[3]);
+    const float mb = sigmoidf_(od[4]);
     // secondary view -w; normal from the decoder's normal head if it has one,
     // else the facing normal -w
     const float3 vb = make_float3(-w.x, -w.y, -w.z);
     const bool nhead = a.brdf_out == 8;
-    const float3 nb = nhead ? head_normal(on0, on1, on2, vb) : vb;
+    const float3 nb = nhead ? head_normal(od[5], od[6], od[7], vb) : vb;
     const Frame frb = make_frame(nb);
     FacingBrdf fb_;
     fb_.set(ab, rb, mb, a.f0, diffuse);
     const SecondaryBrdf sb{nb, vb, ab, rb, mb, a.f0, diffuse, fb_};
-    return nhead ? secondary_lo<PP, true>(a, tiles, W, T, bpt, lane, g, frb, sb, pid, q, hard)
-                 : secondary_lo<PP, false>(a, tiles, W, T, bpt, lane, g, frb, sb, pid, q, hard);
+    return nhead ? secondary_lo<PP, true>(a, tiles, W, T, bpt, lane, frb, sb, pid, q, hard)
+                 : secondary_lo<PP, false>(a, tiles, W, T, bpt, lane, frb, sb, pid, q, hard);
 }
 
 // ============================================================================
@@ -520,15 +743,14 @@ constexpr int kMixThreads = 256;
 template <class PP, bool INDIRECT, bool QUERY, bool MIS>
 __global__ __launch_bounds__(kMixThreads) void k_render_mma(const RenderK a, int64_t n_items) {
     typedef typename PP::Table TT;
-    __shared__ typename PP::Tile tiles[PP::N_TILES * 64];
+    __shared__ typename PP::Tile tiles[PP::kTileFloats];
     __shared__ typename PP::Wave wl[kMixThreads / 64];
     PP::build_tiles(a, tiles);
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    const int g = lane >> 4, jcol = lane & 15;
     typename PP::Wave &W = wl[threadIdx.x >> 6];
     typename PP::Tracer T;
-    T.load(tiles, a, lane, g);
+    T.load(tiles, a, lane);
 
     const bool diffuse = (a.s.flags & 1u) != 0;
     const bool hard = (a.s.flags & 2u) != 0;
@@ -547,7 +769,6 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mma(const RenderK a, int
         const float3 x = make_float3(a.pos[3 * p], a.pos[3 * p + 1], a.pos[3 * p + 2]);
 
         // ---------------- primary point ----------------
-        f32x4 apt[4][4];  // query mode: tracer point part at x per (M-tile, N-tile)
         float3 n_ = make_float3(0.f, 0.f, 1.f), v_ = n_, alb = n_;
         float rr = 0.5f, mm = 0.f;
         if (QUERY) {
@@ -555,13 +776,6 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mma(const RenderK a, int
             encode<TT>(a.g, x.x, x.y, x.z, f);
             PP::store_feat(W, lane, f);
             wave_sync_lds();
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                f32x4 d[4];
-                PP::point_part(tiles, a, W, nt, lane, g, d);
-#pragma unroll
-                for (int m = 0; m < 4; ++m) apt[m][nt] = d[m];
-            }
         } else {
             // lane l encodes level l % 16 of pixel slot l / 16
             const int slot = lane >> 4, lvl = lane & 15;
@@ -592,20 +806,7 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mma(const RenderK a, int
                 PP::store_level(W, slot, lvl, 0.0f, 0.0f);  // slot of a level the grid does not have
             }
             wave_sync_lds();
-            f32x4 oa, ob, ax[4];
-            PP::decoder(tiles, a, W, 0, lane, g, oa, ob);
-            PP::point_part(tiles, a, W, 0, lane, g, ax);
-            if (jcol < ppw) {
-#pragma unroll
-                for (int m = 0; m < 4; ++m)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) W.ax[jcol][16 * m + 4 * g + r] = ax[m][r];
-                if (g == 0) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) W.mat[jcol][r] = oa[r];
-                    W.mat[jcol][4] = ob[0];
-                }
-            }
+            PP::pixel_setup(tiles, a, W, lane, ppw);
             wave_sync_lds();
             const int myslot = lane >> gs;
             n_ = make_float3(a.nrm[3 * p], a.nrm[3 * p + 1], a.nrm[3 * p + 2]);
@@ -645,27 +846,13 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mma(const RenderK a, int
                 wave_sync_lds();
                 PP::store_dir(W, 0, lane, w_own);
                 wave_sync_lds();
-                float o0 = 0.f, o1 = 0.f;
-#pragma unroll
-                for (int nt = 0; nt < 4; ++nt) {
-                    f32x4 c[4];
-#pragma unroll
-                    for (int m = 0; m < 4; ++m) {
-                        if (QUERY) {
-                            c[m] = apt[m][nt];
-                        } else {
-                            // columns of N-tile nt belong to pixel slot (16 nt) >> gs
-                            const float4 v4 =
-                                *reinterpret_cast<const float4 *>(&W.ax[(16 * nt) >> gs][16 * m + 4 * g]);
-                            c[m] = f32x4{v4.x, v4.y, v4.z, v4.w};
-                        }
-                    }
-                    const f32x4 h = PP::tracer(T, tiles, W, 0, nt, lane, c);
-                    if (g == nt) {
-                        o0 = h[0];
-                        o1 = h[1];
-                    }
-                }
+                // tracer point part at x: query mode (one chunk per item) from
+                // the feature rows stored above, shade mode from the pixel slots
+                typename PP::PointPart c;
+                if (QUERY) PP::point_part(tiles, a, W, lane, c);
+                else PP::pixel_point_part(W, lane, gs, c);
+                const float2 oo = PP::template tracer<true>(T, tiles, W, 0, lane, c);
+                const float o0 = oo.x, o1 = oo.y;
                 V_own = hard ? (o0 > 0.0f ? 1.0f : 0.0f) : sigmoidf_(o0);
                 d_own = fminf(softplusf_(o1), 1.0f);
                 if (!QUERY && live && a.vis) {
@@ -721,7 +908,7 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mma(const RenderK a, int
             if (!INDIRECT) {
                 Lin = make_float3(Ve * Le_own.x, Ve * Le_own.y, Ve * Le_own.z);
             } else {
-                const float3 Lo = bounce_lo<PP, TT>(a, tiles, W, T, lane, g, x, we, de, (uint32_t)p,
+                const float3 Lo = bounce_lo<PP, TT>(a, tiles, W, T, lane, x, we, de, (uint32_t)p,
                                                     QUERY ? 0u : ie, hard, diffuse);
                 const float om = 1.0f - Ve;
                 Lin = make_float3(fmaf(Ve, Le_own.x, om * Lo.x), fmaf(Ve, Le_own.y, om * Lo.y),
