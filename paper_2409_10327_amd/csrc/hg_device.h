@@ -213,6 +213,9 @@ template <> struct TabLoad<float> {
     static __device__ __forceinline__ float2 ld(const void *lvl, uint32_t idx) {
         return *reinterpret_cast<const float2 *>(static_cast<const char *>(lvl) + (idx << 3));
     }
+    static __device__ __forceinline__ float2 ld_byte(const void *t, uint32_t off) {
+        return *reinterpret_cast<const float2 *>(static_cast<const char *>(t) + off);
+    }
     static __device__ __forceinline__ float2 ld(const void *t, size_t e) {
         return static_cast<const float2 *>(t)[e];
     }
@@ -223,6 +226,9 @@ template <> struct TabLoad<__half> {
     }
     static __device__ __forceinline__ float2 ld(const void *lvl, uint32_t idx) {
         return __half22float2(*reinterpret_cast<const __half2 *>(static_cast<const char *>(lvl) + (idx << 2)));
+    }
+    static __device__ __forceinline__ float2 ld_byte(const void *t, uint32_t off) {
+        return __half22float2(*reinterpret_cast<const __half2 *>(static_cast<const char *>(t) + off));
     }
     static __device__ __forceinline__ float2 ld(const void *t, size_t e) {
         return __half22float2(static_cast<const __half2 *>(t)[e]);
@@ -245,27 +251,34 @@ __device__ __forceinline__ void pos_to_u(const GridK &g, float x, float y, float
     }
 }
 
-// Table indices of the 8 corners of cell c at level l (corner bit 0 = +x,
-// bit 1 = +y, bit 2 = +z).  The dense/hashed choice is wave-uniform.
-__device__ __forceinline__ void corner_idx(const GridK &g, int l, const uint32_t (&c)[3], uint32_t (&idx)[8]) {
-    // both index forms are computed and selected, keeping the encoder free
-    // of branches (one straight-line scheduling region per level group)
-    const bool dense = (g.dense_mask >> l) & 1u;
-    const uint32_t s = g.stride[l];
+// Table indices of the 8 corners of cell c of a level that is dense (row
+// stride s) or hashed (mask Tmask); corner bit 0 = +x, bit 1 = +y, bit 2 = +z.
+// Both index forms are computed and selected, keeping the encoder free of
+// branches (one straight-line scheduling region per group of levels).
+__device__ __forceinline__ void corner_idx_p(bool dense, uint32_t s, uint32_t Tmask, const uint32_t (&c)[3],
+                                             uint32_t (&idx)[8]) {
     const uint32_t b = c[0] + s * (c[1] + s * c[2]);
     const uint32_t hy0 = c[1] * 2654435761u, hy1 = hy0 + 2654435761u;
     const uint32_t hz0 = c[2] * 805459861u, hz1 = hz0 + 805459861u;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const uint32_t di = b + (k & 1) + ((k >> 1) & 1) * s + ((k >> 2) & 1) * s * s;
-        const uint32_t hi = ((c[0] + (k & 1)) ^ ((k >> 1) & 1 ? hy1 : hy0) ^ ((k >> 2) & 1 ? hz1 : hz0)) & g.Tmask;
+        const uint32_t hi = ((c[0] + (k & 1)) ^ ((k >> 1) & 1 ? hy1 : hy0) ^ ((k >> 2) & 1 ? hz1 : hz0)) & Tmask;
         idx[k] = dense ? di : hi;
     }
 }
+// the same at level l of grid g (the dense/hashed choice is wave-uniform)
+__device__ __forceinline__ void corner_idx(const GridK &g, int l, const uint32_t (&c)[3], uint32_t (&idx)[8]) {
+    corner_idx_p(((g.dense_mask >> l) & 1u) != 0, g.stride[l], g.Tmask, c, idx);
+}
 
-// f = H(x), features level-major.  Levels are processed in groups of four
-// (32 gathers in flight per lane); the scheduling barrier keeps the compiler
-// from hoisting all 128 gathers, which would exhaust the register file.
+// f = H(x), features level-major.  Levels are processed in groups of four:
+// the 32 gathers of a group are all issued before a scheduling barrier and
+// interpolated after it, so that a group costs one memory round trip (left
+// to itself, the scheduler consumes each level's gathers before issuing the
+// next level's, which is 16 round trips).  The level loop has no branch: a
+// slot past the grid's L levels gathers entry 0 of level 0 (always in the
+// table) and its features are set to zero by a select.
 template <typename TT>
 __device__ __forceinline__ void encode(const GridK &g, float x, float y, float z, float (&f)[kNF]) {
     float u[3];
@@ -274,31 +287,37 @@ __device__ __forceinline__ void encode(const GridK &g, float x, float y, float z
 #pragma unroll
     for (int l0 = 0; l0 < kL; l0 += 4) {
         __builtin_amdgcn_sched_barrier(0);
+        float w[4][3];
+        float2 e[4][8];
 #pragma unroll
-        for (int l = l0; l < l0 + 4; ++l) {
+        for (int li = 0; li < 4; ++li) {
+            const int l = l0 + li;
+            const bool have = l < (int)g.L;  // wave-uniform
+            uint32_t c[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) cell_of(u[d], g.resf[l], g.nm1f[l], c[d], w[li][d]);
+            uint32_t idx[8];
+            corner_idx(g, l, c, idx);
+            const void *lvl = TabLoad<TT>::level(g.table, have ? l : 0, g.log2T);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) e[li][k] = TabLoad<TT>::ld(lvl, have ? idx[k] : 0u);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int li = 0; li < 4; ++li) {
+            const int l = l0 + li;
+            const float wx0 = 1.0f - w[li][0], wy0 = 1.0f - w[li][1], wz0 = 1.0f - w[li][2];
             float f0 = 0.0f, f1 = 0.0f;
-            if (l < (int)g.L) {  // wave-uniform
-                uint32_t c[3];
-                float w[3];
 #pragma unroll
-                for (int d = 0; d < 3; ++d) cell_of(u[d], g.resf[l], g.nm1f[l], c[d], w[d]);
-                uint32_t idx[8];
-                corner_idx(g, l, c, idx);
-                const void *lvl = TabLoad<TT>::level(g.table, l, g.log2T);
-                float2 e[8];
-#pragma unroll
-                for (int k = 0; k < 8; ++k) e[k] = TabLoad<TT>::ld(lvl, idx[k]);
-                const float wx0 = 1.0f - w[0], wy0 = 1.0f - w[1], wz0 = 1.0f - w[2];
-#pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const float wt =
-                        ((k & 1) ? w[0] : wx0) * (((k >> 1) & 1) ? w[1] : wy0) * (((k >> 2) & 1) ? w[2] : wz0);
-                    f0 = fmaf(wt, e[k].x, f0);
-                    f1 = fmaf(wt, e[k].y, f1);
-                }
+            for (int k = 0; k < 8; ++k) {
+                const float wt = ((k & 1) ? w[li][0] : wx0) * (((k >> 1) & 1) ? w[li][1] : wy0) *
+                                 (((k >> 2) & 1) ? w[li][2] : wz0);
+                f0 = fmaf(wt, e[li][k].x, f0);
+                f1 = fmaf(wt, e[li][k].y, f1);
             }
-            f[2 * l] = f0;
-            f[2 * l + 1] = f1;
+            const bool have = l < (int)g.L;
+            f[2 * l] = have ? f0 : 0.0f;
+            f[2 * l + 1] = have ? f1 : 0.0f;
         }
     }
     __builtin_amdgcn_sched_barrier(0);

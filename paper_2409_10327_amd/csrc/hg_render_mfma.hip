@@ -100,10 +100,12 @@ __device__ __forceinline__ void wave_sync_lds() {
 // private memory).
 struct WSrc {
     const void *iW0, *iW1, *iW2, *bW0, *bW1, *bW2;
+    const float *ib0, *ib1, *bb0, *bb1;
     int nout;
 };
 __device__ __forceinline__ WSrc wsrc(const RenderK &a) {
-    return WSrc{a.irt.W0, a.irt.W1, a.irt.W2, a.brdf.W0, a.brdf.W1, a.brdf.W2, a.brdf_out};
+    return WSrc{a.irt.W0, a.irt.W1, a.irt.W2, a.brdf.W0, a.brdf.W1, a.brdf.W2,
+                a.irt.b0, a.irt.b1, a.brdf.b0, a.brdf.b1, a.brdf_out};
 }
 
 // ============================================================================
@@ -118,6 +120,8 @@ struct Bf16Path {
     };
     typedef uint4 Tile;  // 8 BF16 per lane
     static constexpr int kTileFloats = N_TILES * 64;  // LDS array length in Tiles
+    static constexpr int kThreads = 256;              // one wave per SIMD
+    static constexpr bool kHalfBounce = false;        // bounce of all 64 points at once
 
     struct Wave {
         uint4 x[64][4];   // per-query input features (32 BF16)
@@ -261,6 +265,14 @@ struct Bf16Path {
             for (int m = 0; m < 4; ++m) pp.v[m][nt] = d[m];
         }
     }
+    // query mode: the point part of the 64 lanes' own features f
+    static __device__ __forceinline__ void query_point_part(const Tile *tiles, const RenderK &a, Wave &W, int lane,
+                                                            const float (&f)[kNF], PointPart &pp) {
+        wave_sync_lds();
+        store_feat(W, lane, f);
+        wave_sync_lds();
+        point_part(tiles, a, W, lane, pp);
+    }
     // decoder outputs of the lane's own query (N-tile l / 16)
     static __device__ __forceinline__ void decoder(const Tile *tiles, const RenderK &a, const Wave &W, int lane,
                                                    float (&o)[8]) {
@@ -311,7 +323,8 @@ struct Bf16Path {
                 pp.v[m][nt] = f32x4{v4.x, v4.y, v4.z, v4.w};
             }
     }
-    template <bool DEPTH>
+    // tracer logits of the lane's own query (N-tile nt uses pp.v[.][nt])
+    template <bool DEPTH, bool SHARED>
     static __device__ __forceinline__ float2 tracer(const Tracer &T, const Tile *tiles, const Wave &W, int buf,
                                                     int lane, const PointPart &pp) {
         const int g = lane >> 4;
@@ -346,8 +359,10 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 __device__ __forceinline__ f32x16 mfma32(float a, float b, const f32x16 &c) {
     return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
-// max(x, 0) in one instruction (median of x, 0 and +inf)
-__device__ __forceinline__ float relu1(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, __builtin_huge_valf()); }
+// max(x, 0) in one instruction: as a signed integer every negative float
+// (sign bit set) is below zero, so an integer max with 0 is the ReLU (and
+// needs no NaN canonicalisation, which a float max does)
+__device__ __forceinline__ float relu1(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
 // row of accumulator register r in lane half h, within a 32-row M-tile
 __device__ __forceinline__ int row32(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
 // physical hidden unit fed by K-step s (0..31) in lane half h: M-tile s / 16,
@@ -356,6 +371,11 @@ __device__ __forceinline__ int unit32(int s, int h) { return 32 * (s >> 4) + row
 
 struct F32Path {
     typedef float Table;
+    // 512 threads per block, two waves per SIMD: with at most 256 registers
+    // per wave, one wave's vector-ALU and memory work overlaps the other's
+    // matrix-core work
+    static constexpr int kThreads = 512;
+    static constexpr bool kHalfBounce = true;  // bounce in two halves of 32 points
     // operand tiles (64 floats each: lane l holds A[l % 32][l / 32])
     enum : int {
         T_W0W = 0,    // tracer direction part: 2 M-tiles x 2 K-steps (m*2 + s), components 2s + h
@@ -365,8 +385,18 @@ struct F32Path {
         D_W1 = 132,   // decoder hidden layer: 2 x 32 K-steps
         N_TILES = 196
     };
-    // head weights for the vector ALU after the tiles: [half][output][16 m + r]
-    static constexpr int HT_OFF = N_TILES * 64;      // tracer: 2 halves x 2 outputs x 32
+    // Bias tiles: a layer starts its accumulators with one matrix-core step
+    // of A[i][0] = b[32 m + i], A[i][1] = 0 against B = (1, 0), which is the
+    // bias exactly and keeps no bias in registers.
+    enum : int {
+        B_TB0 = N_TILES,      // tracer first-layer bias, 2 M-tiles
+        B_TB1 = N_TILES + 2,  // tracer hidden bias
+        B_DB0 = N_TILES + 4,  // decoder first-layer bias
+        B_DB1 = N_TILES + 6,  // decoder hidden bias
+        N_ALL = N_TILES + 8
+    };
+    // after the tiles: head weights for the vector ALU, [half][output][16 m + r]
+    static constexpr int HT_OFF = N_ALL * 64;        // tracer: 2 halves x 2 outputs x 32
     static constexpr int HD_OFF = HT_OFF + 128;      // decoder: 2 halves x 8 outputs x 32
     static constexpr int N_FLOATS = HD_OFF + 512;
     typedef float Tile;
@@ -374,10 +404,12 @@ struct F32Path {
     static constexpr int kXS = 36;  // row stride of the feature rows (16-byte aligned)
 
     struct Wave {
-        float x[64][kXS];   // per-query input features
-        float4 om[2][64];   // per-query direction (x, y, z, 0), two buffers
+        float x[32][kXS];   // input features of 32 points (one N-tile)
+        float4 om[2][64];   // per-lane direction (x, y, z, 0), two buffers
         float ax[4][kH];    // per-pixel tracer point part (shade mode)
         float mat[4][8];    // per-pixel decoder outputs (shade mode)
+        float4 bpx[64];     // every lane's bounce point x' and point id (bits)
+        float4 bpw[64];     // its direction w and sample index (bits)
         uint16_t qi[128];   // queued shadow rays (hard visibility): direction index
         float qd[128];      // and normalised depth
     };
@@ -396,6 +428,11 @@ struct F32Path {
             return wf(a.iW2, o * kH + 32 * (mr >> 4) + row32(mr & 15, h));
         }
         const int t = q >> 6, l = q & 63, i = l & 31, h = l >> 5;
+        if (t >= N_TILES) {
+            const int m = (t - N_TILES) & 1, which = (t - N_TILES) >> 1;
+            const float *b = which == 0 ? a.ib0 : (which == 1 ? a.ib1 : (which == 2 ? a.bb0 : a.bb1));
+            return h == 0 ? b[32 * m + i] : 0.0f;
+        }
         if (t < T_W0F) {
             const int m = (t - T_W0W) >> 1, c = 2 * ((t - T_W0W) & 1) + h;
             return c < 3 ? wf(a.iW0, (32 * m + i) * kNI + kNF + c) : 0.0f;
@@ -421,47 +458,51 @@ struct F32Path {
         for (int q = threadIdx.x; q < N_FLOATS; q += blockDim.x) tiles[q] = tile_value(a, q);
     }
 
-    // accumulator rows of M-tile m in lane half h, from a bias vector
-    static __device__ __forceinline__ f32x16 bias32(const float *b, int m, int h) {
+    static __device__ __forceinline__ f32x16 from4(const float4 (&v)[4]) {
         f32x16 r;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const float4 v = *reinterpret_cast<const float4 *>(b + 32 * m + 8 * q + 4 * h);
-            r[4 * q] = v.x;
-            r[4 * q + 1] = v.y;
-            r[4 * q + 2] = v.z;
-            r[4 * q + 3] = v.w;
+            r[4 * q] = v[q].x;
+            r[4 * q + 1] = v[q].y;
+            r[4 * q + 2] = v[q].z;
+            r[4 * q + 3] = v[q].w;
         }
         return r;
     }
+    // accumulators of M-tile m holding bias tile bt (first of the B_* tiles)
+    static __device__ __forceinline__ f32x16 bias_start(const Tile *tiles, int bt, int m, int lane) {
+        const f32x16 z = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        return mfma32(tiles[(bt + m) * 64 + lane], (lane >> 5) == 0 ? 1.0f : 0.0f, z);
+    }
 
     struct Tracer {
-        f32x16 b1[2];
         float hb0, hb1;
-        __device__ void load(const Tile *, const RenderK &a, int lane) {
-            const int h = lane >> 5;
-            b1[0] = bias32(a.irt.b1, 0, h);
-            b1[1] = bias32(a.irt.b1, 1, h);
+        __device__ void load(const Tile *, const RenderK &a, int) {
             hb0 = a.irt.b2[0];
             hb1 = a.irt.b2[1];
         }
     };
 
-    static __device__ __forceinline__ void store_feat(Wave &W, int row, const float (&f)[kNF]) {
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-            *reinterpret_cast<float4 *>(&W.x[row][4 * q]) = make_float4(f[4 * q], f[4 * q + 1], f[4 * q + 2], f[4 * q + 3]);
-    }
     static __device__ __forceinline__ void store_level(Wave &W, int row, int lvl, float f0, float f1) {
         *reinterpret_cast<float2 *>(&W.x[row][2 * lvl]) = make_float2(f0, f1);
+    }
+    // features 16 hl .. 16 hl + 15 of row `row`
+    static __device__ __forceinline__ void store_feat16(Wave &W, int row, int hl, const float (&f)[16]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            *reinterpret_cast<float4 *>(&W.x[row][16 * hl + 4 * q]) =
+                make_float4(f[4 * q], f[4 * q + 1], f[4 * q + 2], f[4 * q + 3]);
     }
     static __device__ __forceinline__ void store_dir(Wave &W, int buf, int lane, float3 w) {
         W.om[buf][lane] = make_float4(w.x, w.y, w.z, 0.0f);
     }
 
-    // features 16h .. 16h + 15 of query row 32 nt + lane % 32
-    static __device__ __forceinline__ void load_feat(const Wave &W, int nt, int lane, float (&xv)[16]) {
-        const float *xr = &W.x[32 * nt + (lane & 31)][16 * (lane >> 5)];
+    // first layer over the features of the 32 rows: out[m] = b + W x (bias tiles bt)
+    static __device__ __forceinline__ void feat_layer(const Tile *tiles, int base, int bt, const Wave &W, int lane,
+                                                      f32x16 (&out)[2]) {
+        const int h = lane >> 5;
+        const float *xr = &W.x[lane & 31][16 * h];
+        float xv[16];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const float4 v = *reinterpret_cast<const float4 *>(xr + 4 * q);
@@ -470,104 +511,93 @@ struct F32Path {
             xv[4 * q + 2] = v.z;
             xv[4 * q + 3] = v.w;
         }
-    }
-
-    // first layer over the features: out[m][nt] = b + W x for NT N-tiles
-    template <int NT>
-    static __device__ __forceinline__ void feat_layer(const Tile *tiles, int base, const float *bias, const Wave &W,
-                                                      int lane, f32x16 (&out)[2][2]) {
-        const int h = lane >> 5;
-        float xv[2][16];
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) load_feat(W, nt, lane, xv[nt]);
-#pragma unroll
-        for (int m = 0; m < 2; ++m) {
-            const f32x16 b = bias32(bias, m, h);
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) out[m][nt] = b;
-        }
+        out[0] = bias_start(tiles, bt, 0, lane);
+        out[1] = bias_start(tiles, bt, 1, lane);
 #pragma unroll
         for (int st = 0; st < 16; ++st)
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-                for (int m = 0; m < 2; ++m)
-                    out[m][nt] = mfma32(tiles[(base + 16 * m + st) * 64 + lane], xv[nt][st], out[m][nt]);
+            for (int m = 0; m < 2; ++m) out[m] = mfma32(tiles[(base + 16 * m + st) * 64 + lane], xv[st], out[m]);
     }
 
-    // hidden layer: out[m][nt] = bias + W relu(in)
-    template <int NT>
-    static __device__ __forceinline__ void hidden_layer(const Tile *tiles, int base, const f32x16 (&bias)[2],
-                                                        const f32x16 (&in)[2][2], int lane, f32x16 (&out)[2][2]) {
+    // hidden layer: out[m] = b + W relu(in) (bias tiles bt)
+    static __device__ __forceinline__ void hidden_layer(const Tile *tiles, int base, int bt, const f32x16 (&in)[2],
+                                                        int lane, f32x16 (&out)[2]) {
+        out[0] = bias_start(tiles, bt, 0, lane);
+        out[1] = bias_start(tiles, bt, 1, lane);
 #pragma unroll
-        for (int st = 0; st < 32; ++st)
+        for (int st = 0; st < 32; ++st) {
+            // the operand tiles of eight K-steps at a time are loaded ahead, not all 64
+            if ((st & 7) == 0) __builtin_amdgcn_sched_barrier(0);
+            const float b = relu1(in[st >> 4][st & 15]);
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const float b = relu1(in[st >> 4][nt][st & 15]);
-#pragma unroll
-                for (int m = 0; m < 2; ++m)
-                    out[m][nt] = mfma32(tiles[(base + 32 * m + st) * 64 + lane], b, st == 0 ? bias[m] : out[m][nt]);
-            }
+            for (int m = 0; m < 2; ++m) out[m] = mfma32(tiles[(base + 32 * m + st) * 64 + lane], b, out[m]);
+        }
     }
 
-    // head output o of NT N-tiles: this lane's partial over its 32 units,
-    // completed across the lane halves.  NT = 2: the lane's own query
-    // (N-tile l / 32); NT = 1: query l % 32 of N-tile 0.
-    template <int NT>
-    static __device__ __forceinline__ float head(const float *hw, const float (&re)[2][32], int lane) {
-        float p[2] = {0.f, 0.f};
+    // this lane's part of a head output over its 32 units: sum of w relu(e)
+    static __device__ __forceinline__ float head_part(const float *hw, const f32x16 (&e)[2]) {
+        float p = 0.f;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const float4 w = *reinterpret_cast<const float4 *>(hw + 4 * q);
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                p[nt] = fmaf(re[nt][4 * q], w.x, p[nt]);
-                p[nt] = fmaf(re[nt][4 * q + 1], w.y, p[nt]);
-                p[nt] = fmaf(re[nt][4 * q + 2], w.z, p[nt]);
-                p[nt] = fmaf(re[nt][4 * q + 3], w.w, p[nt]);
-            }
+            const int m = q >> 2, r = 4 * (q & 3);
+            p = fmaf(relu1(e[m][r]), w.x, p);
+            p = fmaf(relu1(e[m][r + 1]), w.y, p);
+            p = fmaf(relu1(e[m][r + 2]), w.z, p);
+            p = fmaf(relu1(e[m][r + 3]), w.w, p);
         }
+        return p;
+    }
+    // head output of column lane % 32 of one N-tile: the two lane halves' parts
+    static __device__ __forceinline__ float head_one(float p) { return p + __shfl_xor(p, 32); }
+    // head output of the lane's own column of two N-tiles (N-tile l / 32)
+    static __device__ __forceinline__ float head_two(float p0, float p1, int lane) {
         const bool hi = (lane >> 5) != 0;
-        const float own = (NT == 2 && hi) ? p[1] : p[0];
-        const float send = NT == 2 ? (hi ? p[0] : p[1]) : p[0];
-        return own + __shfl_xor(send, 32);
+        return (hi ? p1 : p0) + __shfl_xor(hi ? p0 : p1, 32);
     }
 
-    static __device__ __forceinline__ void relu_all(const f32x16 (&e)[2][2], int nt, float (&re)[32]) {
-#pragma unroll
-        for (int m = 0; m < 2; ++m)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) re[16 * m + r] = relu1(e[m][nt][r]);
-    }
-
-    // tracer point part W0f f + b0 of all 64 queries
+    // tracer point part W0f f + b0 of the 32 feature rows -> c[m][0]
     static __device__ __forceinline__ void point_part(const Tile *tiles, const RenderK &a, const Wave &W, int lane,
                                                       PointPart &pp) {
-        feat_layer<2>(tiles, T_W0F, a.irt.b0, W, lane, pp.c);
+        f32x16 c[2];
+        feat_layer(tiles, T_W0F, B_TB0, W, lane, c);
+        pp.c[0][0] = c[0];
+        pp.c[1][0] = c[1];
     }
 
-    // decoder outputs (up to 8) of the lane's own query (NT = 2) or of query
-    // lane % 32 (NT = 1)
-    template <int NT>
-    static __device__ __forceinline__ void decoder_nt(const Tile *tiles, const RenderK &a, const Wave &W, int lane,
-                                                      float (&o)[8]) {
-        const int h = lane >> 5;
-        f32x16 d[2][2], e[2][2];
-        feat_layer<NT>(tiles, D_W0, a.brdf.b0, W, lane, d);
-        const f32x16 b1[2] = {bias32(a.brdf.b1, 0, h), bias32(a.brdf.b1, 1, h)};
-        hidden_layer<NT>(tiles, D_W1, b1, d, lane, e);
-        float re[2][32];
+    // query mode: the point part of the 64 lanes' own features f, rows of
+    // lanes 32 nt .. 32 nt + 31 -> c[m][nt]
+    static __device__ __forceinline__ void query_point_part(const Tile *tiles, const RenderK &a, Wave &W, int lane,
+                                                            const float (&f)[kNF], PointPart &pp) {
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) relu_all(e, nt, re[nt]);
+        for (int nt = 0; nt < 2; ++nt) {
+            wave_sync_lds();
+            if ((lane >> 5) == nt) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    *reinterpret_cast<float4 *>(&W.x[lane & 31][4 * q]) =
+                        make_float4(f[4 * q], f[4 * q + 1], f[4 * q + 2], f[4 * q + 3]);
+            }
+            wave_sync_lds();
+            f32x16 c[2];
+            feat_layer(tiles, T_W0F, B_TB0, W, lane, c);
+            pp.c[0][nt] = c[0];
+            pp.c[1][nt] = c[1];
+        }
+    }
+
+    // decoder outputs (up to 8) of point lane % 32 of the 32 feature rows
+    static __device__ __forceinline__ void decoder(const Tile *tiles, const RenderK &a, const Wave &W, int lane,
+                                                   float (&o)[8]) {
+        const int h = lane >> 5;
+        f32x16 d[2], e[2];
+        feat_layer(tiles, D_W0, B_DB0, W, lane, d);
+        hidden_layer(tiles, D_W1, B_DB1, d, lane, e);
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             o[k] = 0.0f;
-            if (k < a.brdf_out) o[k] = head<NT>(&tiles[HD_OFF + (8 * h + k) * 32], re, lane) + a.brdf.b2[k];
+            if (k < a.brdf_out) o[k] = head_one(head_part(&tiles[HD_OFF + (8 * h + k) * 32], e)) + a.brdf.b2[k];
         }
-    }
-    static __device__ __forceinline__ void decoder(const Tile *tiles, const RenderK &a, const Wave &W, int lane,
-                                                   float (&o)[8]) {
-        decoder_nt<2>(tiles, a, W, lane, o);
     }
 
     // shade mode: decoder outputs and tracer point part of the pixel slots
@@ -576,14 +606,14 @@ struct F32Path {
                                                        int ppw) {
         const int h = lane >> 5, j = lane & 31;
         float o[8];
-        decoder_nt<1>(tiles, a, W, lane, o);
-        f32x16 c[2][2];
-        feat_layer<1>(tiles, T_W0F, a.irt.b0, W, lane, c);
+        decoder(tiles, a, W, lane, o);
+        f32x16 c[2];
+        feat_layer(tiles, T_W0F, B_TB0, W, lane, c);
         if (j < ppw) {
 #pragma unroll
             for (int m = 0; m < 2; ++m)
 #pragma unroll
-                for (int r = 0; r < 16; ++r) W.ax[j][32 * m + row32(r, h)] = c[m][0][r];
+                for (int r = 0; r < 16; ++r) W.ax[j][32 * m + row32(r, h)] = c[m][r];
             if (h == 0) {
 #pragma unroll
                 for (int k = 0; k < 5; ++k) W.mat[j][k] = o[k];
@@ -598,46 +628,43 @@ struct F32Path {
         for (int nt = 0; nt < 2; ++nt) {
             const float *ar = W.ax[(32 * nt + j) >> gs];
 #pragma unroll
-            for (int m = 0; m < 2; ++m)
+            for (int m = 0; m < 2; ++m) {
+                float4 v[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const float4 v = *reinterpret_cast<const float4 *>(ar + 32 * m + 8 * q + 4 * h);
-                    pp.c[m][nt][4 * q] = v.x;
-                    pp.c[m][nt][4 * q + 1] = v.y;
-                    pp.c[m][nt][4 * q + 2] = v.z;
-                    pp.c[m][nt][4 * q + 3] = v.w;
-                }
+                for (int q = 0; q < 4; ++q) v[q] = *reinterpret_cast<const float4 *>(ar + 32 * m + 8 * q + 4 * h);
+                pp.c[m][nt] = from4(v);
+            }
         }
     }
 
-    // tracer logits (visibility, and depth if DEPTH) of the lane's own query,
-    // direction operand buffer buf
-    template <bool DEPTH>
+    // tracer logits (visibility, and depth if DEPTH) of the lane's own query:
+    // N-tile nt holds the directions of lanes 32 nt .. 32 nt + 31 (operand
+    // buffer buf); SHARED: both N-tiles use the point part c[m][0] (the same
+    // 32 points with two directions each), else N-tile nt uses c[m][nt].
+    // The two N-tiles run one after the other (two accumulator chains each).
+    template <bool DEPTH, bool SHARED>
     static __device__ __forceinline__ float2 tracer(const Tracer &T, const Tile *tiles, const Wave &W, int buf,
                                                     int lane, const PointPart &pp) {
         const int h = lane >> 5, j = lane & 31;
-        float bd[2][2];
+        float p0[2], p1[2];
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt) {
+            // one N-tile at a time (register pressure)
+            __builtin_amdgcn_sched_barrier(0);
             const float4 w = W.om[buf][32 * nt + j];
-            bd[nt][0] = h ? w.y : w.x;
-            bd[nt][1] = h ? w.w : w.z;
-        }
-        f32x16 d[2][2];
+            const float bd0 = h ? w.y : w.x, bd1 = h ? w.w : w.z;
+            f32x16 d[2], e[2];
 #pragma unroll
-        for (int m = 0; m < 2; ++m)
-#pragma unroll
-            for (int nt = 0; nt < 2; ++nt) {
-                d[m][nt] = mfma32(tiles[(T_W0W + 2 * m) * 64 + lane], bd[nt][0], pp.c[m][nt]);
-                d[m][nt] = mfma32(tiles[(T_W0W + 2 * m + 1) * 64 + lane], bd[nt][1], d[m][nt]);
+            for (int m = 0; m < 2; ++m) {
+                d[m] = mfma32(tiles[(T_W0W + 2 * m) * 64 + lane], bd0, pp.c[m][SHARED ? 0 : nt]);
+                d[m] = mfma32(tiles[(T_W0W + 2 * m + 1) * 64 + lane], bd1, d[m]);
             }
-        f32x16 e[2][2];
-        hidden_layer<2>(tiles, T_W1, T.b1, d, lane, e);
-        float re[2][32];
-        relu_all(e, 0, re[0]);
-        relu_all(e, 1, re[1]);
-        const float o0 = head<2>(&tiles[HT_OFF + (2 * h) * 32], re, lane) + T.hb0;
-        const float o1 = DEPTH ? head<2>(&tiles[HT_OFF + (2 * h + 1) * 32], re, lane) + T.hb1 : 0.0f;
+            hidden_layer(tiles, T_W1, B_TB1, d, lane, e);
+            p0[nt] = head_part(&tiles[HT_OFF + (2 * h) * 32], e);
+            p1[nt] = DEPTH ? head_part(&tiles[HT_OFF + (2 * h + 1) * 32], e) : 0.0f;
+        }
+        const float o0 = head_two(p0[0], p0[1], lane) + T.hb0;
+        const float o1 = DEPTH ? head_two(p1[0], p1[1], lane) + T.hb1 : 0.0f;
         return make_float2(o0, o1);
     }
 };
@@ -683,7 +710,7 @@ __device__ __forceinline__ float3 secondary_lo(const RenderK &a, const typename 
         const float3 wn = sample_dir(pick4(words2, jn), jn, a.s.nb2_shift, a.s.inv_na2, a.s.inv_nb2, frb);
         const float3 En = env_lookup(a.env, wn.x, wn.y, wn.z);
         const float3 cn = sb.eval<NHEAD>(wn);
-        const float vo = PP::template tracer<false>(T, tiles, W, (int)(j & 1u), lane, bpt).x;
+        const float vo = PP::template tracer<false, false>(T, tiles, W, (int)(j & 1u), lane, bpt).x;
         PP::store_dir(W, (int)((j + 1) & 1u), lane, wn);
         // hard visibility: only visible secondary rays contribute
         const float vj = hard ? (vo > 0.0f ? 1.0f : 0.0f) : sigmoidf_(vo);
@@ -733,18 +760,173 @@ __device__ __forceinline__ float3 bounce_lo(const RenderK &a, const typename PP:
                  : secondary_lo<PP, false>(a, tiles, W, T, bpt, lane, frb, sb, pid, q, hard);
 }
 
+
+// Levels 8 hl .. 8 hl + 7 of H(x) (features 16 hl .. 16 hl + 15): the two
+// lane halves of a wave encode the same 32 points, half of the levels each.
+// The level parameters are selected per lane half; a gather addresses the
+// table by a 32-bit byte offset from its base (below 2^31: 16 levels x 2^24
+// entries x 8 bytes).  Gathers are issued two levels at a time, and a slot
+// past the grid's L levels reads entry 0 of level 0 and yields zeros.
+template <typename TT>
+__device__ __forceinline__ void encode_half(const GridK &g, float x, float y, float z, int hl, float (&f)[16]) {
+    float u[3];
+    bool in[3];
+    pos_to_u(g, x, y, z, u, in);
+    const bool hi = hl != 0;
+    const uint32_t esh = sizeof(TT) == 4 ? 3u : 2u;  // log2 bytes per entry (two features)
+#pragma unroll
+    for (int l0 = 0; l0 < 8; l0 += 2) {
+        __builtin_amdgcn_sched_barrier(0);
+        float w[2][3];
+        float2 e[2][8];
+        bool have[2];
+#pragma unroll
+        for (int li = 0; li < 2; ++li) {
+            const int lu = l0 + li;
+            const int l = hi ? lu + 8 : lu;
+            have[li] = l < (int)g.L;
+            const float resf = hi ? g.resf[lu + 8] : g.resf[lu];
+            const float nm1f = hi ? g.nm1f[lu + 8] : g.nm1f[lu];
+            const uint32_t st = hi ? g.stride[lu + 8] : g.stride[lu];
+            const bool dense = ((g.dense_mask >> l) & 1u) != 0;
+            uint32_t c[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) cell_of(u[d], resf, nm1f, c[d], w[li][d]);
+            uint32_t idx[8];
+            corner_idx_p(dense, st, g.Tmask, c, idx);
+            const uint32_t lbase = (uint32_t)l << (g.log2T + esh);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) e[li][k] = TabLoad<TT>::ld_byte(g.table, have[li] ? lbase + (idx[k] << esh) : 0u);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int li = 0; li < 2; ++li) {
+            const float wx0 = 1.0f - w[li][0], wy0 = 1.0f - w[li][1], wz0 = 1.0f - w[li][2];
+            float f0 = 0.0f, f1 = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const float wt = ((k & 1) ? w[li][0] : wx0) * (((k >> 1) & 1) ? w[li][1] : wy0) *
+                                 (((k >> 2) & 1) ? w[li][2] : wz0);
+                f0 = fmaf(wt, e[li][k].x, f0);
+                f1 = fmaf(wt, e[li][k].y, f1);
+            }
+            f[2 * (l0 + li)] = have[li] ? f0 : 0.0f;
+            f[2 * (l0 + li) + 1] = have[li] ? f1 : 0.0f;
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// Sum over this lane's secondary directions j = 2 k + (l / 32) of
+// f_r(w_j) V(x', w_j) L_e(w_j) at point l % 32 of the 32 points whose point
+// part is bpt: a tracer call's two N-tiles are the 32 points with directions
+// 2 k and 2 k + 1 (lane halves), sharing one point part.  Software pipeline
+// as in secondary_lo; the Philox block (j / 4 = k / 2) is wave-uniform.  With
+// N' = 1 the upper half traces a copy of direction 0 with weight zero.
+template <class PP, bool NHEAD>
+__device__ __forceinline__ float3 secondary_pair(const RenderK &a, const typename PP::Tile *tiles,
+                                                 typename PP::Wave &W, const typename PP::Tracer &T,
+                                                 const typename PP::PointPart &bpt, int lane, const Frame &frb,
+                                                 const SecondaryBrdf &sb, uint32_t pid, uint32_t q, bool hard) {
+    const uint32_t n2 = a.s.n_dirs2;
+    const uint32_t hl = (uint32_t)(lane >> 5);
+    const uint32_t npair = (n2 + 1u) >> 1;
+    const float wgt = hl < n2 ? 1.0f : 0.0f;
+    uint4 words2 = philox4x32_10(pid, q, 0u, 1u, a.s.key0, a.s.key1);
+    const uint32_t j0 = hl < n2 ? hl : 0u;
+    const float3 w0 = sample_dir(pick4(words2, j0), j0, a.s.nb2_shift, a.s.inv_na2, a.s.inv_nb2, frb);
+    float3 Ej = env_lookup(a.env, w0.x, w0.y, w0.z);
+    float3 cj = sb.eval<NHEAD>(w0);
+    wave_sync_lds();
+    PP::store_dir(W, 0, lane, w0);
+    wave_sync_lds();
+    float Lx = 0.f, Ly = 0.f, Lz = 0.f;
+    for (uint32_t k = 0; k < npair; ++k) {
+        const uint32_t kn = k + 1 < npair ? k + 1 : k;
+        if (kn != k && (kn & 1u) == 0) words2 = philox4x32_10(pid, q, kn >> 1, 1u, a.s.key0, a.s.key1);
+        const uint32_t jr = 2u * kn + hl;
+        const uint32_t jn = jr < n2 ? jr : 0u;
+        const float3 wn = sample_dir(pick4(words2, jn), jn, a.s.nb2_shift, a.s.inv_na2, a.s.inv_nb2, frb);
+        const float3 En = env_lookup(a.env, wn.x, wn.y, wn.z);
+        const float3 cn = sb.eval<NHEAD>(wn);
+        const float vo = PP::template tracer<false, true>(T, tiles, W, (int)(k & 1u), lane, bpt).x;
+        PP::store_dir(W, (int)((k + 1) & 1u), lane, wn);
+        // hard visibility: only visible secondary rays contribute
+        const float vj = (hard ? (vo > 0.0f ? 1.0f : 0.0f) : sigmoidf_(vo)) * wgt;
+        Lx = fmaf(cj.x * vj, Ej.x, Lx);
+        Ly = fmaf(cj.y * vj, Ej.y, Ly);
+        Lz = fmaf(cj.z * vj, Ej.z, Lz);
+        Ej = En;
+        cj = cn;
+        wave_sync_lds();
+    }
+    return make_float3(Lx, Ly, Lz);
+}
+
+// L'_o at the bounce points of the wave's 64 queries, in two halves of 32
+// points: every lane's bounce point goes to LDS, then for each half the two
+// lane halves encode the 32 points (levels 0..7 / 8..15), the decoder and
+// tracer point part run on one 32-column N-tile, and the lane halves trace
+// alternate secondary directions; the two halves' sums meet in the lane
+// that owns the point.
+template <class PP, class TT>
+__device__ __forceinline__ float3 bounce_lo_half(const RenderK &a, const typename PP::Tile *tiles,
+                                                 typename PP::Wave &W, const typename PP::Tracer &T, int lane,
+                                                 float3 x, float3 w, float dd, uint32_t pid, uint32_t q, bool hard,
+                                                 bool diffuse) {
+    const float t = fmaf(a.t_span, dd, a.t_near);
+    const float3 xb = make_float3(fmaf(t, w.x, x.x), fmaf(t, w.y, x.y), fmaf(t, w.z, x.z));
+    wave_sync_lds();
+    W.bpx[lane] = make_float4(xb.x, xb.y, xb.z, __uint_as_float(pid));
+    W.bpw[lane] = make_float4(w.x, w.y, w.z, __uint_as_float(q));
+    wave_sync_lds();
+    const int j = lane & 31, hl = lane >> 5;
+    const bool nhead = a.brdf_out == 8;
+    const float inv = 1.0f / (float)a.s.n_dirs2;
+    float3 Lo = make_float3(0.f, 0.f, 0.f);
+#pragma unroll 1
+    for (int half = 0; half < 2; ++half) {
+        const float4 bx = W.bpx[32 * half + j], bw = W.bpw[32 * half + j];
+        float fb[16];
+        encode_half<TT>(a.g, bx.x, bx.y, bx.z, hl, fb);
+        PP::store_feat16(W, j, hl, fb);
+        wave_sync_lds();
+        typename PP::PointPart bpt;
+        PP::point_part(tiles, a, W, lane, bpt);
+        float od[8];
+        PP::decoder(tiles, a, W, lane, od);
+        const float3 ab = make_float3(sigmoidf_(od[0]), sigmoidf_(od[1]), sigmoidf_(od[2]));
+        const float rb = 0.09f + 0.91f * sigmoidf_(od[3]);
+        const float mb = sigmoidf_(od[4]);
+        // secondary view -w; normal from the decoder's normal head if it has
+        // one, else the facing normal -w
+        const float3 vb = make_float3(-bw.x, -bw.y, -bw.z);
+        const float3 nb = nhead ? head_normal(od[5], od[6], od[7], vb) : vb;
+        const Frame frb = make_frame(nb);
+        FacingBrdf fb_;
+        fb_.set(ab, rb, mb, a.f0, diffuse);
+        const SecondaryBrdf sb{nb, vb, ab, rb, mb, a.f0, diffuse, fb_};
+        const uint32_t ppid = __float_as_uint(bx.w), pq = __float_as_uint(bw.w);
+        const float3 L = nhead ? secondary_pair<PP, true>(a, tiles, W, T, bpt, lane, frb, sb, ppid, pq, hard)
+                               : secondary_pair<PP, false>(a, tiles, W, T, bpt, lane, frb, sb, ppid, pq, hard);
+        const float sx = L.x + __shfl_xor(L.x, 32), sy = L.y + __shfl_xor(L.y, 32), sz = L.z + __shfl_xor(L.z, 32);
+        if (hl == half) Lo = make_float3(sx * inv, sy * inv, sz * inv);
+        wave_sync_lds();  // the next half rewrites the feature rows and direction buffers
+    }
+    return Lo;
+}
+
 // ============================================================================
 // The kernel.  QUERY: one query per lane with its own point and direction;
 // otherwise shade mode with G = min(N, 64) lanes per pixel (N >= 16, so at
 // most four pixels per wave).
 // ============================================================================
-constexpr int kMixThreads = 256;
-
 template <class PP, bool INDIRECT, bool QUERY, bool MIS>
-__global__ __launch_bounds__(kMixThreads) void k_render_mma(const RenderK a, int64_t n_items) {
+__global__ __launch_bounds__(PP::kThreads) void k_render_mma(const RenderK a, int64_t n_items) {
     typedef typename PP::Table TT;
+    constexpr int kWaves = PP::kThreads / 64;
     __shared__ typename PP::Tile tiles[PP::kTileFloats];
-    __shared__ typename PP::Wave wl[kMixThreads / 64];
+    __shared__ typename PP::Wave wl[kWaves];
     PP::build_tiles(a, tiles);
     __syncthreads();
     const int lane = threadIdx.x & 63;
@@ -757,8 +939,8 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mma(const RenderK a, int
     const uint32_t gs = a.s.g_shift;
     const uint32_t G = 1u << gs;
     const int ppw = 64 >> gs;
-    const int64_t waves_total = (int64_t)gridDim.x * (kMixThreads / 64);
-    const int64_t wave_id = (int64_t)blockIdx.x * (kMixThreads / 64) + (threadIdx.x >> 6);
+    const int64_t waves_total = (int64_t)gridDim.x * kWaves;
+    const int64_t wave_id = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
 
     for (int64_t item = wave_id; item < n_items; item += waves_total) {
         int64_t p_raw;
@@ -771,11 +953,9 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mma(const RenderK a, int
         // ---------------- primary point ----------------
         float3 n_ = make_float3(0.f, 0.f, 1.f), v_ = n_, alb = n_;
         float rr = 0.5f, mm = 0.f;
+        float fq[kNF];  // query mode: the lane's own features at x
         if (QUERY) {
-            float f[kNF];
-            encode<TT>(a.g, x.x, x.y, x.z, f);
-            PP::store_feat(W, lane, f);
-            wave_sync_lds();
+            encode<TT>(a.g, x.x, x.y, x.z, fq);
         } else {
             // lane l encodes level l % 16 of pixel slot l / 16
             const int slot = lane >> 4, lvl = lane & 15;
@@ -847,11 +1027,11 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mma(const RenderK a, int
                 PP::store_dir(W, 0, lane, w_own);
                 wave_sync_lds();
                 // tracer point part at x: query mode (one chunk per item) from
-                // the feature rows stored above, shade mode from the pixel slots
+                // the lanes' features, shade mode from the pixel slots
                 typename PP::PointPart c;
-                if (QUERY) PP::point_part(tiles, a, W, lane, c);
+                if (QUERY) PP::query_point_part(tiles, a, W, lane, fq, c);
                 else PP::pixel_point_part(W, lane, gs, c);
-                const float2 oo = PP::template tracer<true>(T, tiles, W, 0, lane, c);
+                const float2 oo = PP::template tracer<true, false>(T, tiles, W, 0, lane, c);
                 const float o0 = oo.x, o1 = oo.y;
                 V_own = hard ? (o0 > 0.0f ? 1.0f : 0.0f) : sigmoidf_(o0);
                 d_own = fminf(softplusf_(o1), 1.0f);
@@ -908,8 +1088,13 @@ __global__ __launch_bounds__(kMixThreads) void k_render_mma(const RenderK a, int
             if (!INDIRECT) {
                 Lin = make_float3(Ve * Le_own.x, Ve * Le_own.y, Ve * Le_own.z);
             } else {
-                const float3 Lo = bounce_lo<PP, TT>(a, tiles, W, T, lane, x, we, de, (uint32_t)p,
-                                                    QUERY ? 0u : ie, hard, diffuse);
+                float3 Lo;
+                if constexpr (PP::kHalfBounce)
+                    Lo = bounce_lo_half<PP, TT>(a, tiles, W, T, lane, x, we, de, (uint32_t)p, QUERY ? 0u : ie, hard,
+                                                diffuse);
+                else
+                    Lo = bounce_lo<PP, TT>(a, tiles, W, T, lane, x, we, de, (uint32_t)p, QUERY ? 0u : ie, hard,
+                                           diffuse);
                 const float om = 1.0f - Ve;
                 Lin = make_float3(fmaf(Ve, Le_own.x, om * Lo.x), fmaf(Ve, Le_own.y, om * Lo.y),
                                   fmaf(Ve, Le_own.z, om * Lo.z));
@@ -989,10 +1174,11 @@ static hipError_t launch_mma(const RenderK &a, bool indirect, bool query, hipStr
     }
     const int64_t ppw = query ? 64 : (64 >> a.s.g_shift);
     const int64_t items = (a.n + ppw - 1) / ppw;
-    const int64_t want = (items + 3) / 4;
+    constexpr int wpb = PP::kThreads / 64;
+    const int64_t want = (items + wpb - 1) / wpb;
     const int64_t cap = (int64_t)g_num_cus * 2;
     const unsigned blocks = (unsigned)(want < cap ? want : cap);
-    const dim3 grid(blocks), block(kMixThreads);
+    const dim3 grid(blocks), block(PP::kThreads);
     const bool mis = (a.s.flags & 4u) != 0;
     if (query) {
         if (indirect) hipLaunchKernelGGL((k_render_mma<PP, true, true, false>), grid, block, 0, s, a, items);
