@@ -272,25 +272,26 @@ __device__ __forceinline__ void corner_idx(const GridK &g, int l, const uint32_t
     corner_idx_p(((g.dense_mask >> l) & 1u) != 0, g.stride[l], g.Tmask, c, idx);
 }
 
-// f = H(x), features level-major.  Levels are processed in groups of four:
-// the 32 gathers of a group are all issued before a scheduling barrier and
-// interpolated after it, so that a group costs one memory round trip (left
-// to itself, the scheduler consumes each level's gathers before issuing the
-// next level's, which is 16 round trips).  The level loop has no branch: a
-// slot past the grid's L levels gathers entry 0 of level 0 (always in the
-// table) and its features are set to zero by a select.
+// f = H(x), features level-major.  Levels are processed in groups (two
+// levels for FP32 tables, one for FP16): the gathers of a group are all
+// issued before a scheduling barrier and interpolated after it.  Deeper
+// groups (more gathers in flight) measured slower for the FP16 tables, whose
+// random gathers are bound by cache-line throughput, not latency.  The level
+// loop has no branch: a slot past the grid's L levels gathers entry 0 of
+// level 0 (always in the table) and its features are set to zero by a select.
 template <typename TT>
 __device__ __forceinline__ void encode(const GridK &g, float x, float y, float z, float (&f)[kNF]) {
     float u[3];
     bool in[3];
     pos_to_u(g, x, y, z, u, in);
+    constexpr int GRP = sizeof(TT) == 4 ? 2 : 1;
 #pragma unroll
-    for (int l0 = 0; l0 < kL; l0 += 4) {
+    for (int l0 = 0; l0 < kL; l0 += GRP) {
         __builtin_amdgcn_sched_barrier(0);
-        float w[4][3];
-        float2 e[4][8];
+        float w[GRP][3];
+        float2 e[GRP][8];
 #pragma unroll
-        for (int li = 0; li < 4; ++li) {
+        for (int li = 0; li < GRP; ++li) {
             const int l = l0 + li;
             const bool have = l < (int)g.L;  // wave-uniform
             uint32_t c[3];
@@ -304,7 +305,7 @@ __device__ __forceinline__ void encode(const GridK &g, float x, float y, float z
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int li = 0; li < 4; ++li) {
+        for (int li = 0; li < GRP; ++li) {
             const int l = l0 + li;
             const float wx0 = 1.0f - w[li][0], wy0 = 1.0f - w[li][1], wz0 = 1.0f - w[li][2];
             float f0 = 0.0f, f1 = 0.0f;

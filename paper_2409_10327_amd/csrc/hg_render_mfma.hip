@@ -38,9 +38,6 @@ __device__ __forceinline__ f32x4 mfma_bf16(const uint4 &a, const uint4 &b, const
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b),
                                                     c, 0, 0, 0);
 }
-__device__ __forceinline__ f32x4 mfma_f32(float a, float b, const f32x4 &c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
 
 // Round-to-nearest-even FP32 -> BF16 of two values, packed (lo = a).
 __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
