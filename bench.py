@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--no-denoise", action="store_true")
     ap.add_argument("--no-mis", action="store_true")
     ap.add_argument("--no-paper", action="store_true")
+    ap.add_argument("--no-c5", action="store_true", help="skip the mixed N=512 frame + 2^20-query training step")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -146,7 +147,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"frame {args.img}x{args.img}, N={cfg.n_dirs}, N'={cfg.n_dirs2}, L=16, "
                                f"T=2^{cfg.log2_T}, res 16..2048, env 64x128 (FP32 path)",
-                   "shaded_px_per_s": P / (ms * 1e-3), "secondary_queries": S},
+                   "shaded_px_per_s": P / (ms * 1e-3), "secondary_queries": S,
+                   "tertiary_irt_per_s": S * cfg.n_dirs2 / (ms * 1e-3)},
     }
     achieved = FLOP_PER_QUERY * S / (ms * 1e-3) / 1e12
     out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -363,6 +365,34 @@ def main():
         mstm, _, _ = time_events(train_step_mixed, max(2, args.steps // 2), 1, torch)
         out["train"]["mixed"] = {"samples_per_s": B / (mstm * 1e-3), "ms_per_step": mstm,
                                  "dtype": "bf16-mfma fwd / f16-table bwd / f32 masters"}
+        del bp_t, bd_t, tgt
+
+        if not (args.no_mixed or args.no_c5):
+            # the combined mixed workload: the 800x800 frame at N = 512 (327.68M
+            # secondary queries) and a mixed training step over 2^20 queries
+            # (teacher targets, Morton order, recomputed bounce)
+            print("[bench] mixed frame N=512 and mixed step B=2^20", file=sys.stderr, flush=True)
+            N5 = 512
+            rgb5 = torch.empty((P, 3), device=dev)
+            r.refresh_shadows()
+
+            def frame5():
+                hg.render(r, env_t, pos_t, nrm_t, wo_t, n_dirs=N5, n_dirs2=cfg.n_dirs2, seed=H.SEED_DIRS,
+                          indirect=True, precision="mixed", out=(rgb5, None, None))
+            ms5, _, _ = time_events(frame5, max(2, args.steps // 2), 1, torch)
+            B5 = 1 << 20
+            teacher = hg.HashRenderer(H.make_teacher(cfg), dev)
+            bp5, bd5 = H.make_train_batch(B5)
+            bp_t, bd_t = t(bp5), t(bd5)
+            trgb, tvis, tdep = hg.render(teacher, env_t, bp_t, dirs=bd_t)
+            tgt = torch.cat([trgb, tvis[:, None], tdep[:, None]], 1).contiguous()
+            del teacher, trgb, tvis, tdep
+            ms5t, _, _ = time_events(train_step_mixed, max(2, args.steps // 2), 1, torch)
+            out["mixed_n512_train_2e20"] = {
+                "frame_ms": ms5, "frame_queries_per_s": P * N5 / (ms5 * 1e-3), "frame_px_per_s": P / (ms5 * 1e-3),
+                "train_ms": ms5t, "train_samples_per_s": B5 / (ms5t * 1e-3),
+                "dtype": "bf16-mfma/f16-table/f32-acc; f32 masters"}
+            del bp_t, bd_t, tgt
 
     if not args.no_cpu:
         from oracle import oracle as O
