@@ -2,9 +2,9 @@
 //
 // One query per lane.  Every activation of the recursive bounce is
 // recomputed here; nothing is stored by the forward.  Weight gradients of
-// the two MLPs are reduced over the 64 queries of a wave through LDS
-// (each lane owns one input column of a layer) and then added to global
-// memory with FP32 atomics; table gradients are scattered with FP32 atomics
+// the two MLPs are reduced over the 64 queries of a wave from LDS (on the
+// matrix cores for the 64-output layers) and then added to global memory
+// with FP32 atomics; table gradients are scattered with FP32 atomics
 // through the trilinear weights, summed first over the lanes of a wave that
 // share a cell (coarse levels).
 #include "hg_device.h"
@@ -67,6 +67,55 @@ __device__ __forceinline__ void reduce_layer(const float *act, const float *del,
     }
 }
 
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// dW[o][i] += sum_s del[s][o] * act[i][s] for the 64 outputs of a hidden
+// layer, as v_mfma_f32_32x32x2f32 products: M = outputs (two 32-row tiles),
+// N = inputs (32-column tiles), K = the wave's 64 samples, with
+// A[o][s] = del[s][o] and B[s][i] = act[i][s] read straight from the LDS
+// layouts above (lanes read contiguous floats of a del row, and act columns
+// at the odd stride kHS: no bank conflicts).  Lane l then holds
+// dW[32 mo + 8 (r / 4) + 4 (l / 32) + r % 4][32 ni + l % 32] in accumulator
+// register r; columns past NIN (stale rows of the act buffer) are dropped.
+// Bias gradients db[o] = sum_s del[s][o] are added by lane == o.
+template <int NIN>
+__device__ __forceinline__ void reduce_layer_mma(const float *act, const float *del, float *gW, float *gb, int lane) {
+    constexpr int NT = (NIN + 31) / 32;
+    const int h = lane >> 5, j = lane & 31;
+    // one 32-row output tile at a time (register pressure)
+#pragma unroll 1
+    for (int mo = 0; mo < 2; ++mo) {
+        f32x16 acc[NT];
+#pragma unroll
+        for (int ni = 0; ni < NT; ++ni)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[ni][r] = 0.0f;
+#pragma unroll 8
+        for (int st = 0; st < 32; ++st) {
+            const int smp = 2 * st + h;
+            const float av = del[smp * kDelStride + 32 * mo + j];
+#pragma unroll
+            for (int ni = 0; ni < NT; ++ni)
+                acc[ni] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, act[(32 * ni + j) * kHS + smp], acc[ni], 0, 0, 0);
+        }
+#pragma unroll
+        for (int ni = 0; ni < NT; ++ni) {
+            const int i = 32 * ni + j;
+            if (i < NIN) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int o = 32 * mo + 8 * (r >> 2) + 4 * h + (r & 3);
+                    atomic_addf(gW + (size_t)o * NIN + i, acc[ni][r]);
+                }
+            }
+        }
+    }
+    float accb = 0.0f;
+#pragma unroll 8
+    for (int smp = 0; smp < 64; ++smp) accb += del[smp * kDelStride + lane];
+    atomic_addf(gb + lane, accb);
+}
+
 __device__ __forceinline__ void store_row(float *del, int lane, const float (&v)[kH]) {
 #pragma unroll
     for (int k = 0; k < kH; k += 4)
@@ -100,7 +149,7 @@ __device__ __forceinline__ void mlp_bwd_stored(const MlpK &m, float *const *gp, 
     // ---- layer 1: pre2 = W1 h1 + b1
     store_row(del, lane, h);
     wave_sync();
-    reduce_layer<kH, kH>(h1buf, del, gp[2], gp[3], lane);
+    reduce_layer_mma<kH>(h1buf, del, gp[2], gp[3], lane);
     wave_sync();
     // d/d(pre-activation 1) = mask(h1) * W1^T g2, accumulated over rows k of W1
 #pragma unroll
@@ -120,7 +169,7 @@ __device__ __forceinline__ void mlp_bwd_stored(const MlpK &m, float *const *gp, 
 #pragma unroll
     for (int i = 0; i < NIN; ++i) h2buf[i * kHS + lane] = z[i];
     wave_sync();
-    reduce_layer<kH, NIN>(h2buf, del, gp[0], gp[1], lane);
+    reduce_layer_mma<NIN>(h2buf, del, gp[0], gp[1], lane);
     wave_sync();
 #pragma unroll
     for (int i = 0; i < kNF; ++i) dz[i] = 0.0f;
