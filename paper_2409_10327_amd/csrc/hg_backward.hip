@@ -116,6 +116,127 @@ __device__ __forceinline__ void reduce_layer_mma(const float *act, const float *
     atomic_addf(gb + lane, accb);
 }
 
+// T[s][i] = sum_k W[k][i] del[s][k] for i < NI (W row-major with row length
+// ldw, 64 rows k): the input gradient of a 64-output layer for the wave's 64
+// samples, as v_mfma_f32_32x32x2f32 products with M = inputs, N = samples,
+// K = outputs: A[i][k] = W[k][i] from global memory (cached), B[k][s] =
+// del[s][k] from LDS.  Lane l holds T[32 mi + 8 (r / 4) + 4 (l / 32) + r % 4]
+// [32 ns + l % 32] in register r and writes it to the transpose buffer T
+// (row stride kHS), from which each lane then reads its own sample's row.
+template <int NI>
+__device__ __forceinline__ void wt_times_del(const float *W, int ldw, const float *del, float *T, int lane) {
+    constexpr int MT = (NI + 31) / 32;
+    const int h = lane >> 5, j = lane & 31;
+#pragma unroll 1
+    for (int ns = 0; ns < 2; ++ns) {
+        f32x16 acc[MT];
+#pragma unroll
+        for (int mi = 0; mi < MT; ++mi)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[mi][r] = 0.0f;
+#pragma unroll 8
+        for (int st = 0; st < 32; ++st) {
+            const int k = 2 * st + h;
+            const float bv = del[(32 * ns + j) * kDelStride + k];
+#pragma unroll
+            for (int mi = 0; mi < MT; ++mi) {
+                const int i = 32 * mi + j;
+                const float av = i < NI ? W[k * ldw + i] : 0.0f;
+                acc[mi] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[mi], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int mi = 0; mi < MT; ++mi)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int i = 32 * mi + 8 * (r >> 2) + 4 * h + (r & 3);
+                if (i < NI) T[(32 * ns + j) * kHS + i] = acc[mi][r];
+            }
+    }
+}
+
+// Forward of one MLP evaluation for the wave's 64 samples on the matrix
+// cores (v_mfma_f32_32x32x2f32; M = units, N = samples, K = inputs), leaving
+// the ReLU activations in the [unit][sample] layouts the backward reads
+// (h1buf, h2buf; they may alias when h1 is not needed).  The inputs z go
+// through h2buf first (B[k][s] = z_s[k]); the first layer's accumulators,
+// after ReLU, are the second layer's B operand in place (K-step st takes
+// register st % 16 of M-tile st / 16, i.e. unit 32 (st / 16) + 8 ((st % 16) / 4)
+// + 4 (l / 32) + st % 4, so W1 is read with its columns in that order).
+// Weights come from global memory (cached).  Returns h2 of the lane's own
+// sample in h and the outputs in out (vector ALU, one row per output).
+template <int NIN, int NOUT>
+__device__ __forceinline__ void mlp_fwd_mma(const MlpK &m, const float (&z)[NIN], float *h1buf, float *h2buf, int lane,
+                                            float (&h)[kH], float (&out)[NOUT]) {
+    const float *W0 = static_cast<const float *>(m.W0);
+    const float *W1 = static_cast<const float *>(m.W1);
+    const int hh = lane >> 5, j = lane & 31;
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < NIN; ++i) h2buf[i * kHS + lane] = z[i];
+    wave_sync();
+    constexpr int KS0 = (NIN + 1) / 2;
+#pragma unroll 1
+    for (int ns = 0; ns < 2; ++ns) {
+        const int col = 32 * ns + j;
+        f32x16 a0[2], a1[2];
+#pragma unroll
+        for (int mo = 0; mo < 2; ++mo)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) a0[mo][r] = m.b0[32 * mo + 8 * (r >> 2) + 4 * hh + (r & 3)];
+#pragma unroll
+        for (int st = 0; st < KS0; ++st) {
+            // operands of eight K-steps at a time in flight (register pressure)
+            if ((st & 7) == 0) __builtin_amdgcn_sched_barrier(0);
+            const int k = 2 * st + hh;
+            const float bv = k < NIN ? h2buf[k * kHS + col] : 0.0f;
+#pragma unroll
+            for (int mo = 0; mo < 2; ++mo) {
+                const float av = k < NIN ? W0[(32 * mo + j) * NIN + k] : 0.0f;
+                a0[mo] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, a0[mo], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int mo = 0; mo < 2; ++mo)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                a0[mo][r] = fmaxf(a0[mo][r], 0.0f);
+                h1buf[(32 * mo + 8 * (r >> 2) + 4 * hh + (r & 3)) * kHS + col] = a0[mo][r];
+            }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int mo = 0; mo < 2; ++mo)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) a1[mo][r] = m.b1[32 * mo + 8 * (r >> 2) + 4 * hh + (r & 3)];
+#pragma unroll
+        for (int st = 0; st < 32; ++st) {
+            if ((st & 7) == 0) __builtin_amdgcn_sched_barrier(0);
+            const int u = 32 * (st >> 4) + 8 * ((st & 15) >> 2) + 4 * hh + (st & 3);
+            const float bv = a0[st >> 4][st & 15];
+#pragma unroll
+            for (int mo = 0; mo < 2; ++mo)
+                a1[mo] = __builtin_amdgcn_mfma_f32_32x32x2f32(W1[(32 * mo + j) * kH + u], bv, a1[mo], 0, 0, 0);
+        }
+#pragma unroll
+        for (int mo = 0; mo < 2; ++mo)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                h2buf[(32 * mo + 8 * (r >> 2) + 4 * hh + (r & 3)) * kHS + col] = fmaxf(a1[mo][r], 0.0f);
+    }
+    wave_sync();
+#pragma unroll
+    for (int k = 0; k < kH; ++k) h[k] = h2buf[k * kHS + lane];
+    const WPtr<float> W2(m.W2);
+    const BPtr b2(m.b2);
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) {
+        float acc = b2[o];
+#pragma unroll
+        for (int k = 0; k < kH; ++k) acc = fmaf(W2[o * kH + k], h[k], acc);
+        out[o] = acc;
+    }
+}
+
 __device__ __forceinline__ void store_row(float *del, int lane, const float (&v)[kH]) {
 #pragma unroll
     for (int k = 0; k < kH; k += 4)
@@ -151,18 +272,11 @@ __device__ __forceinline__ void mlp_bwd_stored(const MlpK &m, float *const *gp, 
     wave_sync();
     reduce_layer_mma<kH>(h1buf, del, gp[2], gp[3], lane);
     wave_sync();
-    // d/d(pre-activation 1) = mask(h1) * W1^T g2, accumulated over rows k of W1
+    // d/d(pre-activation 1) = mask(h1) * W1^T g2, through the h2 buffer (free now)
+    wt_times_del<kH>(static_cast<const float *>(m.W1), kH, del, h2buf, lane);
+    wave_sync();
 #pragma unroll
-    for (int j = 0; j < kH; ++j) h[j] = 0.0f;
-#pragma unroll 1
-    for (int k = 0; k < kH; ++k) {
-        const WPtr<float> W1(m.W1);
-        const float g2 = del[lane * kDelStride + k];
-#pragma unroll
-        for (int j = 0; j < kH; ++j) h[j] = fmaf(W1[k * kH + j], g2, h[j]);
-    }
-#pragma unroll
-    for (int j = 0; j < kH; ++j) h[j] = h1buf[j * kHS + lane] > 0.0f ? h[j] : 0.0f;
+    for (int j = 0; j < kH; ++j) h[j] = h1buf[j * kHS + lane] > 0.0f ? h2buf[lane * kHS + j] : 0.0f;
     // ---- layer 0: pre1 = W0 z + b0; z goes into the h2 buffer
     wave_sync();
     store_row(del, lane, h);
@@ -171,15 +285,11 @@ __device__ __forceinline__ void mlp_bwd_stored(const MlpK &m, float *const *gp, 
     wave_sync();
     reduce_layer_mma<NIN>(h2buf, del, gp[0], gp[1], lane);
     wave_sync();
+    // d/d(features) = W0f^T g1, through the h1 buffer (free now)
+    wt_times_del<kNF>(static_cast<const float *>(m.W0), NIN, del, h1buf, lane);
+    wave_sync();
 #pragma unroll
-    for (int i = 0; i < kNF; ++i) dz[i] = 0.0f;
-#pragma unroll 1
-    for (int j = 0; j < kH; ++j) {
-        const WPtr<float> W0(m.W0);
-        const float g1 = del[lane * kDelStride + j];
-#pragma unroll
-        for (int i = 0; i < kNF; ++i) dz[i] = fmaf(W0[j * NIN + i], g1, dz[i]);
-    }
+    for (int i = 0; i < kNF; ++i) dz[i] = h1buf[lane * kHS + i];
 }
 
 // Forward recompute plus backward of one MLP evaluation (see mlp_bwd_stored).
@@ -188,7 +298,7 @@ __device__ __forceinline__ void mlp_bwd_wave(const MlpK &m, float *const *gp, co
                                              const float (&gout)[NOUT], float *h1buf, float *h2buf, float *del, int lane,
                                              float (&dz)[kNF]) {
     float h[kH], o[NOUT];
-    mlp_fwd<NIN, NOUT, float>(m, z, h1buf, h2buf, lane, h, o);  // h = h2
+    mlp_fwd_mma<NIN, NOUT>(m, z, h1buf, h2buf, lane, h, o);  // h = h2
     mlp_bwd_stored<NIN, NOUT>(m, gp, z, gout, h, h1buf, h2buf, del, lane, dz);
 }
 
@@ -356,7 +466,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(const BwdK a) {
 #pragma unroll
     for (int i = 0; i < kNF; ++i) z[i] = f[i];
     z[kNF] = w.x; z[kNF + 1] = w.y; z[kNF + 2] = w.z;
-    mlp_fwd<kNI, 2, float>(r.irt, z, h1buf, h1buf, lane, h, o);
+    mlp_fwd_mma<kNI, 2>(r.irt, z, h1buf, h1buf, lane, h, o);
     const float V = sigmoidf_(o[0]);
     const float o1p = o[1];
     const float sp = softplusf_(o1p);
@@ -370,7 +480,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(const BwdK a) {
         float fb[kNF];
         encode<TT>(r.g, xb.x, xb.y, xb.z, fb);
         float ob[5];
-        mlp_fwd<kNF, 5, float>(r.brdf, fb, h1buf, h1buf, lane, h, ob);
+        mlp_fwd_mma<kNF, 5>(r.brdf, fb, h1buf, h1buf, lane, h, ob);
         const float3 ab = make_float3(sigmoidf_(ob[0]), sigmoidf_(ob[1]), sigmoidf_(ob[2]));
         const float s3 = sigmoidf_(ob[3]);
         const float rb = 0.09f + 0.91f * s3;
@@ -396,7 +506,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(const BwdK a) {
             if ((j & 3u) == 0) words = philox4x32_10((uint32_t)p, 0u, j >> 2, 1u, r.s.key0, r.s.key1);
             const float3 wj = sample_dir(pick4(words, j), j, r.s.nb2_shift, r.s.inv_na2, r.s.inv_nb2, fr);
             z[kNF] = wj.x; z[kNF + 1] = wj.y; z[kNF + 2] = wj.z;
-            mlp_fwd<kNI, 2, float>(r.irt, z, h1buf, h2buf, lane, h, o);
+            mlp_fwd_mma<kNI, 2>(r.irt, z, h1buf, h2buf, lane, h, o);
             const float vj = sigmoidf_(o[0]);
             const float3 Ej = env_lookup(r.env, wj.x, wj.y, wj.z);
             const BrdfGrad bg = pi_brdf_grad(nb, nb, wj, ab, rb, mb, r.f0, diffuse);

@@ -100,3 +100,22 @@ def kink_margin(model, pos, dirs, dep, indirect, seed=7, n_dirs2=8):
             m3, _ = margins(irt, np.concatenate([fb, wj], 1))
             mg = np.minimum(mg, m3)
     return mg
+
+
+def grad_condition(om, oe, samp, pos, dirs, g_rgb, g_vis, g_dep, indirect):
+    """Condition number of each MLP parameter gradient as a sum over samples:
+    ||sum_s |g_s| || / ||sum_s g_s|| with g_s the FP64 oracle's contribution
+    of sample s (one backward per sample, with its own point id).  An FP32
+    implementation whose per-sample terms carry a relative rounding error
+    delta is off by up to this factor times delta."""
+    from oracle import oracle as O
+    tot = O.backward(om, oe, samp, pos, dirs, g_rgb, g_vis, g_dep, indirect=indirect)
+    ab = {k: [np.zeros_like(a) for a in tot[k]] for k in ("irt", "brdf")}
+    for s in range(pos.shape[0]):
+        r = O.backward(om, oe, samp, pos[s:s + 1], dirs[s:s + 1], g_rgb[s:s + 1], g_vis[s:s + 1], g_dep[s:s + 1],
+                       indirect=indirect, pid=np.array([s]))
+        for k in ab:
+            for i in range(6):
+                ab[k][i] += np.abs(r[k][i])
+    return {(k, i): float(np.linalg.norm(ab[k][i]) / max(np.linalg.norm(tot[k][i]), 1e-300))
+            for k in ab for i in range(6)}

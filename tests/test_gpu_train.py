@@ -7,7 +7,7 @@ import torch
 import hg_inputs as H
 import paper_2409_10327_amd as hg
 from oracle import oracle as O
-from helpers import kink_margin, relerr
+from helpers import grad_condition, kink_margin, relerr
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -222,7 +222,11 @@ def morton_sorted(pos, dirs):
 def test_backward_parity_spatially_sorted_batch(setup, indirect):
     """A Morton-ordered batch drives the backward's per-cell summation of the
     table gradient at most levels (groups of lanes sharing a cell); gradients
-    still match the oracle at the FP32 bar."""
+    still match the oracle at the FP32 bar.  Each MLP parameter gradient is a
+    sum over samples; where its terms cancel, FP32 rounding of the terms
+    (a few ulps each, 2^-20) is amplified by the sum's condition number
+    kappa (measured with the oracle), so the bar is max(1e-5, kappa 2^-20)
+    (kappa reaches about 90 for the tracer's output bias here)."""
     print(f"case: backward on a Morton-ordered batch, indirect={indirect}", flush=True)
     t = setup["t"]
     n = 4096
@@ -239,8 +243,12 @@ def test_backward_parity_spatially_sorted_batch(setup, indirect):
     ref = O.backward(setup["om"], setup["oe"], O.sampling(1, 8, 7, 0), pos, dirs, g_rgb, g_vis, g_dep,
                      indirect=indirect)
     assert relerr(grads["table"].cpu().numpy(), ref["table"]) < 1e-5
+    kappa = grad_condition(setup["om"], setup["oe"], O.sampling(1, 8, 7, 0), pos, dirs, g_rgb, g_vis, g_dep, indirect)
     for k in ("brdf", "irt"):
         for i in range(6):
             if not indirect and k == "brdf":
                 continue
-            assert relerr(grads[k][i].cpu().numpy(), ref[k][i]) < 1e-5, (k, i)
+            bar = max(1e-5, kappa[(k, i)] * 2.0 ** -20)
+            e = relerr(grads[k][i].cpu().numpy(), ref[k][i])
+            print(f"{k}[{i}]: rel err {e:.3g}, kappa {kappa[(k, i)]:.3g}, bar {bar:.3g}")
+            assert e < bar, (k, i, e, bar)
