@@ -1,8 +1,8 @@
 // hg_device.h -- device building blocks of the gfx950 hash-grid renderer.
 //
 // Included by the .hip translation units only.  Every routine here works on
-// one query per lane (64-wide wavefronts); the matrix-core MLP lives in
-// hg_mfma.h.
+// one query per lane (64-wide wavefronts); the matrix-core MLPs live in
+// hg_render_mfma.hip and hg_backward.hip.
 #pragma once
 
 #include <hip/hip_runtime.h>

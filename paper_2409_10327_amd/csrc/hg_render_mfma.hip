@@ -309,14 +309,15 @@ struct Bf16Path {
             }
         }
     }
-    // shade mode: columns of N-tile nt belong to pixel slot (16 nt) >> gs
-    static __device__ __forceinline__ void pixel_point_part(const Wave &W, int lane, uint32_t gs, PointPart &pp) {
+    // shade mode: columns of N-tile nt belong to pixel slot sbase + ((16 nt) >> gs)
+    static __device__ __forceinline__ void pixel_point_part(const Wave &W, int lane, uint32_t gs, int sbase,
+                                                            PointPart &pp) {
         const int g = lane >> 4;
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
-                const float4 v4 = *reinterpret_cast<const float4 *>(&W.ax[(16 * nt) >> gs][16 * m + 4 * g]);
+                const float4 v4 = *reinterpret_cast<const float4 *>(&W.ax[sbase + ((16 * nt) >> gs)][16 * m + 4 * g]);
                 pp.v[m][nt] = f32x4{v4.x, v4.y, v4.z, v4.w};
             }
     }
@@ -618,12 +619,13 @@ struct F32Path {
         }
     }
 
-    // shade mode: the point part of each query's pixel slot ((32 nt + l % 32) >> gs)
-    static __device__ __forceinline__ void pixel_point_part(const Wave &W, int lane, uint32_t gs, PointPart &pp) {
+    // shade mode: the point part of each query's pixel slot sbase + ((32 nt + l % 32) >> gs)
+    static __device__ __forceinline__ void pixel_point_part(const Wave &W, int lane, uint32_t gs, int sbase,
+                                                            PointPart &pp) {
         const int h = lane >> 5, j = lane & 31;
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt) {
-            const float *ar = W.ax[(32 * nt + j) >> gs];
+            const float *ar = W.ax[sbase + ((32 * nt + j) >> gs)];
 #pragma unroll
             for (int m = 0; m < 2; ++m) {
                 float4 v[4];
@@ -939,7 +941,15 @@ __global__ __launch_bounds__(PP::kThreads) void k_render_mma(const RenderK a, in
     const int64_t waves_total = (int64_t)gridDim.x * kWaves;
     const int64_t wave_id = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
 
-    for (int64_t item = wave_id; item < n_items; item += waves_total) {
+    // Shade mode: a work unit is 4 / ppw consecutive items, whose four pixel
+    // slots share one pixel setup (encode at x, decoder, tracer point part).
+    const int ipw = QUERY ? 1 : 4 / ppw;
+    const int64_t n_units = (n_items + ipw - 1) / ipw;
+    for (int64_t unit = wave_id; unit < n_units; unit += waves_total) {
+    for (int ii = 0; ii < ipw; ++ii) {
+        const int64_t item = unit * ipw + ii;
+        if (item >= n_items) break;  // wave-uniform
+        const int sbase = ii * ppw;  // first pixel slot of this item
         int64_t p_raw;
         if (QUERY) p_raw = item * 64 + lane;
         else p_raw = item * ppw + (lane >> gs);
@@ -953,12 +963,12 @@ __global__ __launch_bounds__(PP::kThreads) void k_render_mma(const RenderK a, in
         float fq[kNF];  // query mode: the lane's own features at x
         if (QUERY) {
             encode<TT>(a.g, x.x, x.y, x.z, fq);
-        } else {
-            // lane l encodes level l % 16 of pixel slot l / 16
+        } else if (ii == 0) {
+            // lane l encodes level l % 16 of pixel slot l / 16 (pixel 4 unit + slot)
             const int slot = lane >> 4, lvl = lane & 15;
-            const int64_t ps_raw = item * ppw + slot;
+            const int64_t ps_raw = unit * 4 + slot;
             const int64_t ps = ps_raw < a.n ? ps_raw : a.n - 1;
-            if (slot < ppw && lvl < (int)a.g.L) {
+            if (lvl < (int)a.g.L) {
                 float u[3];
                 bool in[3];
                 pos_to_u(a.g, a.pos[3 * ps], a.pos[3 * ps + 1], a.pos[3 * ps + 2], u, in);
@@ -979,13 +989,15 @@ __global__ __launch_bounds__(PP::kThreads) void k_render_mma(const RenderK a, in
                     f1 = fmaf(wt, e.y, f1);
                 }
                 PP::store_level(W, slot, lvl, f0, f1);
-            } else if (slot < ppw) {
+            } else {
                 PP::store_level(W, slot, lvl, 0.0f, 0.0f);  // slot of a level the grid does not have
             }
             wave_sync_lds();
-            PP::pixel_setup(tiles, a, W, lane, ppw);
+            PP::pixel_setup(tiles, a, W, lane, 4);
             wave_sync_lds();
-            const int myslot = lane >> gs;
+        }
+        if (!QUERY) {
+            const int myslot = sbase + (lane >> gs);
             n_ = make_float3(a.nrm[3 * p], a.nrm[3 * p + 1], a.nrm[3 * p + 2]);
             v_ = make_float3(a.wo[3 * p], a.wo[3 * p + 1], a.wo[3 * p + 2]);
             alb = make_float3(sigmoidf_(W.mat[myslot][0]), sigmoidf_(W.mat[myslot][1]), sigmoidf_(W.mat[myslot][2]));
@@ -1027,7 +1039,7 @@ __global__ __launch_bounds__(PP::kThreads) void k_render_mma(const RenderK a, in
                 // the lanes' features, shade mode from the pixel slots
                 typename PP::PointPart c;
                 if (QUERY) PP::query_point_part(tiles, a, W, lane, fq, c);
-                else PP::pixel_point_part(W, lane, gs, c);
+                else PP::pixel_point_part(W, lane, gs, sbase, c);
                 const float2 oo = PP::template tracer<true, false>(T, tiles, W, 0, lane, c);
                 const float o0 = oo.x, o1 = oo.y;
                 V_own = hard ? (o0 > 0.0f ? 1.0f : 0.0f) : sigmoidf_(o0);
@@ -1154,6 +1166,7 @@ __global__ __launch_bounds__(PP::kThreads) void k_render_mma(const RenderK a, in
             }
         }
         wave_sync_lds();
+    }
     }
 }
 
