@@ -21,8 +21,14 @@
 // Inputs that come from other lanes (features, directions) go through LDS.
 // The tracer's first layer is split into a per-point part (W0f f + b0,
 // computed once per point and used as the accumulator input) and a
-// direction part (one matrix-core step; the mixed path splits the direction
-// into BF16 high and low halves).
+// direction part (two K-steps in FP32; one in the mixed path, which splits
+// the direction into BF16 high and low halves).
+//
+// Occupancy.  The FP32 path runs 512-thread blocks at two waves per SIMD
+// (at most 256 registers per wave) and bounces a wave's 64 queries in two
+// halves of 32 points (bounce_lo_half); the mixed path runs 256-thread
+// blocks at one wave per SIMD with the whole-wave bounce (bounce_lo), which
+// measured faster for it.
 #include <hip/hip_bf16.h>
 
 #include "hg_device.h"
