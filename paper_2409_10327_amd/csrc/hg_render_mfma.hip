@@ -389,9 +389,9 @@ struct F32Path {
         D_W1 = 132,   // decoder hidden layer: 2 x 32 K-steps
         N_TILES = 196
     };
-    // Bias tiles: a layer starts its accumulators with one matrix-core step
-    // of A[i][0] = b[32 m + i], A[i][1] = 0 against B = (1, 0), which is the
-    // bias exactly and keeps no bias in registers.
+    // Bias region (after the operand tiles, 256 floats used of 8 x 64): a
+    // layer's accumulators start at its bias, loaded from LDS in accumulator
+    // order, so no bias stays in registers and no matrix-core step adds it.
     enum : int {
         B_TB0 = N_TILES,      // tracer first-layer bias, 2 M-tiles
         B_TB1 = N_TILES + 2,  // tracer hidden bias
@@ -433,9 +433,12 @@ struct F32Path {
         }
         const int t = q >> 6, l = q & 63, i = l & 31, h = l >> 5;
         if (t >= N_TILES) {
-            const int m = (t - N_TILES) & 1, which = (t - N_TILES) >> 1;
+            // biases in accumulator order: [layer][M-tile][lane half][register]
+            const int qq = q - N_TILES * 64;
+            if (qq >= 256) return 0.0f;
+            const int which = qq >> 6, m = (qq >> 5) & 1, hh = (qq >> 4) & 1, r = qq & 15;
             const float *b = which == 0 ? a.ib0 : (which == 1 ? a.ib1 : (which == 2 ? a.bb0 : a.bb1));
-            return h == 0 ? b[32 * m + i] : 0.0f;
+            return b[32 * m + row32(r, hh)];
         }
         if (t < T_W0F) {
             const int m = (t - T_W0W) >> 1, c = 2 * ((t - T_W0W) & 1) + h;
@@ -473,10 +476,15 @@ struct F32Path {
         }
         return r;
     }
-    // accumulators of M-tile m holding bias tile bt (first of the B_* tiles)
+    // accumulators of M-tile m started at the bias of layer bt (one of the
+    // B_* ids): register r of lane half h holds the bias of row
+    // 8 (r / 4) + 4 h + r % 4, read as four broadcast 16-byte LDS loads
     static __device__ __forceinline__ f32x16 bias_start(const Tile *tiles, int bt, int m, int lane) {
-        const f32x16 z = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        return mfma32(tiles[(bt + m) * 64 + lane], (lane >> 5) == 0 ? 1.0f : 0.0f, z);
+        const float *bp = &tiles[N_TILES * 64 + ((((bt - N_TILES) >> 1) * 2 + m) * 2 + (lane >> 5)) * 16];
+        float4 v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = *reinterpret_cast<const float4 *>(bp + 4 * q);
+        return from4(v);
     }
 
     struct Tracer {
@@ -501,7 +509,7 @@ struct F32Path {
         W.om[buf][lane] = make_float4(w.x, w.y, w.z, 0.0f);
     }
 
-    // first layer over the features of the 32 rows: out[m] = b + W x (bias tiles bt)
+    // first layer over the features of the 32 rows: out[m] = b + W x (bias bt)
     static __device__ __forceinline__ void feat_layer(const Tile *tiles, int base, int bt, const Wave &W, int lane,
                                                       f32x16 (&out)[2]) {
         const int h = lane >> 5;
@@ -523,7 +531,7 @@ struct F32Path {
             for (int m = 0; m < 2; ++m) out[m] = mfma32(tiles[(base + 16 * m + st) * 64 + lane], xv[st], out[m]);
     }
 
-    // hidden layer: out[m] = b + W relu(in) (bias tiles bt)
+    // hidden layer: out[m] = b + W relu(in) (bias bt)
     static __device__ __forceinline__ void hidden_layer(const Tile *tiles, int base, int bt, const f32x16 (&in)[2],
                                                         int lane, f32x16 (&out)[2]) {
         out[0] = bias_start(tiles, bt, 0, lane);
