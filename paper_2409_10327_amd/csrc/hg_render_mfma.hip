@@ -804,7 +804,7 @@ __device__ __forceinline__ void encode_half(const GridK &g, float x, float y, fl
             const bool dense = ((g.dense_mask >> l) & 1u) != 0;
             uint32_t c[3];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) cell_of(u[d], resf, nm1f, c[d], w[li][d]);
+            for (int d = 0; d < 3; ++d) cell_of_sel(u[d], resf, nm1f, c[d], w[li][d]);
             uint32_t idx[8];
             corner_idx_p(dense, st, g.Tmask, c, idx);
             const uint32_t lbase = (uint32_t)l << (g.log2T + esh);
