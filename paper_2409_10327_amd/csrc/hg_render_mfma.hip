@@ -45,10 +45,14 @@ __device__ __forceinline__ f32x4 mfma_bf16(const uint4 &a, const uint4 &b, const
                                                     c, 0, 0, 0);
 }
 
-// Round-to-nearest-even FP32 -> BF16 of two values, packed (lo = a).
+// Round-to-nearest-even FP32 -> BF16 of two values, packed (lo = a).  Written
+// as one two-element conversion so that it is a single v_cvt_pk_bf16_f32
+// (two scalar conversions become two instructions plus a merge).
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
-    const __bf16 ha = (__bf16)a, hb = (__bf16)b;
-    return (uint32_t)__builtin_bit_cast(uint16_t, ha) | ((uint32_t)__builtin_bit_cast(uint16_t, hb) << 16);
+    const f32x2_t v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
 }
 
 // ReLU on two packed BF16 values: as signed 16-bit integers, every negative
