@@ -126,8 +126,15 @@ struct BPtr {
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64-bit
 // products with the round multipliers, key bumped by the Weyl constants.
 // --------------------------------------------------------------------------
+// OPAQUE_KEY: the (wave-uniform) key is made opaque at the call, so that its
+// schedule of 20 round keys is recomputed by scalar adds there instead of
+// being hoisted out of the loops, where it ran out of scalar registers and was
+// reloaded from vector-register lanes (FP32 800x800 frame 79.9 -> 78.8 ms; the
+// mixed path's secondary loop measured faster with the hoisted schedule).
+template <bool OPAQUE_KEY = true>
 __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                uint32_t k0, uint32_t k1) {
+    if (OPAQUE_KEY) asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;

@@ -719,7 +719,7 @@ __device__ __forceinline__ float3 secondary_lo(const RenderK &a, const typename 
                                                const typename PP::PointPart &bpt, int lane, const Frame &frb,
                                                const SecondaryBrdf &sb, uint32_t pid, uint32_t q, bool hard) {
     const uint32_t n2 = a.s.n_dirs2;
-    uint4 words2 = philox4x32_10(pid, q, 0u, 1u, a.s.key0, a.s.key1);
+    uint4 words2 = philox4x32_10<false>(pid, q, 0u, 1u, a.s.key0, a.s.key1);
     const float3 w0 = sample_dir(pick4(words2, 0u), 0u, a.s.nb2_shift, a.s.inv_na2, a.s.inv_nb2, frb);
     float3 Ej = env_lookup(a.env, w0.x, w0.y, w0.z);
     float3 cj = sb.eval<NHEAD>(w0);
@@ -729,7 +729,7 @@ __device__ __forceinline__ float3 secondary_lo(const RenderK &a, const typename 
     float Lx = 0.f, Ly = 0.f, Lz = 0.f;
     for (uint32_t j = 0; j < n2; ++j) {
         const uint32_t jn = j + 1 < n2 ? j + 1 : j;
-        if ((jn & 3u) == 0) words2 = philox4x32_10(pid, q, jn >> 2, 1u, a.s.key0, a.s.key1);
+        if ((jn & 3u) == 0) words2 = philox4x32_10<false>(pid, q, jn >> 2, 1u, a.s.key0, a.s.key1);
         const float3 wn = sample_dir(pick4(words2, jn), jn, a.s.nb2_shift, a.s.inv_na2, a.s.inv_nb2, frb);
         const float3 En = env_lookup(a.env, wn.x, wn.y, wn.z);
         const float3 cn = sb.eval<NHEAD>(wn);
@@ -1052,7 +1052,10 @@ __global__ __launch_bounds__(PP::kThreads) void k_render_mma(const RenderK a, in
                 } else if (MIS) {
                     w_own = mis_direction(a, fr, vl, rr, (uint32_t)p, i_own, wf_own);
                 } else {
-                    const uint4 words = philox4x32_10((uint32_t)p, 0u, i_own >> 2, 0u, a.s.key0, a.s.key1);
+                    // key schedule recomputed per call on the FP32 path (faster
+                    // there), hoisted on the mixed one
+                    const uint4 words = philox4x32_10<PP::kHalfBounce>((uint32_t)p, 0u, i_own >> 2, 0u,
+                                                                       a.s.key0, a.s.key1);
                     w_own = sample_dir(pick4(words, i_own), i_own, a.s.nb_shift, a.s.inv_na, a.s.inv_nb, fr);
                 }
                 Le_own = env_lookup(a.env, w_own.x, w_own.y, w_own.z);  // overlaps the tracer
@@ -1113,7 +1116,8 @@ __global__ __launch_bounds__(PP::kThreads) void k_render_mma(const RenderK a, in
                 if (MIS) {
                     we = mis_direction(a, fr, vl, rr, (uint32_t)p, ie, wfe);
                 } else {
-                    const uint4 words = philox4x32_10((uint32_t)p, 0u, ie >> 2, 0u, a.s.key0, a.s.key1);
+                    const uint4 words = philox4x32_10<PP::kHalfBounce>((uint32_t)p, 0u, ie >> 2, 0u,
+                                                                       a.s.key0, a.s.key1);
                     we = sample_dir(pick4(words, ie), ie, a.s.nb_shift, a.s.inv_na, a.s.inv_nb, fr);
                 }
             }
