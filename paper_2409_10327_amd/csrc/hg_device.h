@@ -128,10 +128,11 @@ struct BPtr {
 // --------------------------------------------------------------------------
 // OPAQUE_KEY: the (wave-uniform) key is made opaque at the call, so that its
 // schedule of 20 round keys is recomputed by scalar adds there instead of
-// being hoisted out of the loops, where it ran out of scalar registers and was
-// reloaded from vector-register lanes (FP32 800x800 frame 79.9 -> 78.8 ms; the
-// mixed path's secondary loop measured faster with the hoisted schedule).
-template <bool OPAQUE_KEY = true>
+// being hoisted out of the loops.  The two-wave FP32 render kernel, short of
+// scalar registers, otherwise reloads the hoisted schedule from vector-register
+// lanes (800x800 frame 79.9 -> 78.8 ms with it); every other kernel measured
+// faster with the hoisted schedule.
+template <bool OPAQUE_KEY = false>
 __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                uint32_t k0, uint32_t k1) {
     if (OPAQUE_KEY) asm volatile("" : "+s"(k0), "+s"(k1));

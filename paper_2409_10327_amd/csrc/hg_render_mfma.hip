@@ -719,7 +719,7 @@ __device__ __forceinline__ float3 secondary_lo(const RenderK &a, const typename 
                                                const typename PP::PointPart &bpt, int lane, const Frame &frb,
                                                const SecondaryBrdf &sb, uint32_t pid, uint32_t q, bool hard) {
     const uint32_t n2 = a.s.n_dirs2;
-    uint4 words2 = philox4x32_10<false>(pid, q, 0u, 1u, a.s.key0, a.s.key1);
+    uint4 words2 = philox4x32_10(pid, q, 0u, 1u, a.s.key0, a.s.key1);
     const float3 w0 = sample_dir(pick4(words2, 0u), 0u, a.s.nb2_shift, a.s.inv_na2, a.s.inv_nb2, frb);
     float3 Ej = env_lookup(a.env, w0.x, w0.y, w0.z);
     float3 cj = sb.eval<NHEAD>(w0);
@@ -729,7 +729,7 @@ __device__ __forceinline__ float3 secondary_lo(const RenderK &a, const typename 
     float Lx = 0.f, Ly = 0.f, Lz = 0.f;
     for (uint32_t j = 0; j < n2; ++j) {
         const uint32_t jn = j + 1 < n2 ? j + 1 : j;
-        if ((jn & 3u) == 0) words2 = philox4x32_10<false>(pid, q, jn >> 2, 1u, a.s.key0, a.s.key1);
+        if ((jn & 3u) == 0) words2 = philox4x32_10(pid, q, jn >> 2, 1u, a.s.key0, a.s.key1);
         const float3 wn = sample_dir(pick4(words2, jn), jn, a.s.nb2_shift, a.s.inv_na2, a.s.inv_nb2, frb);
         const float3 En = env_lookup(a.env, wn.x, wn.y, wn.z);
         const float3 cn = sb.eval<NHEAD>(wn);
@@ -855,7 +855,7 @@ __device__ __forceinline__ float3 secondary_pair(const RenderK &a, const typenam
     const uint32_t hl = (uint32_t)(lane >> 5);
     const uint32_t npair = (n2 + 1u) >> 1;
     const float wgt = hl < n2 ? 1.0f : 0.0f;
-    uint4 words2 = philox4x32_10(pid, q, 0u, 1u, a.s.key0, a.s.key1);
+    uint4 words2 = philox4x32_10<true>(pid, q, 0u, 1u, a.s.key0, a.s.key1);
     const uint32_t j0 = hl < n2 ? hl : 0u;
     const float3 w0 = sample_dir(pick4(words2, j0), j0, a.s.nb2_shift, a.s.inv_na2, a.s.inv_nb2, frb);
     float3 Ej = env_lookup(a.env, w0.x, w0.y, w0.z);
@@ -866,7 +866,7 @@ __device__ __forceinline__ float3 secondary_pair(const RenderK &a, const typenam
     float Lx = 0.f, Ly = 0.f, Lz = 0.f;
     for (uint32_t k = 0; k < npair; ++k) {
         const uint32_t kn = k + 1 < npair ? k + 1 : k;
-        if (kn != k && (kn & 1u) == 0) words2 = philox4x32_10(pid, q, kn >> 1, 1u, a.s.key0, a.s.key1);
+        if (kn != k && (kn & 1u) == 0) words2 = philox4x32_10<true>(pid, q, kn >> 1, 1u, a.s.key0, a.s.key1);
         const uint32_t jr = 2u * kn + hl;
         const uint32_t jn = jr < n2 ? jr : 0u;
         const float3 wn = sample_dir(pick4(words2, jn), jn, a.s.nb2_shift, a.s.inv_na2, a.s.inv_nb2, frb);
