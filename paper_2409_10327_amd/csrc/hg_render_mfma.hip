@@ -846,7 +846,7 @@ __device__ __forceinline__ void encode_half(const GridK &g, float x, float y, fl
 // 2 k and 2 k + 1 (lane halves), sharing one point part.  Software pipeline
 // as in secondary_lo; the Philox block (j / 4 = k / 2) is wave-uniform.  With
 // N' = 1 the upper half traces a copy of direction 0 with weight zero.
-template <class PP, bool NHEAD>
+template <class PP, bool NHEAD, bool OPQ>
 __device__ __forceinline__ float3 secondary_pair(const RenderK &a, const typename PP::Tile *tiles,
                                                  typename PP::Wave &W, const typename PP::Tracer &T,
                                                  const typename PP::PointPart &bpt, int lane, const Frame &frb,
@@ -855,7 +855,7 @@ __device__ __forceinline__ float3 secondary_pair(const RenderK &a, const typenam
     const uint32_t hl = (uint32_t)(lane >> 5);
     const uint32_t npair = (n2 + 1u) >> 1;
     const float wgt = hl < n2 ? 1.0f : 0.0f;
-    uint4 words2 = philox4x32_10<true>(pid, q, 0u, 1u, a.s.key0, a.s.key1);
+    uint4 words2 = philox4x32_10<OPQ>(pid, q, 0u, 1u, a.s.key0, a.s.key1);
     const uint32_t j0 = hl < n2 ? hl : 0u;
     const float3 w0 = sample_dir(pick4(words2, j0), j0, a.s.nb2_shift, a.s.inv_na2, a.s.inv_nb2, frb);
     float3 Ej = env_lookup(a.env, w0.x, w0.y, w0.z);
@@ -866,7 +866,7 @@ __device__ __forceinline__ float3 secondary_pair(const RenderK &a, const typenam
     float Lx = 0.f, Ly = 0.f, Lz = 0.f;
     for (uint32_t k = 0; k < npair; ++k) {
         const uint32_t kn = k + 1 < npair ? k + 1 : k;
-        if (kn != k && (kn & 1u) == 0) words2 = philox4x32_10<true>(pid, q, kn >> 1, 1u, a.s.key0, a.s.key1);
+        if (kn != k && (kn & 1u) == 0) words2 = philox4x32_10<OPQ>(pid, q, kn >> 1, 1u, a.s.key0, a.s.key1);
         const uint32_t jr = 2u * kn + hl;
         const uint32_t jn = jr < n2 ? jr : 0u;
         const float3 wn = sample_dir(pick4(words2, jn), jn, a.s.nb2_shift, a.s.inv_na2, a.s.inv_nb2, frb);
@@ -892,7 +892,9 @@ __device__ __forceinline__ float3 secondary_pair(const RenderK &a, const typenam
 // tracer point part run on one 32-column N-tile, and the lane halves trace
 // alternate secondary directions; the two halves' sums meet in the lane
 // that owns the point.
-template <class PP, class TT>
+// OPQ: Philox key schedule recomputed per call (shade mode; query mode
+// measured faster with it hoisted)
+template <class PP, class TT, bool OPQ>
 __device__ __forceinline__ float3 bounce_lo_half(const RenderK &a, const typename PP::Tile *tiles,
                                                  typename PP::Wave &W, const typename PP::Tracer &T, int lane,
                                                  float3 x, float3 w, float dd, uint32_t pid, uint32_t q, bool hard,
@@ -930,8 +932,8 @@ __device__ __forceinline__ float3 bounce_lo_half(const RenderK &a, const typenam
         fb_.set(ab, rb, mb, a.f0, diffuse);
         const SecondaryBrdf sb{nb, vb, ab, rb, mb, a.f0, diffuse, fb_};
         const uint32_t ppid = __float_as_uint(bx.w), pq = __float_as_uint(bw.w);
-        const float3 L = nhead ? secondary_pair<PP, true>(a, tiles, W, T, bpt, lane, frb, sb, ppid, pq, hard)
-                               : secondary_pair<PP, false>(a, tiles, W, T, bpt, lane, frb, sb, ppid, pq, hard);
+        const float3 L = nhead ? secondary_pair<PP, true, OPQ>(a, tiles, W, T, bpt, lane, frb, sb, ppid, pq, hard)
+                               : secondary_pair<PP, false, OPQ>(a, tiles, W, T, bpt, lane, frb, sb, ppid, pq, hard);
         const float sx = L.x + __shfl_xor(L.x, 32), sy = L.y + __shfl_xor(L.y, 32), sz = L.z + __shfl_xor(L.z, 32);
         if (hl == half) Lo = make_float3(sx * inv, sy * inv, sz * inv);
         wave_sync_lds();  // the next half rewrites the feature rows and direction buffers
@@ -1127,8 +1129,8 @@ __global__ __launch_bounds__(PP::kThreads) void k_render_mma(const RenderK a, in
             } else {
                 float3 Lo;
                 if constexpr (PP::kHalfBounce)
-                    Lo = bounce_lo_half<PP, TT>(a, tiles, W, T, lane, x, we, de, (uint32_t)p, QUERY ? 0u : ie, hard,
-                                                diffuse);
+                    Lo = bounce_lo_half<PP, TT, !QUERY>(a, tiles, W, T, lane, x, we, de, (uint32_t)p,
+                                                        QUERY ? 0u : ie, hard, diffuse);
                 else
                     Lo = bounce_lo<PP, TT>(a, tiles, W, T, lane, x, we, de, (uint32_t)p, QUERY ? 0u : ie, hard,
                                            diffuse);
