@@ -103,7 +103,7 @@ def time_events(fn, steps, warmup, torch):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (rendering shards by pixel with "
+        print("bench.py measures one GPU: the library has no multi-GPU path (rendering shards by pixel with "
               "no exchange between GPUs).", file=sys.stderr)
         sys.exit(2)
     import torch
