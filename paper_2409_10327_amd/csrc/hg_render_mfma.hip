@@ -28,7 +28,9 @@
 // (at most 256 registers per wave) and bounces a wave's 64 queries in two
 // halves of 32 points (bounce_lo_half); the mixed path runs 256-thread
 // blocks at one wave per SIMD with the whole-wave bounce (bounce_lo), which
-// measured faster for it.
+// measured faster for it.  In the FP32 path a wave raises its issue priority
+// for the tracer's matrix-core steps, so that the vector work of the SIMD's
+// other wave fills the matrix pipe's gaps rather than delaying its next step.
 #include <hip/hip_bf16.h>
 
 #include "hg_device.h"
