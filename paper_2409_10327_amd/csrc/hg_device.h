@@ -83,6 +83,14 @@ __device__ __forceinline__ float rcpf_(float x) { return __builtin_amdgcn_rcpf(x
 // rounded form adds a scaling, two residual fmas and selects, about fourteen
 // instructions); every argument here is zero or a normal number.
 __device__ __forceinline__ float sqrtf_(float x) { return __builtin_amdgcn_sqrtf(x); }
+// sin(2 pi x) and cos(2 pi x) for x in [0, 1) revolutions by the hardware
+// instructions (v_sin_f32 / v_cos_f32 take revolutions): measured on this GPU
+// over 2^20 bin centres of [0, 1), the largest error is 1.24e-7 (about two
+// ulp of 1; sincospif: 5.1e-8, at about thirty instructions).
+__device__ __forceinline__ void sincos2pi_(float x, float &s, float &c) {
+    s = __builtin_amdgcn_sinf(x);
+    c = __builtin_amdgcn_cosf(x);
+}
 __device__ __forceinline__ float sigmoidf_(float z) { return rcpf_(1.0f + __expf(-z)); }
 __device__ __forceinline__ float softplusf_(float z) {
     return fmaxf(z, 0.0f) + log1pf(__expf(-fabsf(z)));
@@ -185,7 +193,7 @@ __device__ __forceinline__ float3 sample_dir(uint32_t word, uint32_t k, uint32_t
     const float s2 = ((float)b + u2) * inv_nb;
     const float r = sqrtf_(s1);
     float sn, cs;
-    sincospif(2.0f * s2, &sn, &cs);
+    sincos2pi_(s2, sn, cs);
     const float lx = r * cs, ly = r * sn, lz = sqrtf_(1.0f - s1);
     return make_float3(lx * fr.t.x + ly * fr.b.x + lz * fr.n.x,
                        lx * fr.t.y + ly * fr.b.y + lz * fr.n.y,
@@ -666,7 +674,7 @@ __device__ __forceinline__ float3 ggx_sample(const Frame &fr, float3 vl, float r
     const float3 T2 = make_float3(vh.y * T1.z - vh.z * T1.y, vh.z * T1.x - vh.x * T1.z, vh.x * T1.y - vh.y * T1.x);
     const float rr = sqrtf_(s1);
     float sn, cs;
-    sincospif(2.0f * s2, &sn, &cs);
+    sincos2pi_(s2, sn, cs);
     const float t1 = rr * cs;
     float t2 = rr * sn;
     const float sv = 0.5f * (1.0f + vh.z);
