@@ -84,9 +84,9 @@ __device__ __forceinline__ float rcpf_(float x) { return __builtin_amdgcn_rcpf(x
 // instructions); every argument here is zero or a normal number.
 __device__ __forceinline__ float sqrtf_(float x) { return __builtin_amdgcn_sqrtf(x); }
 // sin(2 pi x) and cos(2 pi x) for x in [0, 1) revolutions by the hardware
-// instructions (v_sin_f32 / v_cos_f32 take revolutions): measured on this GPU
-// over 2^20 bin centres of [0, 1), the largest error is 1.24e-7 (about two
-// ulp of 1; sincospif: 5.1e-8, at about thirty instructions).
+// instructions (v_sin_f32 / v_cos_f32 take revolutions): measured on an
+// MI355X over 2^20 bin centres of [0, 1), the largest error is 1.24e-7 (about
+// two ulp of 1; sincospif: 5.1e-8, at about thirty instructions).
 __device__ __forceinline__ void sincos2pi_(float x, float &s, float &c) {
     s = __builtin_amdgcn_sinf(x);
     c = __builtin_amdgcn_cosf(x);
@@ -160,12 +160,12 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
     return make_uint4(c0, c1, c2, c3);
 }
 
-// Word k % 4 of a Philox block, without a branch when k is wave-uniform.
+// Word k % 4 of a Philox block: a two-level select on the bits of k (no
+// branch; k may differ between lanes).
 __device__ __forceinline__ uint32_t pick4(const uint4 &w, uint32_t k) {
-    const uint32_t s = k & 3u;
-    const uint32_t m0 = 0u - (uint32_t)(s == 0u), m1 = 0u - (uint32_t)(s == 1u);
-    const uint32_t m2 = 0u - (uint32_t)(s == 2u), m3 = 0u - (uint32_t)(s == 3u);
-    return (w.x & m0) | (w.y & m1) | (w.z & m2) | (w.w & m3);
+    const bool b0 = (k & 1u) != 0, b1 = (k & 2u) != 0;
+    const uint32_t lo = b0 ? w.y : w.x, hi = b0 ? w.w : w.z;
+    return b1 ? hi : lo;
 }
 
 // Orthonormal basis about a unit normal (Duff et al., JCGT 2017).
