@@ -297,12 +297,17 @@ __device__ __forceinline__ void pos_to_u(const GridK &g, float x, float y, float
 // branches (one straight-line scheduling region per group of levels).
 __device__ __forceinline__ void corner_idx_p(bool dense, uint32_t s, uint32_t Tmask, const uint32_t (&c)[3],
                                              uint32_t (&idx)[8]) {
-    const uint32_t b = c[0] + s * (c[1] + s * c[2]);
+    // dense form with 24-bit multiplies (full rate; the 32-bit multiply is
+    // quarter rate): a dense level has s^3 <= T <= 2^24, so s <= 256 and every
+    // operand is below 2^24 and every product below 2^32 (for a hashed level
+    // this form is not selected)
+    const uint32_t b = c[0] + __umul24(s, c[1] + __umul24(s, c[2]));
+    const uint32_t s2 = __umul24(s, s);
     const uint32_t hy0 = c[1] * 2654435761u, hy1 = hy0 + 2654435761u;
     const uint32_t hz0 = c[2] * 805459861u, hz1 = hz0 + 805459861u;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const uint32_t di = b + (k & 1) + ((k >> 1) & 1) * s + ((k >> 2) & 1) * s * s;
+        const uint32_t di = b + (k & 1) + ((k >> 1) & 1) * s + ((k >> 2) & 1) * s2;
         const uint32_t hi = ((c[0] + (k & 1)) ^ ((k >> 1) & 1 ? hy1 : hy0) ^ ((k >> 2) & 1 ? hz1 : hz0)) & Tmask;
         idx[k] = dense ? di : hi;
     }
