@@ -11,8 +11,8 @@ a rounding argument. FP32 arithmetic is reproduced exactly here: the product
 of two FP32 numbers is exact in FP64, so rounding it to FP32 gives fl(u N);
 u N - x for an integer-valued FP32 x is exact in FP64 (at most 49 significant
 bits), so rounding it to FP32 gives the fma fl(u N - x). Every u next to every
-cell boundary of several resolutions must give the exact cell and the once-
-rounded fractional position."""
+cell boundary of several resolutions must give the exact cell and the
+once-rounded fractional position."""
 import numpy as np
 import pytest
 
