@@ -436,6 +436,61 @@ void or_env_lookup(const or_env *e, const double *dirs, int64_t n, double *out)
 /* ------------------------------------------------------------------------ */
 static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
+/* The three factors of the specular lobe for n.l > 0: the GGX normal
+ * distribution D(h) with alpha = r^2, the Schlick weight P = (1 - v.h)^5
+ * (F = F0 + (1 - F0) P), and the visibility term Vis = G2 / (4 n.l n.v) of
+ * the height-correlated Smith masking-shadowing function
+ * G2 = 1 / (1 + Lambda(v) + Lambda(l)) (Heitz, "Understanding the
+ * Masking-Shadowing Function in Microfacet-Based BRDFs", JCGT 2014), written
+ * with Lambda(w) = (sqrt(1 + alpha^2 tan^2) - 1) / 2 cleared of fractions. */
+typedef struct {
+    double NdotL, NdotV, NdotH, VdotH, a2, Q, D, sv, sl, A, B, Vis, P;
+} spec_terms;
+
+static void spec_eval(const double n[3], const double v[3], const double l[3], double r,
+                      spec_terms *t)
+{
+    t->NdotL = dot3(n, l);
+    double NdotV = dot3(n, v);
+    if (NdotV < 1e-4) NdotV = 1e-4;
+    t->NdotV = NdotV;
+    double h[3] = {l[0] + v[0], l[1] + v[1], l[2] + v[2]};
+    double hn = sqrt(dot3(h, h));
+    if (hn > 0.0) {
+        for (int d = 0; d < 3; ++d) h[d] /= hn;
+    } else {
+        for (int d = 0; d < 3; ++d) h[d] = n[d];
+    }
+    double NdotH = dot3(n, h);
+    t->NdotH = NdotH < 0.0 ? 0.0 : NdotH;
+    double VdotH = dot3(v, h);
+    t->VdotH = VdotH < 0.0 ? 0.0 : VdotH;
+    double alpha = r * r;
+    t->a2 = alpha * alpha;
+    t->Q = t->NdotH * t->NdotH * (t->a2 - 1.0) + 1.0;
+    t->D = t->a2 / (M_PI * t->Q * t->Q);
+    t->sv = sqrt(NdotV * NdotV * (1.0 - t->a2) + t->a2);
+    t->sl = sqrt(t->NdotL * t->NdotL * (1.0 - t->a2) + t->a2);
+    t->A = t->NdotL * t->sv;
+    t->B = NdotV * t->sl;
+    t->Vis = 0.5 / (t->A + t->B);
+    t->P = pow(1.0 - t->VdotH, 5.0);
+}
+
+/* Specular factors for pinning: D, Vis and P per sample (0 where n.l <= 0). */
+void or_brdf_terms(const double *n, const double *v, const double *l, const double *r, int64_t cnt,
+                   double *D, double *Vis, double *P)
+{
+    for (int64_t i = 0; i < cnt; ++i) {
+        spec_terms t;
+        spec_eval(n + 3 * i, v + 3 * i, l + 3 * i, r[i], &t);
+        int lit = t.NdotL > 0.0;
+        D[i] = lit ? t.D : 0.0;
+        Vis[i] = lit ? t.Vis : 0.0;
+        P[i] = lit ? t.P : 0.0;
+    }
+}
+
 static void brdf_eval(const double n[3], const double v[3], const double l[3], const double a[3],
                       double r, double m, double f0, int diffuse_only, double f[3],
                       double dfa[3], double dfr[3], double dfm[3])
@@ -453,27 +508,10 @@ static void brdf_eval(const double n[3], const double v[3], const double l[3], c
         }
         return;
     }
-    double NdotV = dot3(n, v);
-    if (NdotV < 1e-4) NdotV = 1e-4;
-    double h[3] = {l[0] + v[0], l[1] + v[1], l[2] + v[2]};
-    double hn = sqrt(dot3(h, h));
-    if (hn > 0.0) {
-        for (int d = 0; d < 3; ++d) h[d] /= hn;
-    } else {
-        for (int d = 0; d < 3; ++d) h[d] = n[d];
-    }
-    double NdotH = dot3(n, h);
-    if (NdotH < 0.0) NdotH = 0.0;
-    double VdotH = dot3(v, h);
-    if (VdotH < 0.0) VdotH = 0.0;
-    double alpha = r * r, a2 = alpha * alpha;
-    double Q = NdotH * NdotH * (a2 - 1.0) + 1.0;
-    double D = a2 / (M_PI * Q * Q);
-    double sv = sqrt(NdotV * NdotV * (1.0 - a2) + a2);
-    double sl = sqrt(NdotL * NdotL * (1.0 - a2) + a2);
-    double A = NdotL * sv, B = NdotV * sl;
-    double Vis = 0.5 / (A + B);
-    double P = pow(1.0 - VdotH, 5.0);
+    spec_terms t;
+    spec_eval(n, v, l, r, &t);
+    const double NdotV = t.NdotV, NdotH = t.NdotH, a2 = t.a2, Q = t.Q, D = t.D;
+    const double sv = t.sv, sl = t.sl, A = t.A, B = t.B, Vis = t.Vis, P = t.P;
     /* derivatives with respect to a2 = r^4 */
     double dD_da2 = (Q - 2.0 * a2 * NdotH * NdotH) / (M_PI * Q * Q * Q);
     double dA_da2 = NdotL * (1.0 - NdotV * NdotV) / (2.0 * sv);
@@ -867,9 +905,14 @@ static void incoming(const or_model *M, const or_env *E, const or_sampling *S, i
 /* Query mode (P->dir != NULL): rgb[p] = L_in(x_p, dir_p), vis[p] = V,       */
 /*   depth[p] = d (the distillation outputs, Sec. 3.3).                      */
 /* ------------------------------------------------------------------------ */
-void or_render(const or_model *M, const or_env *E, const or_sampling *S, const or_points *P,
-               int32_t indirect, double *rgb, double *vis, double *depth)
+/* Returns 0, or -1 without touching the outputs when a required pointer is
+ * NULL (shade mode needs nrm and wo). */
+int32_t or_render(const or_model *M, const or_env *E, const or_sampling *S, const or_points *P,
+                  int32_t indirect, double *rgb, double *vis, double *depth)
 {
+    if (!M || !E || !S || !P || !rgb || (P->n > 0 && !P->pos)) return -1;
+    if (P->n > 0 && !P->dir && (!P->nrm || !P->wo)) return -1;
+    if (!M->grid.table || !E->rgb) return -1;
     const or_grid *g = &M->grid;
     const int nf = g->L * g->F;
     const int query = P->dir != NULL;
@@ -917,6 +960,7 @@ void or_render(const or_model *M, const or_env *E, const or_sampling *S, const o
     }
     if (mis) env_dist_free(&D);
     (void)nf;
+    return 0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1000,10 +1044,15 @@ static void encode_dx(const or_grid *g, const enc_rec *rec, const double *gf, do
         if (!rec->inside[d]) gx[d] = 0.0;
 }
 
-void or_backward(const or_model *M, const or_env *E, const or_sampling *S, const or_points *P,
-                 int32_t indirect, const float *g_rgb, const float *g_vis, const float *g_dep,
-                 double *g_table, double *g_brdf, double *g_irt, double *g_pos)
+/* Query mode only.  Returns 0, or -1 without touching the outputs when a
+ * required pointer is NULL (g_pos may be NULL). */
+int32_t or_backward(const or_model *M, const or_env *E, const or_sampling *S, const or_points *P,
+                    int32_t indirect, const float *g_rgb, const float *g_vis, const float *g_dep,
+                    double *g_table, double *g_brdf, double *g_irt, double *g_pos)
 {
+    if (!M || !E || !S || !P || !g_rgb || !g_vis || !g_dep || !g_table || !g_brdf || !g_irt) return -1;
+    if (P->n > 0 && (!P->pos || !P->dir)) return -1;
+    if (!M->grid.table || !E->rgb) return -1;
     const or_grid *g = &M->grid;
     const int nf = g->L * g->F;
     const int64_t nb_par = mlp_nparams(&M->brdf), ni_par = mlp_nparams(&M->irt);
@@ -1127,6 +1176,7 @@ void or_backward(const or_model *M, const or_env *E, const or_sampling *S, const
         free(lb);
         free(li);
     }
+    return 0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1169,7 +1219,7 @@ void or_adam(double *param, const double *grad, double *m, double *v, int64_t n,
 static double lum(const double *c) { return 0.2126 * c[0] + 0.7152 * c[1] + 0.0722 * c[2]; }
 
 void or_denoise(const float *rgb, const float *depth, const float *nrm, int32_t H, int32_t W, int32_t iters,
-                double sz, double sn, double sl, double *out)
+                double sz, double sn, double sl, double *out, double *var_out)
 {
     const size_t P = (size_t)H * W;
     double *c = (double *)malloc(P * 3 * sizeof(double));
@@ -1243,5 +1293,7 @@ void or_denoise(const float *rgb, const float *depth, const float *nrm, int32_t 
         t = var; var = var2; var2 = t;
     }
     for (size_t i = 0; i < 3 * P; ++i) out[i] = c[i];
+    if (var_out)
+        for (size_t i = 0; i < P; ++i) var_out[i] = var[i];
     free(c); free(c2); free(var); free(var2); free(gx); free(gy); free(g3);
 }

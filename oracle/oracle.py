@@ -72,13 +72,19 @@ class Points(C.Structure):
 _lib = None
 
 
+def _set_types(h):
+    h.or_l2_loss.restype = C.c_double
+    h.or_render.restype = C.c_int32
+    h.or_backward.restype = C.c_int32
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build()
         _lib = C.CDLL(_LIB)
-        _lib.or_l2_loss.restype = C.c_double
+        _set_types(_lib)
     return _lib
 
 
@@ -290,9 +296,11 @@ def render(om: OracleModel, oe: OracleEnv, samp: Sampling, pos, nrm=None, wo=Non
     else:
         vis = np.empty(n)
         dep = np.empty(n)
-    lib().or_render(C.byref(om.c), C.byref(oe.c), C.byref(samp), C.byref(P), C.c_int32(int(indirect)),
-                    _p(rgb), _p(vis), _p(dep))
+    rc = lib().or_render(C.byref(om.c), C.byref(oe.c), C.byref(samp), C.byref(P),
+                         C.c_int32(int(indirect)), _p(rgb), _p(vis), _p(dep))
     del keep
+    if rc != 0:
+        raise ValueError("or_render rejected its arguments (a required pointer is NULL)")
     return rgb, vis, dep
 
 
@@ -326,9 +334,12 @@ def backward(om: OracleModel, oe: OracleEnv, samp: Sampling, pos, dirs, g_rgb, g
     gb = np.zeros(om.n_brdf_params())
     gi = np.zeros(om.n_irt_params())
     gp = np.zeros((P.n, 3)) if want_pos else None
-    lib().or_backward(C.byref(om.c), C.byref(oe.c), C.byref(samp), C.byref(P), C.c_int32(int(indirect)),
-                      _p(g_rgb), _p(g_vis), _p(g_dep), _p(gt), _p(gb), _p(gi), _p(gp))
+    rc = lib().or_backward(C.byref(om.c), C.byref(oe.c), C.byref(samp), C.byref(P),
+                           C.c_int32(int(indirect)), _p(g_rgb), _p(g_vis), _p(g_dep), _p(gt), _p(gb),
+                           _p(gi), _p(gp))
     del keep
+    if rc != 0:
+        raise ValueError("or_backward rejected its arguments (a required pointer is NULL)")
     return dict(table=gt, brdf=split_mlp_grad(gb, om.brdf), irt=split_mlp_grad(gi, om.irt), pos=gp)
 
 
@@ -340,12 +351,24 @@ def adam(param, grad, m, v, step, lr=2e-3, b1=0.9, b2=0.999, eps=1e-8, wd=0.0):
     return p, m, v
 
 
-def denoise(rgb, depth, nrm, iters=5, sigma_z=1.0, sigma_n=128.0, sigma_l=4.0):
+def denoise(rgb, depth, nrm, iters=5, sigma_z=1.0, sigma_n=128.0, sigma_l=4.0, return_var=False):
     """Spatial SVGF filter of an [H, W, 3] image with depth [H, W] and normal
-    [H, W, 3] guides; returns [H, W, 3] float64."""
+    [H, W, 3] guides; returns [H, W, 3] float64 (and, with return_var, the
+    luminance variance [H, W] carried out of the last iteration)."""
     rgb, depth, nrm = _f32(rgb), _f32(depth), _f32(nrm)
     H, W = depth.shape
     out = np.empty((H, W, 3))
+    var = np.empty((H, W)) if return_var else None
     lib().or_denoise(_p(rgb), _p(depth), _p(nrm), C.c_int32(H), C.c_int32(W), C.c_int32(iters),
-                     C.c_double(sigma_z), C.c_double(sigma_n), C.c_double(sigma_l), _p(out))
-    return out
+                     C.c_double(sigma_z), C.c_double(sigma_n), C.c_double(sigma_l), _p(out), _p(var))
+    return (out, var) if return_var else out
+
+
+def brdf_terms(n, v, l, r):
+    """Specular factors per sample: GGX D, the height-correlated Smith
+    visibility Vis = G2 / (4 n.l n.v) and the Schlick weight (1 - v.h)^5."""
+    n, v, l, r = _f64(n), _f64(v), _f64(l), _f64(r)
+    cnt = n.shape[0]
+    D, Vis, P = np.empty(cnt), np.empty(cnt), np.empty(cnt)
+    lib().or_brdf_terms(_p(n), _p(v), _p(l), _p(r), C.c_int64(cnt), _p(D), _p(Vis), _p(P))
+    return D, Vis, P
