@@ -11,9 +11,10 @@
  *
  * Conventions for every call:
  *   - Array arguments are DEVICE pointers (HBM), caller-allocated,
- *     contiguous, row-major, at least 16-byte aligned (8-byte for FP16/BF16
- *     parameter arrays).  Descriptor structs are HOST memory, read only
- *     during the call.
+ *     contiguous, row-major, at least 16-byte aligned (FP16/BF16 tables and
+ *     weights included; only the shadow written by hg_adam_step and the
+ *     light-sampling distribution need just 8 bytes).  Descriptor structs
+ *     are HOST memory, read only during the call.
  *   - Work is enqueued asynchronously on `stream`; nothing synchronises.
  *   - No call allocates device memory; gradients are accumulated (+=) into
  *     caller buffers, so the caller zeroes them between steps.

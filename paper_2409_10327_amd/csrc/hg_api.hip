@@ -258,7 +258,7 @@ hg_status render(const hg_model *model, const hg_env *env, const hg_sampling *sa
     hipError_t e;
     if (prec == Prec::Mixed) e = hg::launch_render_mixed(k, indirect, query, stream);
     else if (query || samp->n_dirs >= 16) e = hg::launch_render_f32_mma(k, indirect, query, stream);
-    else e = hg::launch_render_f32(k, indirect, query, stream);
+    else e = hg::launch_render_f32_shade(k, indirect, stream);
     return hip_status(e, indirect ? "hg_render_indirect" : "hg_render_direct");
 }
 

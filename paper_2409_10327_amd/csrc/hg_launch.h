@@ -3,9 +3,36 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "hg_device.h"
 
 namespace hg {
+
+// Compute-unit count of the calling thread's current device, cached per
+// device ordinal (a relaxed atomic: concurrent first calls store the same
+// value).  Devices beyond the cache are queried on every call.
+inline hipError_t current_device_cus(int &out) {
+    constexpr int kMaxDev = 64;
+    static std::atomic<int> cache[kMaxDev];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev >= 0 && dev < kMaxDev) {
+        const int c = cache[dev].load(std::memory_order_relaxed);
+        if (c > 0) {
+            out = c;
+            return hipSuccess;
+        }
+    }
+    int c = 0;
+    e = hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    if (c < 1) return hipErrorInvalidDevice;
+    if (dev >= 0 && dev < kMaxDev) cache[dev].store(c, std::memory_order_relaxed);
+    out = c;
+    return hipSuccess;
+}
 
 struct BwdK {
     RenderK r;
@@ -18,7 +45,7 @@ struct BwdK {
 
 hipError_t launch_encode(const GridK &g, bool f16, const float *pos, int64_t n, float *feat, hipStream_t s);
 hipError_t launch_encode_index(const GridK &g, const float *pos, int64_t n, uint32_t *idx, float *w, hipStream_t s);
-hipError_t launch_render_f32(const RenderK &a, bool indirect, bool query, hipStream_t s);
+hipError_t launch_render_f32_shade(const RenderK &a, bool indirect, hipStream_t s);
 hipError_t launch_render_f32_mma(const RenderK &a, bool indirect, bool query, hipStream_t s);
 hipError_t launch_render_mixed(const RenderK &a, bool indirect, bool query, hipStream_t s);
 hipError_t launch_backward(const BwdK &a, bool f16, bool indirect, hipStream_t s);

@@ -1,7 +1,8 @@
 // hg_render.hip -- FP32 forward kernels (one query per lane, vector ALU).
 //
 // encode:  f = H(x) per (point, level) pair.
-// render:  Eq. (1) / Eq. (2) with the recursive bounce, shade and query mode.
+// render:  Eq. (1) / Eq. (2) with the recursive bounce, shade mode with fewer
+//          than 16 directions per point (the matrix-core kernel takes the rest).
 #include "hg_device.h"
 #include "hg_launch.h"
 
@@ -142,30 +143,6 @@ __device__ __forceinline__ void incoming(const RenderK &a, const float (&f)[kNF]
 }
 
 // --------------------------------------------------------------------------
-// Query mode: one lane per query (x, w) -> L_in, V, d.
-// --------------------------------------------------------------------------
-template <bool INDIRECT>
-__global__ __launch_bounds__(128) void k_render_query(const RenderK a) {
-    extern __shared__ float lds[];
-    const int lane = threadIdx.x & 63;
-    float *hbuf = lds + (threadIdx.x >> 6) * kHBuf;
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= a.n) return;
-    const float3 x = make_float3(a.pos[3 * p], a.pos[3 * p + 1], a.pos[3 * p + 2]);
-    const float3 w = make_float3(a.dir[3 * p], a.dir[3 * p + 1], a.dir[3 * p + 2]);
-    float f[kNF];
-    encode<float>(a.g, x.x, x.y, x.z, f);
-    float3 Lin;
-    float V, d;
-    incoming<INDIRECT>(a, f, x, w, (uint32_t)p, 0u, hbuf, lane, Lin, V, d);
-    a.rgb[3 * p] = Lin.x;
-    a.rgb[3 * p + 1] = Lin.y;
-    a.rgb[3 * p + 2] = Lin.z;
-    if (a.vis) a.vis[p] = V;
-    if (a.depth) a.depth[p] = d;
-}
-
-// --------------------------------------------------------------------------
 // Shade mode: G = min(N, 64) lanes per pixel, 64/G pixels per wave; each lane
 // sums N/G directions with Kahan compensation, then the G lanes of a pixel
 // combine their (sum, compensation) pairs with TwoSum in a fixed butterfly.
@@ -247,25 +224,19 @@ __global__ __launch_bounds__(128) void k_render_shade(const RenderK a) {
     }
 }
 
-hipError_t launch_render_f32(const RenderK &a, bool indirect, bool query, hipStream_t s) {
+hipError_t launch_render_f32_shade(const RenderK &a, bool indirect, hipStream_t s) {
     // 128-thread blocks: two waves, 2 x 16.6 KB of per-lane activation columns
     const size_t lds = 2 * kHBuf * sizeof(float);
-    if (query) {
-        const unsigned blocks = (unsigned)((a.n + 127) / 128);
-        if (indirect) hipLaunchKernelGGL(k_render_query<true>, dim3(blocks), dim3(128), lds, s, a);
-        else hipLaunchKernelGGL(k_render_query<false>, dim3(blocks), dim3(128), lds, s, a);
+    const int64_t ppw = 64 >> a.s.g_shift;
+    const int64_t waves = (a.n + ppw - 1) / ppw;
+    const unsigned blocks = (unsigned)((waves + 1) / 2);
+    const bool mis = (a.s.flags & 4u) != 0;
+    if (indirect) {
+        if (mis) hipLaunchKernelGGL((k_render_shade<true, true>), dim3(blocks), dim3(128), lds, s, a);
+        else hipLaunchKernelGGL((k_render_shade<true, false>), dim3(blocks), dim3(128), lds, s, a);
     } else {
-        const int64_t ppw = 64 >> a.s.g_shift;
-        const int64_t waves = (a.n + ppw - 1) / ppw;
-        const unsigned blocks = (unsigned)((waves + 1) / 2);
-        const bool mis = (a.s.flags & 4u) != 0;
-        if (indirect) {
-            if (mis) hipLaunchKernelGGL((k_render_shade<true, true>), dim3(blocks), dim3(128), lds, s, a);
-            else hipLaunchKernelGGL((k_render_shade<true, false>), dim3(blocks), dim3(128), lds, s, a);
-        } else {
-            if (mis) hipLaunchKernelGGL((k_render_shade<false, true>), dim3(blocks), dim3(128), lds, s, a);
-            else hipLaunchKernelGGL((k_render_shade<false, false>), dim3(blocks), dim3(128), lds, s, a);
-        }
+        if (mis) hipLaunchKernelGGL((k_render_shade<false, true>), dim3(blocks), dim3(128), lds, s, a);
+        else hipLaunchKernelGGL((k_render_shade<false, false>), dim3(blocks), dim3(128), lds, s, a);
     }
     return hipGetLastError();
 }

@@ -1202,23 +1202,17 @@ __global__ __launch_bounds__(PP::kThreads) void k_render_mma(const RenderK a, in
     }
 }
 
-static int g_num_cus = 0;
-
 template <class PP>
 static hipError_t launch_mma(const RenderK &a, bool indirect, bool query, hipStream_t s) {
     if (!query && a.s.n_dirs < 16) return hipErrorNotSupported;
-    if (g_num_cus == 0) {
-        int dev = 0;
-        hipError_t e = hipGetDevice(&dev);
-        if (e != hipSuccess) return e;
-        e = hipDeviceGetAttribute(&g_num_cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e != hipSuccess) return e;
-    }
+    int n_cus = 0;
+    const hipError_t ec = current_device_cus(n_cus);
+    if (ec != hipSuccess) return ec;
     const int64_t ppw = query ? 64 : (64 >> a.s.g_shift);
     const int64_t items = (a.n + ppw - 1) / ppw;
     constexpr int wpb = PP::kThreads / 64;
     const int64_t want = (items + wpb - 1) / wpb;
-    const int64_t cap = (int64_t)g_num_cus * 2;
+    const int64_t cap = (int64_t)n_cus * 2;
     const unsigned blocks = (unsigned)(want < cap ? want : cap);
     const dim3 grid(blocks), block(PP::kThreads);
     const bool mis = (a.s.flags & 4u) != 0;
