@@ -262,6 +262,23 @@ hg_status hg_denoise(const float *rgb, const float *depth, const float *nrm, int
                      const hg_denoise_params *params, float *out, void *work, size_t work_bytes,
                      hipStream_t stream);
 
+/* hg_denoise for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same filter and the same kernels as hg_denoise, bit for bit, with the
+ * workspace taken from a static device array of the library instead of a
+ * caller buffer.  The array holds HG_DENOISE_NOALLOC_MAX_PIXELS pixels
+ * (48 MiB); each GPU the call runs on holds its own copy until the process
+ * ends.  The call allocates nothing (no hipMalloc, no library allocation);
+ * its first call on a device looks up that device's copy of the array.
+ * Arguments and errors as hg_denoise, plus HG_E_INVALID (nothing launched)
+ * for H * W > HG_DENOISE_NOALLOC_MAX_PIXELS.  The array needs no clearing
+ * (every pass writes what the next one reads), but all calls on one GPU
+ * share it: calls that overlap in time on one GPU (different streams, or
+ * threads without ordering) race and give undefined results. */
+#define HG_DENOISE_NOALLOC_MAX_PIXELS 1048576
+hg_status hg_denoise_noalloc(const float *rgb, const float *depth, const float *nrm, int32_t H, int32_t W,
+                             const hg_denoise_params *params, float *out, hipStream_t stream);
+
 /* Message describing the calling thread's last failed call ("" if none). */
 const char *hg_last_error(void);
 

@@ -64,7 +64,7 @@ class Points(C.Structure):
 
 
 EXPORTS = ["hg_encode", "hg_encode_index", "hg_render_direct", "hg_render_indirect", "hg_backward", "hg_l2_loss",
-           "hg_adam_step", "hg_denoise", "hg_denoise_workspace_size", "hg_env_build_sampling",
+           "hg_adam_step", "hg_denoise", "hg_denoise_noalloc", "hg_denoise_workspace_size", "hg_env_build_sampling",
            "hg_env_sampling_size", "hg_last_error"]
 
 _lib = None
@@ -87,6 +87,8 @@ def lib():
         L.hg_denoise_workspace_size.argtypes = [C.c_int32, C.c_int32]
         L.hg_denoise.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.POINTER(DenoiseParams),
                                  C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+        L.hg_denoise_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                         C.POINTER(DenoiseParams), C.c_void_p, C.c_void_p]
         L.hg_encode.argtypes = [C.POINTER(Grid), C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
         L.hg_encode_index.argtypes = [C.POINTER(Grid), C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
         for nm in ("hg_render_direct", "hg_render_indirect"):
@@ -361,6 +363,20 @@ def denoise(rgb, depth, nrm, iterations=5, sigma_z=1.0, sigma_n=128.0, sigma_l=4
     prm = DenoiseParams(iterations, sigma_z, sigma_n, sigma_l)
     _check(lib().hg_denoise(_ptr(rgb), _ptr(depth), _ptr(nrm), H, W, C.byref(prm), _ptr(out), _ptr(work),
                             work.numel() * work.element_size(), _stream(rgb.device)))
+    return out
+
+
+DENOISE_NOALLOC_MAX_PIXELS = 1 << 20  # HG_DENOISE_NOALLOC_MAX_PIXELS
+
+
+def denoise_noalloc(rgb, depth, nrm, out, iterations=5, sigma_z=1.0, sigma_n=128.0, sigma_l=4.0):
+    """hg_denoise_noalloc: as denoise() into the caller's ``out`` [H,W,3], with the
+    library's static per-device workspace (at most 2^20 pixels; concurrent calls
+    on one GPU race)."""
+    H, W = depth.shape
+    prm = DenoiseParams(iterations, sigma_z, sigma_n, sigma_l)
+    _check(lib().hg_denoise_noalloc(_ptr(rgb), _ptr(depth), _ptr(nrm), H, W, C.byref(prm), _ptr(out),
+                                    _stream(rgb.device)))
     return out
 
 

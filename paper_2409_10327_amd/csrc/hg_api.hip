@@ -413,10 +413,12 @@ size_t hg_denoise_workspace_size(int32_t H, int32_t W) {
     return hg::denoise_workspace_floats(H, W) * sizeof(float);
 }
 
-hg_status hg_denoise(const float *rgb, const float *depth, const float *nrm, int32_t H, int32_t W,
-                     const hg_denoise_params *params, float *out, void *work, size_t work_bytes,
-                     hipStream_t stream) {
-    g_err.clear();
+}  // extern "C"
+
+namespace {
+
+hg_status check_denoise(const float *rgb, const float *depth, const float *nrm, int32_t H, int32_t W,
+                        const hg_denoise_params *params, const float *out) {
     REQUIRE(params != nullptr, "params is NULL");
     REQUIRE(H >= 1 && W >= 1 && (int64_t)H * W < (int64_t(1) << 28) && H <= 65535 * 16,
             "image size %dx%d invalid", H, W);
@@ -429,12 +431,40 @@ hg_status hg_denoise(const float *rgb, const float *depth, const float *nrm, int
     CHECK(check_ptr(depth, "depth"));
     CHECK(check_ptr(nrm, "nrm"));
     CHECK(check_ptr(out, "out"));
+    return HG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hg_status hg_denoise(const float *rgb, const float *depth, const float *nrm, int32_t H, int32_t W,
+                     const hg_denoise_params *params, float *out, void *work, size_t work_bytes,
+                     hipStream_t stream) {
+    g_err.clear();
+    CHECK(check_denoise(rgb, depth, nrm, H, W, params, out));
     CHECK(check_ptr(work, "work"));
     REQUIRE(work_bytes >= hg_denoise_workspace_size(H, W), "work_bytes %zu < %zu", work_bytes,
             hg_denoise_workspace_size(H, W));
     return hip_status(hg::launch_denoise(rgb, depth, nrm, H, W, params->iterations, params->sigma_z,
                                          params->sigma_n, params->sigma_l, out, static_cast<float *>(work), stream),
                       "hg_denoise");
+}
+
+hg_status hg_denoise_noalloc(const float *rgb, const float *depth, const float *nrm, int32_t H, int32_t W,
+                             const hg_denoise_params *params, float *out, hipStream_t stream) {
+    g_err.clear();
+    CHECK(check_denoise(rgb, depth, nrm, H, W, params, out));
+    REQUIRE((int64_t)H * W <= HG_DENOISE_NOALLOC_MAX_PIXELS,
+            "image %dx%d exceeds the static workspace of %d pixels (use hg_denoise with a caller workspace)", H, W,
+            HG_DENOISE_NOALLOC_MAX_PIXELS);
+    float *ws = nullptr;
+    size_t ws_floats = 0;
+    CHECK(hip_status(hg::denoise_scratch(stream, &ws, &ws_floats), "hg_denoise_noalloc: device scratch lookup"));
+    REQUIRE(hg::denoise_workspace_floats(H, W) <= ws_floats, "static workspace too small");
+    return hip_status(hg::launch_denoise(rgb, depth, nrm, H, W, params->iterations, params->sigma_z,
+                                         params->sigma_n, params->sigma_l, out, ws, stream),
+                      "hg_denoise_noalloc");
 }
 
 }  // extern "C"

@@ -6,11 +6,21 @@
 // Workspace (floats per pixel): two colour+luminance buffers (4 each), two
 // variance buffers, depth gradient (2).  One thread per pixel; taps are read
 // through L1/L2 (neighbouring pixels share them).
+#include <mutex>
+
 #include "hg_launch.h"
 
 namespace hg {
 
 constexpr int kDnBlock = 16;
+constexpr int kDnFloatsPerPixel = 12;
+
+// Workspace of hg_denoise_noalloc: one copy per GPU (the runtime places it
+// when the code object is loaded on a device; it is held until the process
+// ends), sized for HG_DENOISE_NOALLOC_MAX_PIXELS pixels = 48 MiB.  Host code
+// never passes this name to a kernel (on the host it is only a stand-in for
+// the symbol): it passes the device address that denoise_scratch() obtains.
+static __device__ __align__(256) float scratch[(size_t)HG_DENOISE_NOALLOC_MAX_PIXELS * kDnFloatsPerPixel];
 
 __device__ __forceinline__ float luminance(float r, float g, float b) {
     return 0.2126f * r + 0.7152f * g + 0.0722f * b;
@@ -118,7 +128,46 @@ __global__ void k_dn_copy(const float *__restrict__ src, float *__restrict__ dst
     if (i < n) dst[i] = src[i];
 }
 
-size_t denoise_workspace_floats(int H, int W) { return (size_t)H * W * 12; }
+size_t denoise_workspace_floats(int H, int W) { return (size_t)H * W * kDnFloatsPerPixel; }
+
+namespace {
+constexpr int kMaxScratchDev = 64;
+std::mutex g_scratch_mu;
+std::atomic<float *> g_scratch_ptr[kMaxScratchDev];
+}  // namespace
+
+// Device address of `scratch` on the device that `s` belongs to (the current
+// device for the null stream).  Resolved once per device with that device
+// current, then read from the per-device cache.
+hipError_t denoise_scratch(hipStream_t s, float **ptr, size_t *floats) {
+    int dev = 0;
+    hipError_t e = s ? hipStreamGetDevice(s, &dev) : hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxScratchDev) return hipErrorInvalidDevice;
+    float *p = g_scratch_ptr[dev].load(std::memory_order_acquire);
+    if (p == nullptr) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        p = g_scratch_ptr[dev].load(std::memory_order_relaxed);
+        if (p == nullptr) {
+            int cur = 0;
+            if ((e = hipGetDevice(&cur)) != hipSuccess) return e;
+            if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+            void *q = nullptr;
+            e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+            if (cur != dev) {
+                const hipError_t back = hipSetDevice(cur);
+                if (e == hipSuccess) e = back;
+            }
+            if (e != hipSuccess) return e;
+            if (q == nullptr) return hipErrorInvalidSymbol;
+            p = static_cast<float *>(q);
+            g_scratch_ptr[dev].store(p, std::memory_order_release);
+        }
+    }
+    *ptr = p;
+    *floats = sizeof(scratch) / sizeof(float);
+    return hipSuccess;
+}
 
 hipError_t launch_denoise(const float *rgb, const float *depth, const float *nrm, int H, int W, int iters, float sz,
                           float sn, float sl, float *out, float *work, hipStream_t s) {

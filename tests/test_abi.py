@@ -19,7 +19,7 @@ def header_symbols():
 
 def test_library_exports_every_declared_symbol():
     syms = header_symbols()
-    assert len(syms) == 12, syms
+    assert len(syms) == 13, syms
     L = hg.lib()
     for s in syms:
         assert hasattr(L, s), s
@@ -152,6 +152,21 @@ def test_points_validation():
     p = hg.Points(); p.n, p.pos, p.nrm, p.wo, p.dir = 0, None, None, None, None
     assert call_render(pts=p, rgb=0) == hg.HG_OK            # n == 0 is a no-op
     assert call_render(rgb=0) == hg.HG_E_INVALID
+
+
+def test_denoise_noalloc_validation():
+    L = hg.lib()
+    f = FAKE
+    prm = hg.DenoiseParams(5, 1.0, 128.0, 4.0)
+    assert hg.DENOISE_NOALLOC_MAX_PIXELS == 1 << 20
+    # beyond the static workspace, or malformed: rejected before any device call
+    assert L.hg_denoise_noalloc(f, f, f, 1024, 1025, C.byref(prm), f, None) == hg.HG_E_INVALID
+    assert "static workspace" in L.hg_last_error().decode()
+    assert L.hg_denoise_noalloc(f, f, f, 0, 8, C.byref(prm), f, None) == hg.HG_E_INVALID
+    assert L.hg_denoise_noalloc(None, f, f, 8, 8, C.byref(prm), f, None) == hg.HG_E_INVALID
+    assert L.hg_denoise_noalloc(f, f, f, 8, 8, C.byref(prm), f + 4, None) == hg.HG_E_INVALID
+    bad = hg.DenoiseParams(11, 1.0, 128.0, 4.0)
+    assert L.hg_denoise_noalloc(f, f, f, 8, 8, C.byref(bad), f, None) == hg.HG_E_INVALID
 
 
 def test_denoise_validation():
