@@ -12,10 +12,11 @@
  * Conventions for every call:
  *   - Array arguments are DEVICE pointers (HBM), caller-allocated,
  *     contiguous, row-major, at least 16-byte aligned (FP16/BF16 tables and
- *     weights included; only the shadow written by hg_adam_step and the
- *     light-sampling distribution need just 8 bytes).  Descriptor structs
- *     are HOST memory, read only during the call.
- *   - Work is enqueued asynchronously on `stream`; nothing synchronises.
+ *     weights included; only the shadow written by hg_adam_step needs just
+ *     8 bytes).  Descriptor structs are HOST memory, read only during the
+ *     call.  The one host array argument is hg_env_build_sampling's map.
+ *   - Work is enqueued asynchronously on `stream`; nothing synchronises
+ *     except hg_env_build_sampling (once per environment map).
  *   - No call allocates device memory; gradients are accumulated (+=) into
  *     caller buffers, so the caller zeroes them between steps.
  *   - Return value: HG_OK, or an error code with no work enqueued
@@ -128,15 +129,22 @@ typedef struct {
  * [-pi + 2 pi x/W, -pi + 2 pi (x+1)/W]; its probability is proportional to
  * its Rec. 709 luminance times its solid angle, and inside a texel the
  * direction is uniform in solid angle.  An all-black map gives the uniform
- * sphere.  The distribution holds (8-byte aligned) cos(theta) at the row
- * edges [H+1] and the marginal CDF [H+1] and conditional CDFs [H][W+1] in
- * FP64, then the texel densities (per steradian) [H][W] in FP32;
- * hg_env_sampling_size(H, W) bytes.  Building it reads env->rgb on `stream`
- * and writes `dist`; it must be rebuilt when the map changes.
- * Errors (HG_E_INVALID, nothing launched): NULL pointers, H or W < 1 or
- * above 8192, dist not 8-byte aligned, bytes too small. */
+ * sphere.  Built once per map on the HOST in double precision from
+ * rgb_host (host memory, [H][W][3] FP32, the same values as hg_env.rgb),
+ * then copied to `dist` (device memory, 16-byte aligned, at least
+ * hg_env_sampling_size(H, W) bytes) on `stream`; the call waits for that
+ * copy (it synchronises `stream`) and must be repeated when the map
+ * changes.  Device layout, all single precision: per row float4 (cos theta
+ * at the top edge, 1 - that cosine, 1 + the cosine at the bottom edge,
+ * top minus bottom cosine) [H]; marginal CDF over rows [H+1] and
+ * conditional CDFs over the columns of each row [H][W+1] as float2
+ * (hi, lo) with hi + lo the double value to 2^-48 relative; texel densities
+ * per steradian [H][W].  Errors (HG_E_INVALID, nothing copied): NULL
+ * pointers, H or W < 1 or above 8192, dist not 16-byte aligned, bytes too
+ * small; HG_E_HIP if the copy fails. */
 size_t hg_env_sampling_size(int32_t H, int32_t W);
-hg_status hg_env_build_sampling(const hg_env *env, void *dist, size_t bytes, hipStream_t stream);
+hg_status hg_env_build_sampling(const float *rgb_host, int32_t H, int32_t W, void *dist, size_t bytes,
+                                hipStream_t stream);
 
 /* Light sampling: n_dirs stratified cosine-weighted directions per primary
  * point and n_dirs2 per secondary point (8 in the paper's renderer,

@@ -82,7 +82,7 @@ def lib():
             getattr(L, name).restype = C.c_int
         L.hg_env_sampling_size.restype = C.c_size_t
         L.hg_env_sampling_size.argtypes = [C.c_int32, C.c_int32]
-        L.hg_env_build_sampling.argtypes = [C.POINTER(Env), C.c_void_p, C.c_size_t, C.c_void_p]
+        L.hg_env_build_sampling.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]
         L.hg_denoise_workspace_size.restype = C.c_size_t
         L.hg_denoise_workspace_size.argtypes = [C.c_int32, C.c_int32]
         L.hg_denoise.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.POINTER(DenoiseParams),
@@ -237,13 +237,15 @@ def env_struct(env: torch.Tensor, dist: torch.Tensor | None = None):
 
 def env_sampling(env: torch.Tensor) -> torch.Tensor:
     """Light-importance distribution of an environment map [H,W,3] (needed
-    by flags=HG_MIS); an opaque FP64 device buffer."""
+    by flags=HG_MIS): built by the library on the host from a host copy of
+    the map, returned as an opaque FP32 device buffer."""
     H, W = env.shape[0], env.shape[1]
     nbytes = lib().hg_env_sampling_size(H, W)
     if nbytes == 0:
         raise HGError(HG_E_INVALID, f"environment map {H}x{W} is outside [1, 8192]^2")
-    dist = torch.empty((nbytes + 7) // 8, device=env.device, dtype=torch.float64)
-    _check(lib().hg_env_build_sampling(C.byref(env_struct(env)), _ptr(dist), dist.numel() * 8,
+    host = env.detach().to("cpu", torch.float32).contiguous()
+    dist = torch.empty((nbytes + 3) // 4, device=env.device, dtype=torch.float32)
+    _check(lib().hg_env_build_sampling(C.c_void_p(host.data_ptr()), H, W, _ptr(dist), dist.numel() * 4,
                                        _stream(env.device)))
     return dist
 

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/hg.h"
 #include "hg_launch.h"
@@ -150,22 +151,20 @@ hg_status check_env(const hg_env *e, hg::EnvK &k) {
     k.W = e->W;
     k.Hf = (float)e->H;
     k.Wf = (float)e->W;
-    k.ct = k.marg = k.cond = nullptr;
+    k.rows = nullptr;
+    k.marg = k.cond = nullptr;
     k.dens = nullptr;
     if (e->dist) {
-        REQUIRE(aligned(e->dist, 8), "env.dist is not 8-byte aligned");
-        const double *d = static_cast<const double *>(e->dist);
-        k.ct = d;
-        k.marg = d + (e->H + 1);
+        REQUIRE(aligned(e->dist, 16), "env.dist is not 16-byte aligned");
+        k.rows = static_cast<const float4 *>(e->dist);
+        k.marg = reinterpret_cast<const float2 *>(k.rows + e->H);
         k.cond = k.marg + (e->H + 1);
         k.dens = reinterpret_cast<const float *>(k.cond + (size_t)e->H * (e->W + 1));
     }
     return HG_OK;
 }
 
-size_t env_sampling_bytes(int32_t H, int32_t W) {
-    return (size_t)(2 * (H + 1) + (size_t)H * (W + 1)) * sizeof(double) + (size_t)H * W * sizeof(float);
-}
+size_t env_sampling_bytes(int32_t H, int32_t W) { return hg::env_dist_bytes(H, W); }
 
 hg_status check_sampling(const hg_sampling *s, bool need_primary, hg::SampK &k) {
     REQUIRE(s != nullptr, "sampling is NULL");
@@ -395,17 +394,19 @@ size_t hg_env_sampling_size(int32_t H, int32_t W) {
     return env_sampling_bytes(H, W);
 }
 
-hg_status hg_env_build_sampling(const hg_env *env, void *dist, size_t bytes, hipStream_t stream) {
+hg_status hg_env_build_sampling(const float *rgb_host, int32_t H, int32_t W, void *dist, size_t bytes,
+                                hipStream_t stream) {
     g_err.clear();
-    REQUIRE(env != nullptr, "env is NULL");
-    REQUIRE(env->H >= 1 && env->W >= 1 && env->H <= 8192 && env->W <= 8192, "env size %dx%d outside [1, 8192]^2",
-            env->H, env->W);
-    CHECK(check_ptr(env->rgb, "env.rgb"));
-    CHECK(check_ptr(dist, "dist", 8));
-    REQUIRE(bytes >= env_sampling_bytes(env->H, env->W), "bytes %zu < %zu", bytes,
-            env_sampling_bytes(env->H, env->W));
-    return hip_status(hg::launch_env_dist(env->rgb, env->H, env->W, static_cast<double *>(dist), stream),
-                      "hg_env_build_sampling");
+    REQUIRE(rgb_host != nullptr, "rgb_host is NULL");
+    REQUIRE(H >= 1 && W >= 1 && H <= 8192 && W <= 8192, "env size %dx%d outside [1, 8192]^2", H, W);
+    CHECK(check_ptr(dist, "dist"));
+    REQUIRE(bytes >= env_sampling_bytes(H, W), "bytes %zu < %zu", bytes, env_sampling_bytes(H, W));
+    std::vector<unsigned char> host(env_sampling_bytes(H, W));
+    hg::build_env_dist_host(rgb_host, H, W, host.data());
+    CHECK(hip_status(hipMemcpyAsync(dist, host.data(), host.size(), hipMemcpyHostToDevice, stream),
+                     "hg_env_build_sampling: copy"));
+    // the staging buffer is freed on return
+    return hip_status(hipStreamSynchronize(stream), "hg_env_build_sampling: synchronise");
 }
 
 size_t hg_denoise_workspace_size(int32_t H, int32_t W) {

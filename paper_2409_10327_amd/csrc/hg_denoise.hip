@@ -102,7 +102,9 @@ __global__ __launch_bounds__(kDnBlock * kDnBlock) void k_dn_atrous(
             const float wz = __expf(-fabsf(zp - depth[q]) /
                                     (sz * fabsf(gp.x * (float)(i * step) + gp.y * (float)(j * step)) + 1e-6f));
             const float nd = npx * nrm[3 * q] + npy * nrm[3 * q + 1] + npz * nrm[3 * q + 2];
-            const float wn = nd > 0.0f ? __powf(nd, sn) : (sn == 0.0f ? 1.0f : 0.0f);
+            // nd^sn as exp2(sn log2 nd) by the hardware log2 / exp2
+            const float wn = nd > 0.0f ? __builtin_amdgcn_exp2f(sn * __builtin_amdgcn_logf(nd))
+                                       : (sn == 0.0f ? 1.0f : 0.0f);
             const float wl = __expf(-fabsf(cp.w - cq.w) / lden);
             const float w = h[i + 2] * h[j + 2] * wz * wn * wl;
             ws += w;

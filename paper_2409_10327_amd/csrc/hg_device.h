@@ -43,9 +43,11 @@ struct EnvK {
     const float *rgb;  // [H][W][3]
     int32_t H, W;
     float Hf, Wf;
-    // light-sampling distribution (MIS): cos(theta) at row edges [H+1],
-    // marginal CDF [H+1], conditional CDFs [H][W+1], densities [H][W]
-    const double *ct, *marg, *cond;
+    // light-sampling distribution (MIS): per row (cos theta_top,
+    // 1 - cos theta_top, 1 + cos theta_bottom, cos span) [H]; marginal CDF
+    // [H+1] and conditional CDFs [H][W+1] as (hi, lo) pairs; densities [H][W]
+    const float4 *rows;
+    const float2 *marg, *cond;
     const float *dens;
 };
 
@@ -92,9 +94,32 @@ __device__ __forceinline__ void sincos2pi_(float x, float &s, float &c) {
     c = __builtin_amdgcn_cosf(x);
 }
 __device__ __forceinline__ float sigmoidf_(float z) { return rcpf_(1.0f + __expf(-z)); }
-__device__ __forceinline__ float softplusf_(float z) {
-    return fmaxf(z, 0.0f) + log1pf(__expf(-fabsf(z)));
+// log(1 + y) for y in [0, 1] from log(1 + y) = 2 atanh(s), s = y / (2 + y)
+// in [0, 1/3]: s from the hardware reciprocal plus one residual correction
+// (the rounding of 2 + y recovered exactly, Sterbenz), then 2 s + the odd
+// series of atanh to s^15 (truncation below 2e-9 relative), all in single
+// precision: within 2.1e-7 relative (mean 0.5 ulp) when emulated exactly
+// (the device library's log1pf takes the exponent through double precision).
+__device__ __forceinline__ float log1p01_(float y) {
+#pragma clang fp contract(off)
+    const float d = 2.0f + y;
+    const float ed = y - (d - 2.0f);  // (2 + y) - d, exact
+    const float rc = rcpf_(d);
+    const float s0 = y * rc;
+    float r = fmaf(-s0, d, y);
+    r = fmaf(-s0, ed, r);
+    const float s = fmaf(r, rc, s0);
+    const float s2 = s * s;
+    float q = 2.0f / 15.0f;
+    q = fmaf(q, s2, 2.0f / 13.0f);
+    q = fmaf(q, s2, 2.0f / 11.0f);
+    q = fmaf(q, s2, 2.0f / 9.0f);
+    q = fmaf(q, s2, 2.0f / 7.0f);
+    q = fmaf(q, s2, 2.0f / 5.0f);
+    q = fmaf(q, s2, 2.0f / 3.0f);
+    return fmaf(2.0f, s, (s * s2) * q);
 }
+__device__ __forceinline__ float softplusf_(float z) { return fmaxf(z, 0.0f) + log1p01_(__expf(-fabsf(z))); }
 
 // Weights are read through constant-address-space pointers so that the
 // wave-uniform reads become scalar loads.  The pointer is passed through an
@@ -596,38 +621,54 @@ __device__ __forceinline__ void mlp_fwd(const MlpK &m, const float (&in)[NIN], f
 // Multiple importance sampling of the primary directions (Sec. 4.1): light
 // samples from the environment's piecewise-constant distribution and GGX
 // samples of the visible normals (Heitz, JCGT 2018), balance heuristic.
-// The inversion of the FP64 CDFs and the placement inside the texel run in
-// FP64, so texel choices and in-texel offsets do not depend on FP32
-// rounding of the CDFs; the rest runs in FP32.
+// The CDFs come as (hi, lo) single-precision pairs of double values; the
+// test u - hi >= lo decides c <= u for an FP32 uniform exactly as the double
+// c would (u - hi is exact when u is within a factor two of hi, and
+// otherwise its sign already decides), so texel choices do not depend on
+// rounding.  Everything here is FP32.
 // --------------------------------------------------------------------------
 // largest i in [0, n-1] with c[i] <= u (c nondecreasing, c[0] = 0 <= u)
-__device__ __forceinline__ int cdf_find(const double *c, int n, double u) {
+__device__ __forceinline__ int cdf_find(const float2 *c, int n, float u) {
     int lo = 0, hi = n - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (c[mid] <= u) lo = mid;
+        const float2 v = c[mid];
+        if (u - v.x >= v.y) lo = mid;
         else hi = mid - 1;
     }
     return lo;
 }
 
+// position of u in [a, b) as a fraction of the interval
+__device__ __forceinline__ float cdf_frac(float2 a, float2 b, float u) {
+    const float num = (u - a.x) - a.y;
+    const float den = (b.x - a.x) + (b.y - a.y);
+    return den > 0.0f ? clamp01(num / den) : 0.5f;
+}
+
 // light sample for the stratified uniforms (s1, s2); returns the direction
 // and its density (per steradian)
-__device__ __forceinline__ float3 env_light_sample(const EnvK &e, double s1, double s2, float &dens) {
+__device__ __forceinline__ float3 env_light_sample(const EnvK &e, float s1, float s2, float &dens) {
     const int H = e.H, W = e.W;
     const int y = cdf_find(e.marg, H, s1);
-    const double fv = (s1 - e.marg[y]) / (e.marg[y + 1] - e.marg[y]);
-    const double *c = e.cond + (size_t)y * (W + 1);
+    const float fv = cdf_frac(e.marg[y], e.marg[y + 1], s1);
+    const float2 *c = e.cond + (size_t)y * (W + 1);
     const int x = cdf_find(c, W, s2);
-    const double fu = (s2 - c[x]) / (c[x + 1] - c[x]);
-    const double cth = e.ct[y] - fv * (e.ct[y] - e.ct[y + 1]);
-    const float sth = (float)sqrt((1.0 - cth) * (1.0 + cth));
-    // phi / pi in [-1, 1]
-    const float t = (float)(-1.0 + 2.0 * ((double)x + fu) / (double)W);
+    const float fu = cdf_frac(c[x], c[x + 1], s2);
+    // uniform in cos(theta) inside the row: cos = cos_top - fv span, with
+    // 1 - cos and 1 + cos each formed without cancellation
+    const float4 row = e.rows[y];
+    const float omc = fmaf(fv, row.w, row.y);
+    const float opc = fmaf(1.0f - fv, row.w, row.z);
+    const float cth = fv < 0.5f ? fmaf(-fv, row.w, row.x) : opc - 1.0f;
+    const float sth = sqrtf_(omc * opc);
+    // phi = -pi + 2 pi r with r = (x + fu) / W in [0, 1] revolutions, so
+    // (cos phi, sin phi) = -(cos 2 pi r, sin 2 pi r)
+    const float r = ((float)x + fu) / (float)W;
     float sn, cs;
-    sincospif(t, &sn, &cs);
+    sincos2pi_(r, sn, cs);
     dens = e.dens[(size_t)y * W + x];
-    return make_float3(sth * cs, (float)cth, sth * sn);
+    return make_float3(-sth * cs, cth, -sth * sn);
 }
 
 // density of the light distribution at a direction (texel lookup)
@@ -712,7 +753,7 @@ __device__ __forceinline__ float3 mis_direction(const RenderK &a, const Frame &f
     float3 d;
     float pe;
     if (light) {
-        d = env_light_sample(a.env, (double)s1, (double)s2, pe);
+        d = env_light_sample(a.env, s1, s2, pe);
     } else {
         d = ggx_sample(fr, vl, r, s1, s2);
         pe = env_light_density(a.env, d);

@@ -54,7 +54,8 @@ hipError_t launch_l2_loss(const float *rgb, const float *vis, const float *dep, 
                           float *loss, float *g_rgb, float *g_vis, float *g_dep, hipStream_t s);
 size_t denoise_workspace_floats(int H, int W);
 hipError_t denoise_scratch(hipStream_t s, float **ptr, size_t *floats);
-hipError_t launch_env_dist(const float *rgb, int H, int W, double *dist, hipStream_t s);
+size_t env_dist_bytes(int H, int W);
+void build_env_dist_host(const float *rgb, int H, int W, unsigned char *out);
 hipError_t launch_denoise(const float *rgb, const float *depth, const float *nrm, int H, int W, int iters, float sz,
                           float sn, float sl, float *out, float *work, hipStream_t s);
 hipError_t launch_adam(float *param, const float *grad, float *m, float *v, int64_t n, float lr, float b1,

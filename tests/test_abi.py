@@ -133,15 +133,17 @@ def test_mis_validation():
     assert call_render(env=env, samp=hg.sampling_struct(1, 8, 7, hg.HG_MIS)) == hg.HG_E_INVALID  # n_dirs = 1
     q = hg.Points(); q.n, q.pos, q.nrm, q.wo, q.dir = 10, FAKE, None, None, FAKE
     assert call_render(env=env, samp=mis, pts=q) == hg.HG_E_UNSUPPORTED  # query mode
-    # distribution size: 2 (H+1) + H (W+1) doubles and H W floats
-    assert L.hg_env_sampling_size(16, 32) == (2 * 17 + 16 * 33) * 8 + 16 * 32 * 4
+    # distribution size: H float4 rows, (H+1) + H (W+1) float2 CDF pairs, H W floats
+    assert L.hg_env_sampling_size(16, 32) == 16 * 16 + (17 + 16 * 33) * 8 + 16 * 32 * 4
     assert L.hg_env_sampling_size(0, 32) == 0 and L.hg_env_sampling_size(16, 9000) == 0
     need = L.hg_env_sampling_size(16, 32)
-    assert L.hg_env_build_sampling(C.byref(env), None, need, None) == hg.HG_E_INVALID
-    assert L.hg_env_build_sampling(C.byref(env), C.c_void_p(FAKE), need - 1, None) == hg.HG_E_INVALID
-    assert L.hg_env_build_sampling(C.byref(env), C.c_void_p(FAKE + 4), need, None) == hg.HG_E_INVALID
-    big = hg.Env(); big.H, big.W, big.rgb = 9000, 16, FAKE
-    assert L.hg_env_build_sampling(C.byref(big), C.c_void_p(FAKE), 1 << 30, None) == hg.HG_E_INVALID
+    host = (C.c_float * (16 * 32 * 3))()
+    assert L.hg_env_build_sampling(host, 16, 32, None, need, None) == hg.HG_E_INVALID
+    assert L.hg_env_build_sampling(None, 16, 32, C.c_void_p(FAKE), need, None) == hg.HG_E_INVALID
+    assert L.hg_env_build_sampling(host, 16, 32, C.c_void_p(FAKE), need - 1, None) == hg.HG_E_INVALID
+    assert L.hg_env_build_sampling(host, 16, 32, C.c_void_p(FAKE + 8), need, None) == hg.HG_E_INVALID
+    assert L.hg_env_build_sampling(host, 9000, 16, C.c_void_p(FAKE), 1 << 30, None) == hg.HG_E_INVALID
+    assert L.hg_env_build_sampling(host, 16, 0, C.c_void_p(FAKE), 1 << 30, None) == hg.HG_E_INVALID
 
 
 def test_points_validation():

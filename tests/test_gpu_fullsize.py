@@ -12,7 +12,7 @@ import torch
 import hg_inputs as H
 import paper_2409_10327_amd as hg
 from oracle import oracle as O
-from helpers import kink_margin, psnr, relerr
+from helpers import adversarial_positions, kink_margin, max_rel, psnr, relerr
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -34,6 +34,25 @@ def frame():
                 om=O.OracleModel(model, H.BOX_LO, H.BOX_EXTENT), oe=O.OracleEnv(env))
 
 
+@pytest.mark.parametrize("which", ["frame", "teacher"])
+def test_encode_indices_bit_exact_full_grids(frame, which):
+    """Hash and dense indices of the benchmark grid (T = 2^19, res 16..2048,
+    five dense levels) and the teacher grid (T = 2^20, six dense levels) on
+    random positions and positions on and next to every level's vertices."""
+    print(f"case: encode index, {which} grid", flush=True)
+    model = frame["model"] if which == "frame" else H.make_teacher(frame["cfg"])
+    r = frame["r"] if which == "frame" else hg.HashRenderer(model, DEV)
+    om = frame["om"] if which == "frame" else O.OracleModel(model, H.BOX_LO, H.BOX_EXTENT)
+    pos = adversarial_positions(model["res"], seed=5)
+    idx, w = hg.encode_index(r, frame["t"](pos))
+    torch.cuda.synchronize()
+    oidx, ow = O.encode_index(om, pos)
+    gi = idx.cpu().numpy().view(np.uint32)
+    assert np.array_equal(gi, oidx), np.argwhere(gi != oidx)[:5]
+    assert gi.max() < (1 << model["log2_T"])
+    assert np.max(np.abs(w.cpu().numpy() - ow)) < 2e-7
+
+
 @pytest.mark.parametrize("N,precision", [(128, "fp32"), (128, "mixed"), (512, "mixed")])
 def test_full_frame_sampled_pixels(frame, N, precision):
     print(f"case: full frame 800x800 N={N} {precision}", flush=True)
@@ -44,8 +63,8 @@ def test_full_frame_sampled_pixels(frame, N, precision):
     sm = frame["sample"] if N == 128 else frame["sample"][::4]
     orgb = O.render(frame["om"], frame["oe"], O.sampling(N, 8, H.SEED_DIRS, 0), frame["pos"][sm],
                     frame["nrm"][sm], frame["wo"][sm], indirect=True, want_vis=False, pid=sm)[0]
-    e, ps = relerr(rgb[sm], orgb), psnr(rgb[sm], orgb)
-    print(f"{precision} N={N}: sampled rgb rel {e:.3g}, PSNR {ps:.1f} dB")
+    e, ps, mr = relerr(rgb[sm], orgb), psnr(rgb[sm], orgb), max_rel(rgb[sm], orgb)
+    print(f"{precision} N={N}: sampled rgb rel {e:.3g}, element-wise max {mr:.3g}, PSNR {ps:.1f} dB")
     if precision == "fp32":
         assert e < 1e-5
     else:
