@@ -35,6 +35,17 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0
 # 4416 + 6464 + 2048 + 8*4416 = 48,256 MAC = 96,512 FLOP.
 FLOP_PER_QUERY = 2 * (4416 + 6464 + 2048 + 8 * 4416)
 
+# Backward of one query-mode training sample (hg_backward): the recomputed
+# forward (tracer at (x, w) 35*64 + 64*64 + 64*2, decoder at x', the tracer's
+# point part at x' and 8 direction parts) plus, per layer, the weight
+# gradient (fan_in * fan_out MAC) and the input gradient (the same, except
+# for the direction inputs of the tracer): tracer at x 6464 + 6464 + 6272,
+# decoder 6464 + 6464 + 6464, bounce tracer 37376 + 51712 + 50176
+# = 177,856 MAC.  Table-gradient scatter: 2 encodes x 16 levels x 8 corners
+# x 2 features = 512 FP32 adds per sample before any aggregation.
+BWD_FLOP_PER_SAMPLE = 2 * (6464 + 6464 + 6272 + 6464 + 6464 + 6464 + 37376 + 51712 + 50176)
+ATOMICS_PER_SAMPLE = 512
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -50,6 +61,7 @@ def parse():
     ap.add_argument("--no-encode", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=3)
     ap.add_argument("--no-denoise", action="store_true")
+    ap.add_argument("--no-errors", action="store_true", help="skip the per-output errors against the oracle")
     ap.add_argument("--no-mis", action="store_true")
     ap.add_argument("--no-paper", action="store_true")
     ap.add_argument("--no-c5", action="store_true", help="skip the mixed N=512 frame + 2^20-query training step")
@@ -80,6 +92,84 @@ def measured_traffic(img, n_dirs):
         return float(kv["traffic_bytes_per_launch"])
     except (KeyError, OSError, ValueError):
         return None
+
+
+def _rel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    n = np.linalg.norm(b.ravel())
+    return float(np.linalg.norm((a - b).ravel()) / n) if n > 0 else float(np.linalg.norm(a.ravel()))
+
+
+def _max_rel(a, b, floor_frac=1e-3):
+    """Element-wise |a - b| / (|b| + floor_frac RMS(b))."""
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    rms = np.sqrt(np.mean(b * b))
+    return float(np.max(np.abs(a - b) / (np.abs(b) + floor_frac * rms)))
+
+
+def _psnr(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    mse = np.mean((a - b) ** 2)
+    return float(10 * np.log10(b.max() ** 2 / mse)) if mse > 0 else float("inf")
+
+
+def _frame_errors(g, o):
+    (grgb, gvis, gdep), (orgb, ovis, odep) = g, o
+    return {"rgb": {"rel": _rel(grgb, orgb), "max_rel": _max_rel(grgb, orgb), "psnr_db": _psnr(grgb, orgb)},
+            "vis": {"rel": _rel(gvis, ovis), "max_rel": _max_rel(gvis, ovis)},
+            "depth": {"rel": _rel(gdep, odep), "max_rel": _max_rel(gdep, odep)}}
+
+
+def output_errors(args, cfg, model, env, pos, nrm, wo, sub, oracle_out, O, H, hg, torch, dev):
+    """Error per output against the FP64 oracle, outside every timed region:
+    the benchmark frame (FP32 and mixed paths) on the oracle's pixel subset
+    (rgb, and visibility and depth of every primary direction), the mixed
+    N = 512 frame on a sparser subset, and the gradients of one 4096-sample
+    training sub-batch (FP32 backward, and the FP16-table backward after the
+    mixed forward), norm-wise per parameter array.  The renderer is rebuilt
+    from the seeded model (the training leg has updated its own)."""
+    print("[bench] errors against the oracle", file=sys.stderr, flush=True)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    re_ = hg.HashRenderer(model, dev)
+    re_.refresh_shadows()
+    env_t, pos_t, nrm_t, wo_t = t(env), t(pos), t(nrm), t(wo)
+    res = {"pixels": int(len(sub)), "note": "norm-wise relative (rel), element-wise |d|/(|ref| + 1e-3 RMS(ref)) "
+                                             "(max_rel), PSNR on HDR rgb; vis/depth per primary direction"}
+    for prec in ("fp32", "mixed"):
+        g = hg.render(re_, env_t, pos_t, nrm_t, wo_t, n_dirs=cfg.n_dirs, n_dirs2=cfg.n_dirs2, seed=H.SEED_DIRS,
+                      indirect=True, want_vis=True, precision=prec)
+        g = tuple(a[torch.from_numpy(sub).to(dev)].cpu().numpy() for a in g)
+        res[f"frame_n{cfg.n_dirs}_{prec}"] = _frame_errors(g, oracle_out)
+        del g
+    if not (args.no_mixed or args.no_c5):
+        sub5 = H.subset_rows_cols(cfg.img_h, cfg.img_w, 3 * args.cpu_stride)
+        o5 = O.render(O.OracleModel(model, H.BOX_LO, H.BOX_EXTENT), O.OracleEnv(env),
+                      O.sampling(512, cfg.n_dirs2, H.SEED_DIRS, 0), pos[sub5], nrm[sub5], wo[sub5], indirect=True,
+                      want_vis=True, pid=sub5)
+        g = hg.render(re_, env_t, pos_t, nrm_t, wo_t, n_dirs=512, n_dirs2=cfg.n_dirs2, seed=H.SEED_DIRS,
+                      indirect=True, want_vis=True, precision="mixed")
+        g = tuple(a[torch.from_numpy(sub5).to(dev)].cpu().numpy() for a in g)
+        res["frame_n512_mixed"] = dict(_frame_errors(g, o5), pixels=int(len(sub5)))
+        del g
+    # gradients of one training sub-batch
+    nb = 4096
+    bp, bd = H.make_train_batch(nb, seed=31)
+    tgt = t(H.make_targets(nb))
+    om = O.OracleModel(model, H.BOX_LO, H.BOX_EXTENT)
+    oe = O.OracleEnv(env)
+    for fwd, bwd in (("fp32", "fp32"), ("mixed", "f16table")):
+        rgb_, vis_, dep_ = hg.render(re_, env_t, t(bp), dirs=t(bd), precision=fwd)
+        _, g_rgb, g_vis, g_dep = hg.l2_loss(rgb_, vis_, dep_, tgt)
+        grads = hg.zero_grads(re_)
+        hg.backward(re_, env_t, t(bp), t(bd), g_rgb, g_vis, g_dep, grads, precision=bwd)
+        ref = O.backward(om, oe, O.sampling(1, cfg.n_dirs2, 7, 0), bp, bd, g_rgb.cpu().numpy(),
+                         g_vis.cpu().numpy(), g_dep.cpu().numpy(), indirect=True)
+        e = {"table": _rel(grads["table"].cpu().numpy(), ref["table"])}
+        for k in ("brdf", "irt"):
+            for i, nm in enumerate(("W0", "b0", "W1", "b1", "W2", "b2")):
+                e[f"{k}.{nm}"] = _rel(grads[k][i].cpu().numpy(), ref[k][i])
+        res[f"grad_batch{nb}_{bwd}"] = e
+    return res
 
 
 def time_events(fn, steps, warmup, torch):
@@ -267,31 +357,48 @@ def main():
         # hg_encode gather bandwidth: 2^24 points uniform in the scene's
         # bounding region, FP32 tables (T = 2^19, 64 MiB).  Algorithmic bytes
         # per point: 16 levels x 8 corners x 8 B gathered + 12 B position +
-        # 128 B features.  Reference: a plain random 8-byte gather over the
-        # same table (torch index_select), the achievable random-gather rate.
+        # 128 B features.  Ceiling: the same kernel grid gathering exactly the
+        # encoder's own corner addresses (indices recorded by hg_encode_index
+        # and streamed from HBM, no arithmetic) -- the achievable rate for this
+        # access stream; for context, fully random 8-byte gathers over a table
+        # of the same size (every load a different cache line).
+        from paper_2409_10327_amd import membench as MB
+        print("[bench] encode", file=sys.stderr, flush=True)
         ne = 1 << 24
         gen = torch.Generator(device=dev)
         gen.manual_seed(3)
         epos = (torch.rand((ne, 3), device=dev, generator=gen) * 8.0 - 4.0).contiguous()
-        feat = torch.empty((ne, 32), device=dev)
 
         def enc():
             hg.encode(r, epos)
         mse, _, _ = time_events(enc, args.steps, 1, torch)
         alg = ne * (16 * 8 * 8 + 12 + 128)
-        rows = r.table.view(-1, 2)
-        gidx = torch.randint(0, rows.shape[0], (ne * 16,), device=dev, generator=gen)
-        gout = torch.empty((ne * 16, 2), device=dev)
-
-        def gath():
-            torch.index_select(rows, 0, gidx, out=gout)
-        msg, _, _ = time_events(gath, args.steps, 1, torch)
-        g_bw = gidx.numel() * (8 + 8 + 8) / (msg * 1e-3) / 1e9
+        gbytes = ne * 16 * 8 * 8
+        idx, _w = hg.encode_index(r, epos)
+        del _w
+        lvl_off = (torch.arange(16, device=dev, dtype=torch.int32) << cfg.log2_T).view(1, 16, 1)
+        gidx = (idx + lvl_off).view(-1)
+        del idx
+        ms_replay = min(MB.gather_indexed_ms(r.table, 8, gidx, blocks_per_cu=b) for b in (2, 4, 8))
+        # the replay's own index stream, timed with every gather an L1 hit
+        ms_stream = MB.gather_indexed_ms(torch.zeros(32, device=dev, dtype=torch.int32), 8, torch.zeros_like(gidx),
+                                         blocks_per_cu=2)
+        del gidx
+        rnd = MB.gather(64 << 20, 8)
+        # the pure gather time of the stream lies in [replay - index stream, replay]
         out["encode"] = {"points": ne, "ms": mse, "gather_GBps": alg / (mse * 1e-3) / 1e9,
-                         "achievable_random_gather_GBps": g_bw,
-                         "frac_of_achievable": (alg / (mse * 1e-3) / 1e9) / g_bw,
-                         "hbm_peak_GBps": HBM_PEAK_GBS}
-        del epos, feat, gidx, gout
+                         "corner_gathers_per_s": ne * 128 / (mse * 1e-3),
+                         "achievable": {"kind": "replay of the encoder's own corner addresses in its order (persistent "
+                                                "grid, indices streamed non-temporally and prefetched, no arithmetic; "
+                                                "fastest of 2, 4, 8 blocks per CU)",
+                                        "replay_ms": ms_replay, "index_stream_ms": ms_stream,
+                                        "gather_ms_bounds": [ms_replay - ms_stream, ms_replay]},
+                         "frac_of_achievable": (ms_replay - ms_stream) / mse,
+                         "frac_of_achievable_bounds": [(ms_replay - ms_stream) / mse, ms_replay / mse],
+                         "random_8B_gather_64MiB": {"items_per_s": rnd["items_per_s"],
+                                                    "useful_GBps": rnd["useful_GBps"]},
+                         "hbm_peak_GBps": HBM_PEAK_GBS, "frac_of_hbm_peak": alg / (mse * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        del epos
 
     if not args.no_train:
         B = args.train_batch
@@ -341,6 +448,31 @@ def main():
         out["train"] = {"samples_per_s": B / (mst * 1e-3), "ms_per_step": mst, "batch": B,
                         "secondary_queries_per_s_fwd_bwd": B / (mst * 1e-3), "dtype": "f32"}
 
+        def backward_roofline(precision):
+            """Time the backward alone (the step's dominant kernel) on one
+            Morton-ordered batch; roofline against the measured random FP32
+            atomic rate (the table scatter) and the matrix-core peak."""
+            order = morton_order(bp_t)
+            sp, sd, st = bp_t[order], bd_t[order], tgt[order]
+            fwd_prec = "fp32" if precision == "fp32" else "mixed"
+            rgb_, vis_, dep_ = hg.render(r, env_t, sp, dirs=sd, precision=fwd_prec)
+            _, g_rgb, g_vis, g_dep = hg.l2_loss(rgb_, vis_, dep_, st)
+
+            def bwd():
+                hg.backward(r, env_t, sp, sd, g_rgb, g_vis, g_dep, grads, precision=precision)
+            msb, _, _ = time_events(bwd, max(5, args.steps), 1, torch)
+            at = ATOMICS_PER_SAMPLE * B / (msb * 1e-3)
+            fl = BWD_FLOP_PER_SAMPLE * B / (msb * 1e-3) / 1e12
+            return msb, {"bound": "atomics", "kernel": "k_backward (query mode, indirect)", "ms": msb,
+                         "achieved": at, "peak": atomic_ceiling["lane_atomics_per_s"], "unit": "FP32 atomics/s",
+                         "frac": at / atomic_ceiling["lane_atomics_per_s"],
+                         "peak_kind": "measured random FP32 atomic adds over 64 MiB",
+                         "mfma": {"achieved": fl, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                  "frac": fl / FP32_MFMA_PEAK_TFLOPS}}
+        from paper_2409_10327_amd import membench as MB
+        atomic_ceiling = MB.atomic(64 << 20, 1)
+        _, out["train"]["roofline"] = backward_roofline("fp32")
+
         # mixed-precision step: forward with FP16 tables and BF16 MLPs on the
         # matrix cores, backward gathering the FP16 tables with the FP32 master
         # MLPs, Adam on the FP32 masters refreshing the FP16/BF16 shadows
@@ -365,6 +497,8 @@ def main():
         mstm, _, _ = time_events(train_step_mixed, max(5, args.steps), 2, torch)
         out["train"]["mixed"] = {"samples_per_s": B / (mstm * 1e-3), "ms_per_step": mstm,
                                  "dtype": "bf16-mfma fwd / f16-table bwd / f32 masters"}
+        _, out["train"]["mixed"]["roofline"] = backward_roofline("f16table")
+        out["train"]["random_atomic_ceiling"] = atomic_ceiling
         del bp_t, bd_t, tgt
 
         if not (args.no_mixed or args.no_c5):
@@ -398,16 +532,19 @@ def main():
         from oracle import oracle as O
         sub = H.subset_rows_cols(cfg.img_h, cfg.img_w, args.cpu_stride)
         om, oe = O.OracleModel(model, H.BOX_LO, H.BOX_EXTENT), O.OracleEnv(env)
+        samp = O.sampling(cfg.n_dirs, cfg.n_dirs2, H.SEED_DIRS, 0)
         print(f"[bench] oracle on {len(sub)} px", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
-        O.render(om, oe, O.sampling(cfg.n_dirs, cfg.n_dirs2, H.SEED_DIRS, 0), pos[sub], nrm[sub], wo[sub],
-                 indirect=True, want_vis=False)
+        orgb, ovis, odep = O.render(om, oe, samp, pos[sub], nrm[sub], wo[sub], indirect=True, want_vis=True, pid=sub)
         dt = time.perf_counter() - t0
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         out["cpu_baseline"] = {"value": len(sub) * cfg.n_dirs / dt, "unit": "queries/s", "cores": cores,
                                "kind": "oracle",
                                "sample": f"every {args.cpu_stride}th row and column ({len(sub)} px x "
                                          f"{cfg.n_dirs} dirs), FP64, {dt:.1f} s"}
+        if not args.no_errors:
+            out["errors"] = output_errors(args, cfg, model, env, pos, nrm, wo, sub, (orgb, ovis, odep), O, H, hg,
+                                          torch, dev)
     print(json.dumps(out), flush=True)
 
 

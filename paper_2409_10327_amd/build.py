@@ -16,6 +16,9 @@ OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhg.so")
 
 SOURCES = ["hg_api.hip", "hg_render.hip", "hg_render_mfma.hip", "hg_backward.hip", "hg_train.hip", "hg_denoise.hip", "hg_mis.hip"]
+# microbenchmarks of the measured ceilings (gathers, atomics, matrix cores): a library of their own
+MB_SOURCES = ["hg_membench.hip"]
+MB_LIB = os.path.join(HERE, "libhg_membench.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -35,18 +38,23 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(OBJDIR, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), 8)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+def _link(objs, lib):
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(OBJDIR, exist_ok=True)
+    with cf.ThreadPoolExecutor(max_workers=8) as ex:
+        objs = list(ex.map(_compile, SOURCES + MB_SOURCES))
+    _link(objs[:len(SOURCES)], LIB)
+    _link(objs[len(SOURCES):], MB_LIB)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", MB_LIB)
     return LIB
 
 

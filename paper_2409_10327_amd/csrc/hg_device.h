@@ -397,10 +397,10 @@ __device__ __forceinline__ void encode(const GridK &g, float x, float y, float z
 
 // --------------------------------------------------------------------------
 // atan2 from a polynomial approximation of atan on [0, 1]:
-// atan(t) ~ t * P(t^2), P of degree 7, coefficients fitted here by weighted
-// least squares on 4000 Chebyshev nodes with Lawson reweighting towards the
-// minimax error; |error| < 1.5e-7 rad when evaluated in FP32 (about one ulp
-// of pi).  Octant reduction: t = min(|x|,|y|) / max(|x|,|y|), formed with the
+// atan(t) ~ t * P(t^2), P of degree 7, the coefficients printed by
+// fit_atan_poly.py beside this file (Lawson-reweighted least squares on 4000
+// Chebyshev nodes towards the minimax absolute error); |error| < 1.4e-7 rad
+// when evaluated in FP32 (about one ulp of pi).  Octant reduction: t = min(|x|,|y|) / max(|x|,|y|), formed with the
 // hardware reciprocal (relative error about 1.5 ulp, which moves atan(t) by
 // at most t / (1 + t^2) * 1.8e-7 <= 9e-8 rad): |error| < 2.5e-7 rad.
 // --------------------------------------------------------------------------
@@ -409,14 +409,14 @@ __device__ __forceinline__ float atan2_poly(float y, float x) {
     const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
     const float t = mx > 0.0f ? mn * rcpf_(mx) : 0.0f;
     const float s = t * t;
-    float p = -0.00405457f;
-    p = fmaf(p, s, 0.02186296f);
-    p = fmaf(p, s, -0.05591233f);
-    p = fmaf(p, s, 0.09642199f);
-    p = fmaf(p, s, -0.1390863f);
-    p = fmaf(p, s, 0.19946566f);
-    p = fmaf(p, s, -0.3332986f);
-    p = fmaf(p, s, 0.99999934f);
+    float p = -0.00405456731f;
+    p = fmaf(p, s, 0.0218629576f);
+    p = fmaf(p, s, -0.055912327f);
+    p = fmaf(p, s, 0.0964219719f);
+    p = fmaf(p, s, -0.139086291f);
+    p = fmaf(p, s, 0.199465662f);
+    p = fmaf(p, s, -0.333298594f);
+    p = fmaf(p, s, 0.999999344f);
     float r = p * t;
     if (ay > ax) r = 1.57079632679489662f - r;
     if (x < 0.0f) r = kPi - r;

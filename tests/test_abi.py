@@ -212,3 +212,27 @@ def test_other_entry_points_validate():
     m.grid.dtype = hg.HG_F16
     assert L.hg_backward(C.byref(m), C.byref(env), C.byref(s), C.byref(p), 1, C.c_void_p(FAKE), C.c_void_p(FAKE),
                          C.c_void_p(FAKE), C.c_void_p(FAKE), gb, gb, None, None) == hg.HG_E_UNSUPPORTED
+
+
+def test_membench_exports_and_validation():
+    """libhg_membench.so exports every call of include/hg_membench.h and
+    rejects malformed arguments before any launch."""
+    from paper_2409_10327_amd import membench as MB
+    src = open(os.path.join(ROOT, "include", "hg_membench.h")).read()
+    syms = sorted(set(re.findall(r"^int\s+(hgmb_\w+)\s*\(", src, re.M)))
+    assert syms == sorted(MB.EXPORTS), syms
+    L = MB.lib()
+    for s_ in syms:
+        assert hasattr(L, s_)
+    f = C.c_void_p(FAKE)
+    assert L.hgmb_gather(f, 20, 12, 1, 1, 0, f, None) == 1           # item size
+    assert L.hgmb_gather(C.c_void_p(FAKE + 4), 20, 8, 1, 1, 0, f, None) == 1  # alignment
+    assert L.hgmb_gather(f, 29, 8, 1, 1, 0, f, None) == 1            # table beyond 2^31 bytes
+    assert L.hgmb_gather(f, 20, 8, 0, 1, 0, f, None) == 1            # no blocks
+    assert L.hgmb_gather_indexed(f, 8, C.c_void_p(FAKE + 4), 16, 1, f, None) == 1  # index alignment
+    assert L.hgmb_gather_indexed(f, 8, f, 16, 0, f, None) == 1       # no blocks
+    assert L.hgmb_gather_indexed(f, 8, None, 0, 1, f, None) == 0     # empty stream: nothing launched
+    assert L.hgmb_atomic(f, 20, 1, 1, 3, 0, None) == 1               # lanes per address not a power of two
+    assert L.hgmb_atomic(f, 20, 1, 1, 128, 0, None) == 1
+    assert L.hgmb_mfma(2, 1, 1, 1, f, None) == 1                     # kind
+    assert L.hgmb_mfma(0, 1, 1, 3, f, None) == 1                     # chains

@@ -65,10 +65,13 @@ def test_full_frame_sampled_pixels(frame, N, precision):
                     frame["nrm"][sm], frame["wo"][sm], indirect=True, want_vis=False, pid=sm)[0]
     e, ps, mr = relerr(rgb[sm], orgb), psnr(rgb[sm], orgb), max_rel(rgb[sm], orgb)
     print(f"{precision} N={N}: sampled rgb rel {e:.3g}, element-wise max {mr:.3g}, PSNR {ps:.1f} dB")
+    # element-wise: FP32 pixels here sit within 3.2e-6 (a pixel whose bounce
+    # frame flips at n'_z ~ 0 between FP32 and FP64 can reach ~3e-4, which
+    # this sample does not contain); mixed within 1.1e-3
     if precision == "fp32":
-        assert e < 1e-5
+        assert e < 1e-5 and mr < 1e-4
     else:
-        assert e < 2e-3 and ps >= 45.0
+        assert e < 2e-3 and ps >= 45.0 and mr < 5e-3
 
 
 @pytest.mark.parametrize("B,precision", [(1 << 18, "fp32"), (1 << 18, "mixed"), (1 << 20, "mixed")])
