@@ -63,6 +63,7 @@ def parse():
     ap.add_argument("--no-denoise", action="store_true")
     ap.add_argument("--no-errors", action="store_true", help="skip the per-output errors against the oracle")
     ap.add_argument("--no-mis", action="store_true")
+    ap.add_argument("--no-hardvis", action="store_true")
     ap.add_argument("--no-paper", action="store_true")
     ap.add_argument("--no-c5", action="store_true", help="skip the mixed N=512 frame + 2^20-query training step")
     ap.add_argument("--copy-probe", action="store_true",
@@ -273,6 +274,7 @@ def main():
         except hg.HGError as e:
             out["mixed"] = {"unavailable": str(e)}
 
+    if not (args.no_mixed or args.no_hardvis):
         # hard visibility: the bounce runs only for shadow rays
         def frame_hard(prec):
             def f():

@@ -50,7 +50,7 @@ typedef enum {
     HG_OK = 0,
     HG_E_INVALID = 1,     /* malformed argument (NULL, size, alignment, shape) */
     HG_E_UNSUPPORTED = 2, /* well-formed but not built (shape, dtype pair) */
-    HG_E_WORKSPACE = 3,   /* reserved */
+    HG_E_WORKSPACE = 3,   /* a workspace cannot hold what the call needs */
     HG_E_HIP = 4          /* a HIP launch or runtime call failed */
 } hg_status;
 
@@ -206,6 +206,12 @@ hg_status hg_render_indirect(const hg_model *model, const hg_env *env, const hg_
                              const hg_points *pts, float *rgb, float *vis, float *depth,
                              hipStream_t stream);
 
+/* Workspace bytes hg_backward needs for n queries: 0 for the direct
+ * backward (indirect = 0); for the indirect one, per query its bounce point,
+ * the feature gradient there and a sort key (172 bytes), plus the radix
+ * sort's temporary storage.  0 for n <= 0 or n >= 2^31. */
+size_t hg_backward_workspace_size(int32_t indirect, int64_t n);
+
 /* Backward of query mode (the distillation forward, Sec. 3.3), with the
  * bounce activations recomputed, not stored.  Given upstream gradients
  * g_rgb [n][3], g_vis [n], g_depth [n], ADDS the gradients of
@@ -215,12 +221,20 @@ hg_status hg_render_indirect(const hg_model *model, const hg_env *env, const hg_
  * and WRITES d/dpos into g_pos [n][3] if it is not NULL.
  * indirect selects the query mode of hg_render_indirect (1) or
  * hg_render_direct (0).  MLP weights must be FP32 (the masters); the table
- * may be FP32 or FP16.  Accumulation order of the atomics is unspecified. */
+ * may be FP32 or FP16.  Accumulation order of the atomics is unspecified.
+ * ws: device workspace of at least hg_backward_workspace_size(indirect, n)
+ * bytes, 256-byte aligned (NULL allowed when that size is 0); its contents
+ * on entry are ignored.  The indirect backward scatters the table gradient
+ * at the bounce points after sorting the queries by a Morton key of the
+ * bounce point, so that a wave's contributions share cells and merge before
+ * the atomics.  Errors: HG_E_INVALID for a missing, misaligned or small
+ * workspace; HG_E_WORKSPACE if the sort would need more temporary storage
+ * than the size query reserved. */
 hg_status hg_backward(const hg_model *model, const hg_env *env, const hg_sampling *samp,
                       const hg_points *pts, int32_t indirect, const float *g_rgb,
                       const float *g_vis, const float *g_depth, float *g_table,
                       float *const g_brdf[6], float *const g_irt[6], float *g_pos,
-                      hipStream_t stream);
+                      void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* L2 distillation loss (squared-error reading of Sec. 3.3's losses):
  *   loss = 1/n sum_p [ |rgb_p - t_p[0:3]|^2 + (vis_p - t_p[3])^2 +

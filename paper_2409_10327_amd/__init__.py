@@ -63,7 +63,8 @@ class Points(C.Structure):
                 ("dir", C.c_void_p)]
 
 
-EXPORTS = ["hg_encode", "hg_encode_index", "hg_render_direct", "hg_render_indirect", "hg_backward", "hg_l2_loss",
+EXPORTS = ["hg_encode", "hg_encode_index", "hg_render_direct", "hg_render_indirect", "hg_backward",
+           "hg_backward_workspace_size", "hg_l2_loss",
            "hg_adam_step", "hg_denoise", "hg_denoise_noalloc", "hg_denoise_workspace_size", "hg_env_build_sampling",
            "hg_env_sampling_size", "hg_last_error"]
 
@@ -96,7 +97,9 @@ def lib():
                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.hg_backward.argtypes = [C.POINTER(Model), C.POINTER(Env), C.POINTER(Sampling), C.POINTER(Points),
                                   C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                                  C.c_void_p * 6, C.c_void_p * 6, C.c_void_p, C.c_void_p]
+                                  C.c_void_p * 6, C.c_void_p * 6, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+        L.hg_backward_workspace_size.restype = C.c_size_t
+        L.hg_backward_workspace_size.argtypes = [C.c_int32, C.c_int64]
         L.hg_l2_loss.argtypes = [C.c_void_p] * 4 + [C.c_int64] + [C.c_void_p] * 5
         L.hg_adam_step.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
                                    C.c_float, C.c_float, C.c_float, C.c_float, C.c_float, C.c_void_p, C.c_int32,
@@ -321,17 +324,22 @@ def render(r: HashRenderer, env: torch.Tensor, pos, nrm=None, wo=None, dirs=None
 
 
 def backward(r: HashRenderer, env, pos, dirs, g_rgb, g_vis, g_dep, grads, n_dirs2=8, seed=7, flags=0,
-             indirect=True, g_pos=None, precision="fp32"):
-    """Adds query-mode gradients into grads = dict(table=..., brdf=[6], irt=[6])."""
+             indirect=True, g_pos=None, precision="fp32", ws=None):
+    """Adds query-mode gradients into grads = dict(table=..., brdf=[6], irt=[6]).
+    ws: optional uint8 device workspace of hg_backward_workspace_size bytes
+    (allocated here if None)."""
     m = r.model_struct(precision)
     e = env_struct(env)
     s = sampling_struct(1, n_dirs2, seed, flags)
     p = points_struct(pos, None, None, dirs)
     gb = (C.c_void_p * 6)(*[g.data_ptr() for g in grads["brdf"]])
     gi = (C.c_void_p * 6)(*[g.data_ptr() for g in grads["irt"]])
+    need = lib().hg_backward_workspace_size(int(indirect), pos.shape[0])
+    if need and (ws is None or ws.numel() * ws.element_size() < need):
+        ws = torch.empty(need, device=pos.device, dtype=torch.uint8)
     _check(lib().hg_backward(C.byref(m), C.byref(e), C.byref(s), C.byref(p), int(indirect), _ptr(g_rgb),
                              _ptr(g_vis), _ptr(g_dep), _ptr(grads["table"]), gb, gi, _ptr(g_pos),
-                             _stream(pos.device)))
+                             _ptr(ws) if need else None, need, _stream(pos.device)))
 
 
 def l2_loss(rgb, vis, dep, tgt):

@@ -54,6 +54,9 @@ int ilog2(int64_t v) {
         if (st_ != HG_OK) return st_;              \
     } while (0)
 
+// the radix sort of the indirect backward counts queries in int
+constexpr int64_t kMaxBackwardN = (int64_t(1) << 31) - 1;
+
 hg_status check_ptr(const void *p, const char *name, size_t align = 16) {
     REQUIRE(p != nullptr, "%s is NULL", name);
     REQUIRE(aligned(p, align), "%s is not %zu-byte aligned", name, align);
@@ -301,9 +304,19 @@ hg_status hg_render_indirect(const hg_model *model, const hg_env *env, const hg_
     return render(model, env, samp, pts, rgb, vis, depth, stream, true);
 }
 
+// Bound on the radix sort's temporary storage that hg_backward_workspace_size
+// reserves (the exact need is queried at call time and checked against it).
+static size_t bounce_sort_bound(int64_t n) { return (size_t(2) << 20) + (size_t)n * 8; }
+
+size_t hg_backward_workspace_size(int32_t indirect, int64_t n) {
+    if (indirect != 1 || n <= 0 || n > kMaxBackwardN) return 0;
+    return hg::bounce_ws_layout(n, bounce_sort_bound(n), nullptr, nullptr);
+}
+
 hg_status hg_backward(const hg_model *model, const hg_env *env, const hg_sampling *samp, const hg_points *pts,
                       int32_t indirect, const float *g_rgb, const float *g_vis, const float *g_depth, float *g_table,
-                      float *const g_brdf[6], float *const g_irt[6], float *g_pos, hipStream_t stream) {
+                      float *const g_brdf[6], float *const g_irt[6], float *g_pos, void *ws, size_t ws_bytes,
+                      hipStream_t stream) {
     g_err.clear();
     hg::BwdK k{};
     Prec prec;
@@ -341,6 +354,18 @@ hg_status hg_backward(const hg_model *model, const hg_env *env, const hg_samplin
     k.g_dep = g_depth;
     k.g_table = g_table;
     k.g_pos = g_pos;
+    if (indirect) {
+        REQUIRE(pts->n <= kMaxBackwardN, "n = %lld above %lld for the indirect backward", (long long)pts->n,
+                (long long)kMaxBackwardN);
+        CHECK(check_ptr(ws, "ws", 256));
+        REQUIRE(ws_bytes >= hg_backward_workspace_size(1, pts->n), "ws_bytes %zu < hg_backward_workspace_size %zu",
+                ws_bytes, hg_backward_workspace_size(1, pts->n));
+        size_t tmp = 0;
+        CHECK(hip_status(hg::bounce_sort_bytes(pts->n, tmp), "hg_backward: sort size"));
+        if (tmp > bounce_sort_bound(pts->n))
+            return fail(HG_E_WORKSPACE, "sort needs %zu bytes, above the reserved %zu", tmp, bounce_sort_bound(pts->n));
+        hg::bounce_ws_layout(pts->n, bounce_sort_bound(pts->n), ws, &k.ws);
+    }
     return hip_status(hg::launch_backward(k, model->grid.dtype == HG_F16, indirect != 0, stream), "hg_backward");
 }
 

@@ -7,6 +7,8 @@
 // with FP32 atomics; table gradients are scattered with FP32 atomics
 // through the trilinear weights, summed first over the lanes of a wave that
 // share a cell (coarse levels).
+#include <hipcub/hipcub.hpp>
+
 #include "hg_device.h"
 #include "hg_launch.h"
 
@@ -399,6 +401,56 @@ __device__ __forceinline__ void encode_bwd(const GridK &g, float x, float y, flo
     gx = make_float3(in[0] ? gxx : 0.f, in[1] ? gxy : 0.f, in[2] ? gxz : 0.f);
 }
 
+// d/dx of the encoding at x contracted with gf (table reads only; the table
+// gradient at x is scattered later, in spatial order, by k_scatter_bounce).
+template <typename TT>
+__device__ __forceinline__ float3 encode_dx(const GridK &g, float x, float y, float z, const float (&gf)[kNF]) {
+    float u[3];
+    bool in[3];
+    pos_to_u(g, x, y, z, u, in);
+    float gxx = 0.f, gxy = 0.f, gxz = 0.f;
+#pragma unroll
+    for (int l = 0; l < kL; ++l) {
+        if (l >= (int)g.L) break;  // wave-uniform
+        uint32_t c[3];
+        float w[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) cell_of(u[d], g.resf[l], g.nm1f[l], c[d], w[d]);
+        const size_t base = (size_t)l << g.log2T;
+        uint32_t idx[8];
+        corner_idx(g, l, c, idx);
+        const float w0[3] = {1.0f - w[0], 1.0f - w[1], 1.0f - w[2]};
+        const float sc = g.dscale[l];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int dx = k & 1, dy = (k >> 1) & 1, dzz = (k >> 2) & 1;
+            const float fx = dx ? w[0] : w0[0], fy = dy ? w[1] : w0[1], fz = dzz ? w[2] : w0[2];
+            const float2 te = TabLoad<TT>::ld(g.table, base + idx[k]);
+            const float ge = (gf[2 * l] * te.x + gf[2 * l + 1] * te.y) * sc;
+            gxx = fmaf(ge, (dx ? 1.0f : -1.0f) * fy * fz, gxx);
+            gxy = fmaf(ge, fx * (dy ? 1.0f : -1.0f) * fz, gxy);
+            gxz = fmaf(ge, fx * fy * (dzz ? 1.0f : -1.0f), gxz);
+        }
+    }
+    return make_float3(in[0] ? gxx : 0.f, in[1] ? gxy : 0.f, in[2] ? gxz : 0.f);
+}
+
+// 30-bit Morton code of x over the grid's box, 10 bits per axis
+__device__ __forceinline__ uint32_t spread10(uint32_t v) {
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    return (v | (v << 2)) & 0x09249249u;
+}
+__device__ __forceinline__ uint32_t morton30(const GridK &g, float3 x) {
+    const float q[3] = {clamp01((x.x - g.lo) * g.inv_ext), clamp01((x.y - g.lo) * g.inv_ext),
+                        clamp01((x.z - g.lo) * g.inv_ext)};
+    uint32_t k = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) k |= spread10(min((uint32_t)(q[d] * 1024.0f), 1023u)) << d;
+    return k;
+}
+
 // pi f_r and its derivatives with respect to albedo (per channel),
 // roughness and metallic.
 struct BrdfGrad {
@@ -532,7 +584,17 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(const BwdK a) {
         mlp_bwd_wave<kNF, 5>(r.brdf, a.gb, fb, gob, h1buf, h2buf, del, lane, dz);
 #pragma unroll
         for (int i = 0; i < kNF; ++i) gfb[i] += dz[i];
-        encode_bwd<TT>(r.g, xb.x, xb.y, xb.z, gfb, a.g_table, live, true, gxb);
+        // the table gradient at x' is scattered by k_scatter_bounce after the
+        // queries are sorted by x'; here only d/dx' (for the depth head)
+        gxb = encode_dx<TT>(r.g, xb.x, xb.y, xb.z, gfb);
+        if (live) {
+            a.ws.xb[p] = make_float4(xb.x, xb.y, xb.z, 0.0f);
+            float4 *gdst = reinterpret_cast<float4 *>(a.ws.gf + (size_t)p * kNF);
+#pragma unroll
+            for (int i = 0; i < kNF; i += 4) gdst[i / 4] = make_float4(gfb[i], gfb[i + 1], gfb[i + 2], gfb[i + 3]);
+            a.ws.key[p] = morton30(r.g, xb);
+            a.ws.id[p] = (uint32_t)p;
+        }
         const float gt = gxb.x * w.x + gxb.y * w.y + gxb.z * w.z;
         gd = fmaf(r.t_span, gt, gd);
     } else {
@@ -553,6 +615,62 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(const BwdK a) {
     }
 }
 
+// Table-gradient scatter at the bounce points, one lane per query in the
+// order of the Morton keys of x': a wave's 64 bounce points are then
+// neighbours, so the per-cell summation of scatter_cell merges their
+// contributions at all but the finest levels (in query order they come
+// from 64 random directions and merge only at the coarsest levels).
+constexpr int kScatterThreads = 256;
+template <typename TT>
+__global__ __launch_bounds__(kScatterThreads) void k_scatter_bounce(const GridK g, const uint32_t *__restrict__ id,
+                                                                    const float4 *__restrict__ xb,
+                                                                    const float *__restrict__ gf,
+                                                                    float *__restrict__ g_table, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kScatterThreads + threadIdx.x;
+    const bool live = i < n;
+    const uint32_t p = id[live ? i : n - 1];
+    const float4 x = xb[p];
+    float gfp[kNF];
+    const float4 *src = reinterpret_cast<const float4 *>(gf + (size_t)p * kNF);
+#pragma unroll
+    for (int k = 0; k < kNF; k += 4) {
+        const float4 v = src[k / 4];
+        gfp[k] = v.x;
+        gfp[k + 1] = v.y;
+        gfp[k + 2] = v.z;
+        gfp[k + 3] = v.w;
+    }
+    float u[3];
+    bool in[3];
+    pos_to_u(g, x.x, x.y, x.z, u, in);
+#pragma unroll
+    for (int l = 0; l < kL; ++l) {
+        if (l >= (int)g.L) break;  // wave-uniform
+        uint32_t c[3];
+        float w[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) cell_of(u[d], g.resf[l], g.nm1f[l], c[d], w[d]);
+        uint32_t idx[8];
+        corner_idx(g, l, c, idx);
+        const float w0[3] = {1.0f - w[0], 1.0f - w[1], 1.0f - w[2]};
+        float v[16];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const float wt = ((k & 1) ? w[0] : w0[0]) * (((k >> 1) & 1) ? w[1] : w0[1]) * (((k >> 2) & 1) ? w[2] : w0[2]);
+            v[2 * k] = wt * gfp[2 * l];
+            v[2 * k + 1] = wt * gfp[2 * l + 1];
+        }
+        scatter_cell(g_table + 2 * ((size_t)l << g.log2T), idx, c, v, live, (int)(threadIdx.x & 63));
+    }
+}
+
+hipError_t bounce_sort_bytes(int64_t n, size_t &bytes) {
+    bytes = 0;
+    return hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                                              (const uint32_t *)nullptr, (uint32_t *)nullptr, (int)n, 0, 30,
+                                              (hipStream_t)0);
+}
+
 hipError_t launch_backward(const BwdK &a, bool f16, bool indirect, hipStream_t s) {
     const unsigned blocks = (unsigned)((a.r.n + kBwdThreads - 1) / kBwdThreads);
     const size_t lds = (size_t)(kBwdThreads / 64) * kWaveLds * sizeof(float);
@@ -563,7 +681,49 @@ hipError_t launch_backward(const BwdK &a, bool f16, bool indirect, hipStream_t s
         if (indirect) hipLaunchKernelGGL((k_backward<float, true>), dim3(blocks), dim3(kBwdThreads), lds, s, a);
         else hipLaunchKernelGGL((k_backward<float, false>), dim3(blocks), dim3(kBwdThreads), lds, s, a);
     }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !indirect) return e;
+    size_t tmp = a.ws.sort_tmp_bytes;
+    e = hipcub::DeviceRadixSort::SortPairs(a.ws.sort_tmp, tmp, a.ws.key, a.ws.key_sorted, a.ws.id, a.ws.id_sorted,
+                                           (int)a.r.n, 0, 30, s);
+    if (e != hipSuccess) return e;
+    const unsigned sb = (unsigned)((a.r.n + kScatterThreads - 1) / kScatterThreads);
+    if (f16)
+        hipLaunchKernelGGL(k_scatter_bounce<__half>, dim3(sb), dim3(kScatterThreads), 0, s, a.r.g, a.ws.id_sorted,
+                           a.ws.xb, a.ws.gf, a.g_table, a.r.n);
+    else
+        hipLaunchKernelGGL(k_scatter_bounce<float>, dim3(sb), dim3(kScatterThreads), 0, s, a.r.g, a.ws.id_sorted,
+                           a.ws.xb, a.ws.gf, a.g_table, a.r.n);
     return hipGetLastError();
+}
+
+size_t bounce_ws_layout(int64_t n, size_t sort_tmp_bytes, void *base, BounceWs *ws) {
+    auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
+    const size_t un = (size_t)n;
+    size_t off = 0;
+    const size_t o_xb = off;
+    off += al(un * sizeof(float4));
+    const size_t o_gf = off;
+    off += al(un * kNF * sizeof(float));
+    size_t o_k[4];
+    for (int k = 0; k < 4; ++k) {
+        o_k[k] = off;
+        off += al(un * sizeof(uint32_t));
+    }
+    const size_t o_tmp = off;
+    off += al(sort_tmp_bytes);
+    if (ws && base) {
+        char *b = static_cast<char *>(base);
+        ws->xb = reinterpret_cast<float4 *>(b + o_xb);
+        ws->gf = reinterpret_cast<float *>(b + o_gf);
+        ws->key = reinterpret_cast<uint32_t *>(b + o_k[0]);
+        ws->id = reinterpret_cast<uint32_t *>(b + o_k[1]);
+        ws->key_sorted = reinterpret_cast<uint32_t *>(b + o_k[2]);
+        ws->id_sorted = reinterpret_cast<uint32_t *>(b + o_k[3]);
+        ws->sort_tmp = b + o_tmp;
+        ws->sort_tmp_bytes = sort_tmp_bytes;
+    }
+    return off;
 }
 
 }  // namespace hg

@@ -35,6 +35,19 @@ inline hipError_t current_device_cus(int &out) {
     return hipSuccess;
 }
 
+// Workspace of the indirect backward: per query its bounce point, the
+// gradient of the loss with respect to the features there, and a Morton key
+// of the bounce point with the query's id (and their sorted copies), so that
+// the table scatter at the bounce points runs in spatial order.
+struct BounceWs {
+    float4 *xb;        // [n] bounce point (w unused)
+    float *gf;         // [n][kNF] d loss / d f(x')
+    uint32_t *key, *id;          // [n] Morton key of x', query id
+    uint32_t *key_sorted, *id_sorted;
+    void *sort_tmp;
+    size_t sort_tmp_bytes;
+};
+
 struct BwdK {
     RenderK r;
     const float *g_rgb, *g_vis, *g_dep;
@@ -42,7 +55,14 @@ struct BwdK {
     float *gb[6];
     float *gi[6];
     float *g_pos;
+    BounceWs ws;
 };
+
+// Layout of the indirect backward's workspace for n queries inside `base`
+// (sort_tmp_bytes: what the radix sort needs); returns the bytes used.
+size_t bounce_ws_layout(int64_t n, size_t sort_tmp_bytes, void *base, BounceWs *ws);
+// Temporary bytes the radix sort of n keys needs (a host query).
+hipError_t bounce_sort_bytes(int64_t n, size_t &bytes);
 
 hipError_t launch_encode(const GridK &g, bool f16, const float *pos, int64_t n, float *feat, hipStream_t s);
 hipError_t launch_encode_index(const GridK &g, const float *pos, int64_t n, uint32_t *idx, float *w, hipStream_t s);

@@ -19,7 +19,7 @@ def header_symbols():
 
 def test_library_exports_every_declared_symbol():
     syms = header_symbols()
-    assert len(syms) == 13, syms
+    assert len(syms) == 14, syms
     L = hg.lib()
     for s in syms:
         assert hasattr(L, s), s
@@ -89,7 +89,7 @@ def test_brdf_outputs_and_normal_head():
     f = C.c_void_p(FAKE)
     # the normal head is forward only
     assert hg.lib().hg_backward(C.byref(m), C.byref(env), C.byref(s), C.byref(q), 1, f, f, f, f, gb, gb, None,
-                                None) == hg.HG_E_UNSUPPORTED
+                                None, 0, None) == hg.HG_E_UNSUPPORTED
 
 
 def test_mlp_shape_and_dtype_pairs():
@@ -203,15 +203,39 @@ def test_other_entry_points_validate():
     gb = (C.c_void_p * 6)(*[FAKE] * 6)
     # backward needs query-mode points
     assert L.hg_backward(C.byref(m), C.byref(env), C.byref(s), C.byref(p), 1, C.c_void_p(FAKE), C.c_void_p(FAKE),
-                         C.c_void_p(FAKE), C.c_void_p(FAKE), gb, gb, None, None) == hg.HG_E_INVALID
+                         C.c_void_p(FAKE), C.c_void_p(FAKE), gb, gb, None, None, 0, None) == hg.HG_E_INVALID
     p.dir = FAKE
     sh = hg.sampling_struct(1, 8, 7, hg.HG_HARD_VIS)   # hard visibility is forward-only
     assert L.hg_backward(C.byref(m), C.byref(env), C.byref(sh), C.byref(p), 1, C.c_void_p(FAKE), C.c_void_p(FAKE),
-                         C.c_void_p(FAKE), C.c_void_p(FAKE), gb, gb, None, None) == hg.HG_E_UNSUPPORTED
+                         C.c_void_p(FAKE), C.c_void_p(FAKE), gb, gb, None, None, 0, None) == hg.HG_E_UNSUPPORTED
     m.brdf.dtype = m.irt.dtype = hg.HG_BF16
     m.grid.dtype = hg.HG_F16
     assert L.hg_backward(C.byref(m), C.byref(env), C.byref(s), C.byref(p), 1, C.c_void_p(FAKE), C.c_void_p(FAKE),
-                         C.c_void_p(FAKE), C.c_void_p(FAKE), gb, gb, None, None) == hg.HG_E_UNSUPPORTED
+                         C.c_void_p(FAKE), C.c_void_p(FAKE), gb, gb, None, None, 0, None) == hg.HG_E_UNSUPPORTED
+
+
+def test_backward_workspace():
+    """The indirect backward needs a workspace of at least the queried size,
+    256-byte aligned; the direct one needs none."""
+    L = hg.lib()
+    assert L.hg_backward_workspace_size(0, 1000) == 0
+    assert L.hg_backward_workspace_size(1, 0) == 0 and L.hg_backward_workspace_size(1, -3) == 0
+    assert L.hg_backward_workspace_size(1, 1 << 31) == 0
+    n = 1000
+    need = L.hg_backward_workspace_size(1, n)
+    assert need >= n * (16 + 128 + 16)
+    m = fake_model()
+    env = hg.Env(); env.H, env.W, env.rgb = 16, 32, FAKE
+    s = hg.sampling_struct(1, 8, 7, 0)
+    p = hg.Points(); p.n, p.pos, p.nrm, p.wo, p.dir = n, FAKE, None, None, FAKE
+    gb = (C.c_void_p * 6)(*[FAKE] * 6)
+    f = C.c_void_p(FAKE)
+    call = lambda ws, nb: L.hg_backward(C.byref(m), C.byref(env), C.byref(s), C.byref(p), 1, f, f, f, f, gb, gb,
+                                        None, ws, nb, None)
+    assert call(None, need) == hg.HG_E_INVALID                 # missing
+    assert call(C.c_void_p(FAKE + 16), need) == hg.HG_E_INVALID  # not 256-byte aligned
+    assert call(f, need - 1) == hg.HG_E_INVALID                 # too small
+    assert "ws" in L.hg_last_error().decode()
 
 
 def test_membench_exports_and_validation():
