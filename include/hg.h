@@ -206,10 +206,11 @@ hg_status hg_render_indirect(const hg_model *model, const hg_env *env, const hg_
                              const hg_points *pts, float *rgb, float *vis, float *depth,
                              hipStream_t stream);
 
-/* Workspace bytes hg_backward needs for n queries: 0 for the direct
- * backward (indirect = 0); for the indirect one, per query its bounce point,
- * the feature gradient there and a sort key (172 bytes), plus the radix
- * sort's temporary storage.  0 for n <= 0 or n >= 2^31. */
+/* Workspace bytes hg_backward needs for n queries: per encoding the loss
+ * depends on (x, and with the bounce also x') one record of 160 bytes
+ * (the point, the feature gradient there, a sort key and an index, and
+ * their sorted copies), plus the radix sort's temporary storage.  0 for
+ * n <= 0, n >= 2^30 or indirect not 0/1. */
 size_t hg_backward_workspace_size(int32_t indirect, int64_t n);
 
 /* Backward of query mode (the distillation forward, Sec. 3.3), with the
@@ -223,13 +224,12 @@ size_t hg_backward_workspace_size(int32_t indirect, int64_t n);
  * hg_render_direct (0).  MLP weights must be FP32 (the masters); the table
  * may be FP32 or FP16.  Accumulation order of the atomics is unspecified.
  * ws: device workspace of at least hg_backward_workspace_size(indirect, n)
- * bytes, 256-byte aligned (NULL allowed when that size is 0); its contents
- * on entry are ignored.  The indirect backward scatters the table gradient
- * at the bounce points after sorting the queries by a Morton key of the
- * bounce point, so that a wave's contributions share cells and merge before
- * the atomics.  Errors: HG_E_INVALID for a missing, misaligned or small
- * workspace; HG_E_WORKSPACE if the sort would need more temporary storage
- * than the size query reserved. */
+ * bytes, 256-byte aligned; its contents on entry are ignored.  The table
+ * gradient is scattered after sorting the encodings' points by a Morton
+ * key, so that a wave's contributions share cells and merge before the
+ * atomics (all of it on `stream`).  Errors: HG_E_INVALID for a missing, misaligned or small workspace;
+ * HG_E_WORKSPACE if the sort would need more temporary storage than the
+ * size query reserved. */
 hg_status hg_backward(const hg_model *model, const hg_env *env, const hg_sampling *samp,
                       const hg_points *pts, int32_t indirect, const float *g_rgb,
                       const float *g_vis, const float *g_depth, float *g_table,

@@ -54,8 +54,8 @@ int ilog2(int64_t v) {
         if (st_ != HG_OK) return st_;              \
     } while (0)
 
-// the radix sort of the indirect backward counts queries in int
-constexpr int64_t kMaxBackwardN = (int64_t(1) << 31) - 1;
+// the backward's radix sort counts records (two per query) in int
+constexpr int64_t kMaxBackwardN = (int64_t(1) << 30) - 1;
 
 hg_status check_ptr(const void *p, const char *name, size_t align = 16) {
     REQUIRE(p != nullptr, "%s is NULL", name);
@@ -305,12 +305,14 @@ hg_status hg_render_indirect(const hg_model *model, const hg_env *env, const hg_
 }
 
 // Bound on the radix sort's temporary storage that hg_backward_workspace_size
-// reserves (the exact need is queried at call time and checked against it).
-static size_t bounce_sort_bound(int64_t n) { return (size_t(2) << 20) + (size_t)n * 8; }
+// reserves for `records` keys (the exact need is queried at call time and
+// checked against it).
+static size_t sort_bound(int64_t records) { return (size_t(2) << 20) + (size_t)records * 8; }
 
 size_t hg_backward_workspace_size(int32_t indirect, int64_t n) {
-    if (indirect != 1 || n <= 0 || n > kMaxBackwardN) return 0;
-    return hg::bounce_ws_layout(n, bounce_sort_bound(n), nullptr, nullptr);
+    if ((indirect != 0 && indirect != 1) || n <= 0 || n > kMaxBackwardN) return 0;
+    const int R = indirect ? 2 : 1;
+    return hg::backward_ws_layout(n, R, sort_bound(R * n), nullptr, nullptr);
 }
 
 hg_status hg_backward(const hg_model *model, const hg_env *env, const hg_sampling *samp, const hg_points *pts,
@@ -354,17 +356,19 @@ hg_status hg_backward(const hg_model *model, const hg_env *env, const hg_samplin
     k.g_dep = g_depth;
     k.g_table = g_table;
     k.g_pos = g_pos;
-    if (indirect) {
-        REQUIRE(pts->n <= kMaxBackwardN, "n = %lld above %lld for the indirect backward", (long long)pts->n,
-                (long long)kMaxBackwardN);
+    {
+        const int R = indirect ? 2 : 1;
+        REQUIRE(pts->n <= kMaxBackwardN, "n = %lld above %lld", (long long)pts->n, (long long)kMaxBackwardN);
         CHECK(check_ptr(ws, "ws", 256));
-        REQUIRE(ws_bytes >= hg_backward_workspace_size(1, pts->n), "ws_bytes %zu < hg_backward_workspace_size %zu",
-                ws_bytes, hg_backward_workspace_size(1, pts->n));
+        REQUIRE(ws_bytes >= hg_backward_workspace_size(indirect, pts->n),
+                "ws_bytes %zu < hg_backward_workspace_size %zu", ws_bytes,
+                hg_backward_workspace_size(indirect, pts->n));
+        const int64_t rec = R * pts->n;
         size_t tmp = 0;
-        CHECK(hip_status(hg::bounce_sort_bytes(pts->n, tmp), "hg_backward: sort size"));
-        if (tmp > bounce_sort_bound(pts->n))
-            return fail(HG_E_WORKSPACE, "sort needs %zu bytes, above the reserved %zu", tmp, bounce_sort_bound(pts->n));
-        hg::bounce_ws_layout(pts->n, bounce_sort_bound(pts->n), ws, &k.ws);
+        CHECK(hip_status(hg::backward_sort_bytes(rec, tmp), "hg_backward: sort size"));
+        if (tmp > sort_bound(rec))
+            return fail(HG_E_WORKSPACE, "sort needs %zu bytes, above the reserved %zu", tmp, sort_bound(rec));
+        hg::backward_ws_layout(pts->n, R, sort_bound(rec), ws, &k.ws);
     }
     return hip_status(hg::launch_backward(k, model->grid.dtype == HG_F16, indirect != 0, stream), "hg_backward");
 }

@@ -9,6 +9,7 @@
 // share a cell (coarse levels).
 #include <hipcub/hipcub.hpp>
 
+
 #include "hg_device.h"
 #include "hg_launch.h"
 
@@ -358,51 +359,8 @@ __device__ __forceinline__ void scatter_cell(float *gl, const uint32_t (&idx)[8]
     }
 }
 
-// Scatter gf through the trilinear weights of the cell of x into the table
-// gradient, and (optionally) return d/dx of the encoding contracted with gf.
-template <typename TT>
-__device__ __forceinline__ void encode_bwd(const GridK &g, float x, float y, float z, const float (&gf)[kNF], float *g_table,
-                           bool live, bool want_dx, float3 &gx) {
-    float u[3];
-    bool in[3];
-    pos_to_u(g, x, y, z, u, in);
-    float gxx = 0.f, gxy = 0.f, gxz = 0.f;
-#pragma unroll
-    for (int l = 0; l < kL; ++l) {
-        if (l >= (int)g.L) break;  // wave-uniform
-        uint32_t c[3];
-        float w[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) cell_of(u[d], g.resf[l], g.nm1f[l], c[d], w[d]);
-        const size_t base = (size_t)l << g.log2T;
-        uint32_t idx[8];
-        corner_idx(g, l, c, idx);
-        const float w0[3] = {1.0f - w[0], 1.0f - w[1], 1.0f - w[2]};
-        const float sc = g.dscale[l];
-        float v[16];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int dx = k & 1, dy = (k >> 1) & 1, dzz = (k >> 2) & 1;
-            const size_t e = base + idx[k];
-            const float fx = dx ? w[0] : w0[0], fy = dy ? w[1] : w0[1], fz = dzz ? w[2] : w0[2];
-            const float wt = fx * fy * fz;
-            v[2 * k] = wt * gf[2 * l];
-            v[2 * k + 1] = wt * gf[2 * l + 1];
-            if (want_dx) {
-                const float2 te = TabLoad<TT>::ld(g.table, e);
-                const float ge = (gf[2 * l] * te.x + gf[2 * l + 1] * te.y) * sc;
-                gxx = fmaf(ge, (dx ? 1.0f : -1.0f) * fy * fz, gxx);
-                gxy = fmaf(ge, fx * (dy ? 1.0f : -1.0f) * fz, gxy);
-                gxz = fmaf(ge, fx * fy * (dzz ? 1.0f : -1.0f), gxz);
-            }
-        }
-        scatter_cell(g_table + 2 * base, idx, c, v, live, (int)(threadIdx.x & 63));
-    }
-    gx = make_float3(in[0] ? gxx : 0.f, in[1] ? gxy : 0.f, in[2] ? gxz : 0.f);
-}
-
 // d/dx of the encoding at x contracted with gf (table reads only; the table
-// gradient at x is scattered later, in spatial order, by k_scatter_bounce).
+// gradient is scattered later, in spatial order, by k_scatter_records).
 template <typename TT>
 __device__ __forceinline__ float3 encode_dx(const GridK &g, float x, float y, float z, const float (&gf)[kNF]) {
     float u[3];
@@ -449,6 +407,18 @@ __device__ __forceinline__ uint32_t morton30(const GridK &g, float3 x) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) k |= spread10(min((uint32_t)(q[d] * 1024.0f), 1023u)) << d;
     return k;
+}
+
+// One record of the table scatter: the point, its feature gradient, the
+// Morton key and the record's own index.
+__device__ __forceinline__ void put_record(const BounceWs &ws, const GridK &g, int64_t rec, float3 x,
+                                           const float (&gf)[kNF]) {
+    ws.xb[rec] = make_float4(x.x, x.y, x.z, 0.0f);
+    float4 *dst = reinterpret_cast<float4 *>(ws.gf + (size_t)rec * kNF);
+#pragma unroll
+    for (int i = 0; i < kNF; i += 4) dst[i / 4] = make_float4(gf[i], gf[i + 1], gf[i + 2], gf[i + 3]);
+    ws.key[rec] = morton30(g, x);
+    ws.id[rec] = (uint32_t)rec;
 }
 
 // pi f_r and its derivatives with respect to albedo (per channel),
@@ -499,10 +469,11 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(const BwdK a) {
     float *h1buf = lds + (threadIdx.x >> 6) * kWaveLds;
     float *h2buf = h1buf + kHBuf;
     float *del = h2buf + kHBuf;
-    const int64_t p_raw = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t p_raw = a.p_begin + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const RenderK &r = a.r;
-    const bool live = p_raw < r.n;
-    const int64_t p = live ? p_raw : r.n - 1;
+    const bool live = p_raw < a.p_end;
+    const int64_t p = live ? p_raw : a.p_end - 1;
+    constexpr int R = INDIRECT ? 2 : 1;  // records per query: x (and x')
     const float3 x = make_float3(r.pos[3 * p], r.pos[3 * p + 1], r.pos[3 * p + 2]);
     const float3 w = make_float3(r.dir[3 * p], r.dir[3 * p + 1], r.dir[3 * p + 2]);
     float3 G = make_float3(0.f, 0.f, 0.f);
@@ -584,17 +555,10 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(const BwdK a) {
         mlp_bwd_wave<kNF, 5>(r.brdf, a.gb, fb, gob, h1buf, h2buf, del, lane, dz);
 #pragma unroll
         for (int i = 0; i < kNF; ++i) gfb[i] += dz[i];
-        // the table gradient at x' is scattered by k_scatter_bounce after the
+        // the table gradient at x' is scattered by k_scatter_records after the
         // queries are sorted by x'; here only d/dx' (for the depth head)
         gxb = encode_dx<TT>(r.g, xb.x, xb.y, xb.z, gfb);
-        if (live) {
-            a.ws.xb[p] = make_float4(xb.x, xb.y, xb.z, 0.0f);
-            float4 *gdst = reinterpret_cast<float4 *>(a.ws.gf + (size_t)p * kNF);
-#pragma unroll
-            for (int i = 0; i < kNF; i += 4) gdst[i / 4] = make_float4(gfb[i], gfb[i + 1], gfb[i + 2], gfb[i + 3]);
-            a.ws.key[p] = morton30(r.g, xb);
-            a.ws.id[p] = (uint32_t)p;
-        }
+        if (live) put_record(a.ws, r.g, R * p + 1, xb, gfb);
         const float gt = gxb.x * w.x + gxb.y * w.y + gxb.z * w.z;
         gd = fmaf(r.t_span, gt, gd);
     } else {
@@ -606,8 +570,10 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(const BwdK a) {
     z[kNF] = w.x; z[kNF + 1] = w.y; z[kNF + 2] = w.z;
     const float go2[2] = {gV * V * (1.0f - V), sp < 1.0f ? gd * sigmoidf_(o1p) : 0.0f};
     mlp_bwd_wave<kNI, 2>(r.irt, a.gi, z, go2, h1buf, h2buf, del, lane, dz);
-    float3 gx;
-    encode_bwd<TT>(r.g, x.x, x.y, x.z, dz, a.g_table, live, a.g_pos != nullptr, gx);
+    // the table gradient at x is scattered by k_scatter_records too
+    float3 gx = make_float3(0.f, 0.f, 0.f);
+    if (a.g_pos) gx = encode_dx<TT>(r.g, x.x, x.y, x.z, dz);
+    if (live) put_record(a.ws, r.g, R * p, x, dz);
     if (live && a.g_pos) {
         a.g_pos[3 * p] = gx.x + gxb.x;
         a.g_pos[3 * p + 1] = gx.y + gxb.y;
@@ -615,17 +581,31 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(const BwdK a) {
     }
 }
 
-// Table-gradient scatter at the bounce points, one lane per query in the
-// order of the Morton keys of x': a wave's 64 bounce points are then
-// neighbours, so the per-cell summation of scatter_cell merges their
-// contributions at all but the finest levels (in query order they come
-// from 64 random directions and merge only at the coarsest levels).
+// Table-gradient scatter, one lane per record in the order of the Morton
+// keys of the record points, so that a wave's 64 points are neighbours.  Per
+// level the wave sums its 64 x 8 corner contributions by table entry in a
+// wave-private LDS hash table (open addressing, LDS compare-and-swap on the
+// key, LDS float adds on the two features) and then issues one global
+// atomic per entry and feature: adjacent cells share corners, so this
+// merges more than summing per cell, and the global FP32 atomic add costs
+// the same per lane whatever the addresses, so their count is the cost.
 constexpr int kScatterThreads = 256;
+constexpr int kHashSlots = 1024;  // >= 2 x the 512 corner entries of a wave and level
+constexpr uint32_t kEmptySlot = 0xffffffffu;
 template <typename TT>
-__global__ __launch_bounds__(kScatterThreads) void k_scatter_bounce(const GridK g, const uint32_t *__restrict__ id,
-                                                                    const float4 *__restrict__ xb,
-                                                                    const float *__restrict__ gf,
-                                                                    float *__restrict__ g_table, int64_t n) {
+__global__ __launch_bounds__(kScatterThreads) void k_scatter_records(const GridK g, const uint32_t *__restrict__ id,
+                                                                     const float4 *__restrict__ xb,
+                                                                     const float *__restrict__ gf,
+                                                                     float *__restrict__ g_table, int64_t n) {
+    __shared__ uint32_t hkey[kScatterThreads / 64][kHashSlots];
+    __shared__ float2 hval[kScatterThreads / 64][kHashSlots];
+    const int lane = threadIdx.x & 63;
+    uint32_t *K = hkey[threadIdx.x >> 6];
+    float2 *V = hval[threadIdx.x >> 6];
+    for (int q = lane; q < kHashSlots; q += 64) {
+        K[q] = kEmptySlot;
+        V[q] = make_float2(0.0f, 0.0f);
+    }
     const int64_t i = (int64_t)blockIdx.x * kScatterThreads + threadIdx.x;
     const bool live = i < n;
     const uint32_t p = id[live ? i : n - 1];
@@ -643,63 +623,97 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter_bounce(const GridK 
     float u[3];
     bool in[3];
     pos_to_u(g, x.x, x.y, x.z, u, in);
-#pragma unroll
+    wave_sync();
+#pragma unroll 1
     for (int l = 0; l < kL; ++l) {
         if (l >= (int)g.L) break;  // wave-uniform
-        uint32_t c[3];
-        float w[3];
+        if (live) {
+            uint32_t c[3];
+            float w[3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) cell_of(u[d], g.resf[l], g.nm1f[l], c[d], w[d]);
-        uint32_t idx[8];
-        corner_idx(g, l, c, idx);
-        const float w0[3] = {1.0f - w[0], 1.0f - w[1], 1.0f - w[2]};
-        float v[16];
+            for (int d = 0; d < 3; ++d) cell_of(u[d], g.resf[l], g.nm1f[l], c[d], w[d]);
+            uint32_t idx[8];
+            corner_idx(g, l, c, idx);
+            const float w0[3] = {1.0f - w[0], 1.0f - w[1], 1.0f - w[2]};
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const float wt = ((k & 1) ? w[0] : w0[0]) * (((k >> 1) & 1) ? w[1] : w0[1]) * (((k >> 2) & 1) ? w[2] : w0[2]);
-            v[2 * k] = wt * gfp[2 * l];
-            v[2 * k + 1] = wt * gfp[2 * l + 1];
+            for (int k = 0; k < 8; ++k) {
+                const float wt =
+                    ((k & 1) ? w[0] : w0[0]) * (((k >> 1) & 1) ? w[1] : w0[1]) * (((k >> 2) & 1) ? w[2] : w0[2]);
+                const uint32_t e = idx[k];
+                uint32_t h = (e * 2654435761u) >> (32 - 10);
+                // at most 512 distinct keys in 1024 slots: the probe ends
+                while (true) {
+                    const uint32_t prev = atomicCAS(&K[h], kEmptySlot, e);
+                    if (prev == kEmptySlot || prev == e) break;
+                    h = (h + 1) & (kHashSlots - 1);
+                }
+                atomicAdd(&V[h].x, wt * gfp[2 * l]);
+                atomicAdd(&V[h].y, wt * gfp[2 * l + 1]);
+            }
         }
-        scatter_cell(g_table + 2 * ((size_t)l << g.log2T), idx, c, v, live, (int)(threadIdx.x & 63));
+        wave_sync();
+        float *gl = g_table + 2 * ((size_t)l << g.log2T);
+        for (int q = lane; q < kHashSlots; q += 64) {
+            const uint32_t e = K[q];
+            if (e != kEmptySlot) {
+                const float2 a = V[q];
+                atomic_addf(gl + 2 * (size_t)e, a.x);
+                atomic_addf(gl + 2 * (size_t)e + 1, a.y);
+                K[q] = kEmptySlot;
+                V[q] = make_float2(0.0f, 0.0f);
+            }
+        }
+        wave_sync();
     }
 }
 
-hipError_t bounce_sort_bytes(int64_t n, size_t &bytes) {
+hipError_t backward_sort_bytes(int64_t records, size_t &bytes) {
     bytes = 0;
     return hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint32_t *)nullptr, (uint32_t *)nullptr,
-                                              (const uint32_t *)nullptr, (uint32_t *)nullptr, (int)n, 0, 30,
+                                              (const uint32_t *)nullptr, (uint32_t *)nullptr, (int)records, 0, 30,
                                               (hipStream_t)0);
 }
 
+// The per-query kernel, then the sort of its records by Morton key and the
+// table scatter, all on the caller's stream.  (A pipeline over chunks of
+// queries with the scatter on a second stream measured slower: the two
+// kernels slowed each other down and the scatter side became the critical
+// path, 7.5 against 7.0 ms at 2^18 queries.)
 hipError_t launch_backward(const BwdK &a, bool f16, bool indirect, hipStream_t s) {
-    const unsigned blocks = (unsigned)((a.r.n + kBwdThreads - 1) / kBwdThreads);
+    const int64_t n = a.r.n;
+    const int R = indirect ? 2 : 1;
     const size_t lds = (size_t)(kBwdThreads / 64) * kWaveLds * sizeof(float);
+    BwdK c = a;
+    c.p_begin = 0;
+    c.p_end = n;
+    const unsigned blocks = (unsigned)((n + kBwdThreads - 1) / kBwdThreads);
     if (f16) {
-        if (indirect) hipLaunchKernelGGL((k_backward<__half, true>), dim3(blocks), dim3(kBwdThreads), lds, s, a);
-        else hipLaunchKernelGGL((k_backward<__half, false>), dim3(blocks), dim3(kBwdThreads), lds, s, a);
+        if (indirect) hipLaunchKernelGGL((k_backward<__half, true>), dim3(blocks), dim3(kBwdThreads), lds, s, c);
+        else hipLaunchKernelGGL((k_backward<__half, false>), dim3(blocks), dim3(kBwdThreads), lds, s, c);
     } else {
-        if (indirect) hipLaunchKernelGGL((k_backward<float, true>), dim3(blocks), dim3(kBwdThreads), lds, s, a);
-        else hipLaunchKernelGGL((k_backward<float, false>), dim3(blocks), dim3(kBwdThreads), lds, s, a);
+        if (indirect) hipLaunchKernelGGL((k_backward<float, true>), dim3(blocks), dim3(kBwdThreads), lds, s, c);
+        else hipLaunchKernelGGL((k_backward<float, false>), dim3(blocks), dim3(kBwdThreads), lds, s, c);
     }
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !indirect) return e;
+    if (e != hipSuccess) return e;
+    const int64_t rn = R * n;
     size_t tmp = a.ws.sort_tmp_bytes;
     e = hipcub::DeviceRadixSort::SortPairs(a.ws.sort_tmp, tmp, a.ws.key, a.ws.key_sorted, a.ws.id, a.ws.id_sorted,
-                                           (int)a.r.n, 0, 30, s);
+                                           (int)rn, 0, 30, s);
     if (e != hipSuccess) return e;
-    const unsigned sb = (unsigned)((a.r.n + kScatterThreads - 1) / kScatterThreads);
+    const unsigned sb = (unsigned)((rn + kScatterThreads - 1) / kScatterThreads);
     if (f16)
-        hipLaunchKernelGGL(k_scatter_bounce<__half>, dim3(sb), dim3(kScatterThreads), 0, s, a.r.g, a.ws.id_sorted,
-                           a.ws.xb, a.ws.gf, a.g_table, a.r.n);
+        hipLaunchKernelGGL(k_scatter_records<__half>, dim3(sb), dim3(kScatterThreads), 0, s, a.r.g, a.ws.id_sorted,
+                           a.ws.xb, a.ws.gf, a.g_table, rn);
     else
-        hipLaunchKernelGGL(k_scatter_bounce<float>, dim3(sb), dim3(kScatterThreads), 0, s, a.r.g, a.ws.id_sorted,
-                           a.ws.xb, a.ws.gf, a.g_table, a.r.n);
+        hipLaunchKernelGGL(k_scatter_records<float>, dim3(sb), dim3(kScatterThreads), 0, s, a.r.g, a.ws.id_sorted,
+                           a.ws.xb, a.ws.gf, a.g_table, rn);
     return hipGetLastError();
 }
 
-size_t bounce_ws_layout(int64_t n, size_t sort_tmp_bytes, void *base, BounceWs *ws) {
+size_t backward_ws_layout(int64_t n, int R, size_t sort_tmp_bytes, void *base, BounceWs *ws) {
     auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
-    const size_t un = (size_t)n;
+    const size_t un = (size_t)n * (size_t)R;
     size_t off = 0;
     const size_t o_xb = off;
     off += al(un * sizeof(float4));

@@ -35,14 +35,15 @@ inline hipError_t current_device_cus(int &out) {
     return hipSuccess;
 }
 
-// Workspace of the indirect backward: per query its bounce point, the
+// Workspace of the backward: one record per encoding the loss depends on
+// (R = 2 per query with the bounce: x and x'; 1 without): the point, the
 // gradient of the loss with respect to the features there, and a Morton key
-// of the bounce point with the query's id (and their sorted copies), so that
-// the table scatter at the bounce points runs in spatial order.
+// of the point with the record's id (and their sorted copies), so that the
+// table scatter runs in spatial order, decoupled from the per-query work.
 struct BounceWs {
-    float4 *xb;        // [n] bounce point (w unused)
-    float *gf;         // [n][kNF] d loss / d f(x')
-    uint32_t *key, *id;          // [n] Morton key of x', query id
+    float4 *xb;        // [R n] point (w unused)
+    float *gf;         // [R n][kNF] d loss / d f(point)
+    uint32_t *key, *id;          // [R n] Morton key, record id
     uint32_t *key_sorted, *id_sorted;
     void *sort_tmp;
     size_t sort_tmp_bytes;
@@ -56,13 +57,15 @@ struct BwdK {
     float *gi[6];
     float *g_pos;
     BounceWs ws;
+    int64_t p_begin, p_end;  // the queries [p_begin, p_end) of this launch
 };
 
-// Layout of the indirect backward's workspace for n queries inside `base`
-// (sort_tmp_bytes: what the radix sort needs); returns the bytes used.
-size_t bounce_ws_layout(int64_t n, size_t sort_tmp_bytes, void *base, BounceWs *ws);
-// Temporary bytes the radix sort of n keys needs (a host query).
-hipError_t bounce_sort_bytes(int64_t n, size_t &bytes);
+// Layout of the backward's workspace for n queries with R records each
+// inside `base` (sort_tmp_bytes: what the radix sort of the R n keys needs);
+// returns the bytes used.
+size_t backward_ws_layout(int64_t n, int R, size_t sort_tmp_bytes, void *base, BounceWs *ws);
+// Temporary bytes the radix sort of `records` keys needs (a host query).
+hipError_t backward_sort_bytes(int64_t records, size_t &bytes);
 
 hipError_t launch_encode(const GridK &g, bool f16, const float *pos, int64_t n, float *feat, hipStream_t s);
 hipError_t launch_encode_index(const GridK &g, const float *pos, int64_t n, uint32_t *idx, float *w, hipStream_t s);

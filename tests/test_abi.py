@@ -215,15 +215,14 @@ def test_other_entry_points_validate():
 
 
 def test_backward_workspace():
-    """The indirect backward needs a workspace of at least the queried size,
-    256-byte aligned; the direct one needs none."""
+    """The backward needs a workspace of at least the queried size, 256-byte
+    aligned (two records per query with the bounce, one without)."""
     L = hg.lib()
-    assert L.hg_backward_workspace_size(0, 1000) == 0
     assert L.hg_backward_workspace_size(1, 0) == 0 and L.hg_backward_workspace_size(1, -3) == 0
-    assert L.hg_backward_workspace_size(1, 1 << 31) == 0
+    assert L.hg_backward_workspace_size(1, 1 << 30) == 0 and L.hg_backward_workspace_size(2, 1000) == 0
     n = 1000
     need = L.hg_backward_workspace_size(1, n)
-    assert need >= n * (16 + 128 + 16)
+    assert need >= 2 * n * (16 + 128 + 16) and L.hg_backward_workspace_size(0, n) >= n * (16 + 128 + 16)
     m = fake_model()
     env = hg.Env(); env.H, env.W, env.rgb = 16, 32, FAKE
     s = hg.sampling_struct(1, 8, 7, 0)
