@@ -158,7 +158,7 @@ def output_errors(args, cfg, model, env, pos, nrm, wo, sub, oracle_out, O, H, hg
     tgt = t(H.make_targets(nb))
     om = O.OracleModel(model, H.BOX_LO, H.BOX_EXTENT)
     oe = O.OracleEnv(env)
-    for fwd, bwd in (("fp32", "fp32"), ("mixed", "f16table")):
+    for fwd, bwd in (("fp32", "fp32"), ("mixed", "mixed")):
         rgb_, vis_, dep_ = hg.render(re_, env_t, t(bp), dirs=t(bd), precision=fwd)
         _, g_rgb, g_vis, g_dep = hg.l2_loss(rgb_, vis_, dep_, tgt)
         grads = hg.zero_grads(re_)
@@ -475,9 +475,9 @@ def main():
         atomic_ceiling = MB.atomic(64 << 20, 1)
         _, out["train"]["roofline"] = backward_roofline("fp32")
 
-        # mixed-precision step: forward with FP16 tables and BF16 MLPs on the
-        # matrix cores, backward gathering the FP16 tables with the FP32 master
-        # MLPs, Adam on the FP32 masters refreshing the FP16/BF16 shadows
+        # mixed-precision step: forward and backward with FP16 tables and BF16
+        # MLPs on the matrix cores (FP32 accumulation, FP32 master gradients),
+        # Adam on the FP32 masters refreshing the FP16/BF16 shadows
         r.refresh_shadows()
         shadows = [r.table16] + [r.brdf16[i] if i % 2 == 0 else None for i in range(6)] + \
                   [r.irt16[i] if i % 2 == 0 else None for i in range(6)]
@@ -490,7 +490,7 @@ def main():
                 g.zero_()
             rgb_, vis_, dep_ = hg.render(r, env_t, sp, dirs=sd, precision="mixed")
             loss, g_rgb, g_vis, g_dep = hg.l2_loss(rgb_, vis_, dep_, st)
-            hg.backward(r, env_t, sp, sd, g_rgb, g_vis, g_dep, grads, precision="f16table")
+            hg.backward(r, env_t, sp, sd, g_rgb, g_vis, g_dep, grads, precision="mixed")
             for i, (p_, g_) in enumerate(zip(params, gl)):
                 hg.adam_step(p_, g_, ms_[i], vs_[i], step[0], lr=2e-3, weight_decay=0.0 if i == 0 else 1e-6,
                              shadow=shadows[i])
@@ -498,8 +498,8 @@ def main():
 
         mstm, _, _ = time_events(train_step_mixed, max(5, args.steps), 2, torch)
         out["train"]["mixed"] = {"samples_per_s": B / (mstm * 1e-3), "ms_per_step": mstm,
-                                 "dtype": "bf16-mfma fwd / f16-table bwd / f32 masters"}
-        _, out["train"]["mixed"]["roofline"] = backward_roofline("f16table")
+                                 "dtype": "bf16-mfma fwd+bwd / f16 tables / f32 masters and gradients"}
+        _, out["train"]["mixed"]["roofline"] = backward_roofline("mixed")
         out["train"]["random_atomic_ceiling"] = atomic_ceiling
         del bp_t, bd_t, tgt
 

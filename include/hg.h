@@ -209,8 +209,9 @@ hg_status hg_render_indirect(const hg_model *model, const hg_env *env, const hg_
 /* Workspace bytes hg_backward needs for n queries: per encoding the loss
  * depends on (x, and with the bounce also x') one record of 160 bytes
  * (the point, the feature gradient there, a sort key and an index, and
- * their sorted copies), plus the radix sort's temporary storage.  0 for
- * n <= 0, n >= 2^30 or indirect not 0/1. */
+ * their sorted copies), plus the radix sort's temporary storage and the
+ * BF16 weight tiles of the mixed backward (66 KiB).  0 for n <= 0,
+ * n >= 2^30 or indirect not 0/1. */
 size_t hg_backward_workspace_size(int32_t indirect, int64_t n);
 
 /* Backward of query mode (the distillation forward, Sec. 3.3), with the
@@ -221,15 +222,19 @@ size_t hg_backward_workspace_size(int32_t indirect, int64_t n);
  *   g_brdf[6], g_irt[6]: FP32 W0,b0,W1,b1,W2,b2 of decoder and tracer,
  * and WRITES d/dpos into g_pos [n][3] if it is not NULL.
  * indirect selects the query mode of hg_render_indirect (1) or
- * hg_render_direct (0).  MLP weights must be FP32 (the masters); the table
- * may be FP32 or FP16.  Accumulation order of the atomics is unspecified.
+ * hg_render_direct (0).  Precisions (table, MLP weights): (FP32, FP32);
+ * (FP16, FP32): the FP32 MLP arithmetic on FP16 tables; (FP16, BF16): the
+ * mixed path, the MLP products in BF16 on the matrix cores with FP32
+ * accumulation (weights the BF16 shadows, activations and deltas packed to
+ * BF16), the gradient arrays FP32 in every case.  Biases are FP32 in all.
+ * Accumulation order of the atomics is unspecified.
  * ws: device workspace of at least hg_backward_workspace_size(indirect, n)
  * bytes, 256-byte aligned; its contents on entry are ignored.  The table
  * gradient is scattered after sorting the encodings' points by a Morton
  * key, so that a wave's contributions share cells and merge before the
- * atomics (all of it on `stream`).  Errors: HG_E_INVALID for a missing, misaligned or small workspace;
- * HG_E_WORKSPACE if the sort would need more temporary storage than the
- * size query reserved. */
+ * atomics (all of it on `stream`).  Errors: HG_E_INVALID for a missing,
+ * misaligned or small workspace; HG_E_WORKSPACE if the sort would need more
+ * temporary storage than the size query reserved. */
 hg_status hg_backward(const hg_model *model, const hg_env *env, const hg_sampling *samp,
                       const hg_points *pts, int32_t indirect, const float *g_rgb,
                       const float *g_vis, const float *g_depth, float *g_table,

@@ -422,5 +422,5 @@ class HGQueryFn(torch.autograd.Function):
         z = lambda t, shape: torch.zeros(shape, device=pos.device) if t is None else t.contiguous()
         backward(r, ctx.env, pos, dirs, z(g_rgb, (pos.shape[0], 3)), z(g_vis, (pos.shape[0],)),
                  z(g_dep, (pos.shape[0],)), grads, n_dirs2=n_dirs2, seed=seed, indirect=indirect,
-                 precision="fp32" if precision == "fp32" else "f16table")
+                 precision=precision)
         return (None, None, None, None, None, None, None, None, grads["table"], *grads["brdf"], *grads["irt"])

@@ -328,7 +328,6 @@ hg_status hg_backward(const hg_model *model, const hg_env *env, const hg_samplin
     CHECK(check_points(pts, query));
     REQUIRE(query || pts->n == 0, "hg_backward needs query-mode points (dir != NULL)");
     CHECK(check_sampling(samp, false, k.r.s));
-    SUPPORT(prec != Prec::Mixed, "hg_backward needs FP32 MLP weights (the masters)");
     SUPPORT((samp->flags & (HG_HARD_VIS | HG_MIS)) == 0, "hard visibility and MIS are forward-only modes");
     SUPPORT(model->brdf.n_out == 5, "the decoder's normal head is forward-only (hg_backward needs n_out = 5)");
     REQUIRE(indirect == 0 || indirect == 1, "indirect must be 0 or 1");
@@ -370,7 +369,8 @@ hg_status hg_backward(const hg_model *model, const hg_env *env, const hg_samplin
             return fail(HG_E_WORKSPACE, "sort needs %zu bytes, above the reserved %zu", tmp, sort_bound(rec));
         hg::backward_ws_layout(pts->n, R, sort_bound(rec), ws, &k.ws);
     }
-    return hip_status(hg::launch_backward(k, model->grid.dtype == HG_F16, indirect != 0, stream), "hg_backward");
+    return hip_status(hg::launch_backward(k, model->grid.dtype == HG_F16, prec == Prec::Mixed, indirect != 0, stream),
+                      "hg_backward");
 }
 
 hg_status hg_l2_loss(const float *rgb, const float *vis, const float *depth, const float *tgt, int64_t n,

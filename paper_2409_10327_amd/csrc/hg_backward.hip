@@ -295,6 +295,29 @@ __device__ __forceinline__ void mlp_bwd_stored(const MlpK &m, float *const *gp, 
     for (int i = 0; i < kNF; ++i) dz[i] = h1buf[lane * kHS + i];
 }
 
+// The FP32 MLP functions behind the interface the kernel body calls (the
+// BF16 ones are in hg_bwd_bf16.h): per-wave LDS = two activation buffers and
+// the delta rows; the state kept from forward to backward is the lane's own
+// last hidden layer.
+struct F32Mlp {
+    static constexpr int kLdsBytes = kWaveLds * (int)sizeof(float);
+    struct State {
+        float h[kH];
+    };
+    template <int NIN, int NOUT, int W>
+    static __device__ void fwd(const MlpK &m, const uint4 *, uint8_t *lds, const float (&z)[NIN], bool, State &st,
+                               float (&out)[NOUT], int lane) {
+        float *h1 = reinterpret_cast<float *>(lds);
+        mlp_fwd_mma<NIN, NOUT>(m, z, h1, h1 + kHBuf, lane, st.h, out);
+    }
+    template <int NIN, int NOUT, int W>
+    static __device__ void bwd(const MlpK &m, const uint4 *, uint8_t *lds, float *const *gp, const float (&z)[NIN],
+                               const float (&gout)[NOUT], bool, State &st, float (&dz)[kNF], int lane) {
+        float *h1 = reinterpret_cast<float *>(lds);
+        mlp_bwd_stored<NIN, NOUT>(m, gp, z, gout, st.h, h1, h1 + kHBuf, h1 + 2 * kHBuf, lane, dz);
+    }
+};
+
 // Forward recompute plus backward of one MLP evaluation (see mlp_bwd_stored).
 template <int NIN, int NOUT>
 __device__ __forceinline__ void mlp_bwd_wave(const MlpK &m, float *const *gp, const float (&z)[NIN],
@@ -421,6 +444,12 @@ __device__ __forceinline__ void put_record(const BounceWs &ws, const GridK &g, i
     ws.id[rec] = (uint32_t)rec;
 }
 
+}  // namespace hg
+
+#include "hg_bwd_bf16.h"
+
+namespace hg {
+
 // pi f_r and its derivatives with respect to albedo (per channel),
 // roughness and metallic.
 struct BrdfGrad {
@@ -462,13 +491,16 @@ __device__ __forceinline__ BrdfGrad pi_brdf_grad(float3 n, float3 v, float3 l, f
     return o;
 }
 
-template <typename TT, bool INDIRECT>
+// One query per lane; MLP = F32Mlp (FP32 matrix cores) or Bf16Mlp (BF16
+// matrix cores, FP32 accumulation).  The features last staged for the MLPs
+// (flags "new_x" below) are f(x) after the first tracer call, f(x') from the
+// decoder at x' through the bounce, and f(x) again for the final tracer.
+template <typename TT, bool INDIRECT, typename MLP>
 __global__ __launch_bounds__(kBwdThreads) void k_backward(const BwdK a) {
-    extern __shared__ float lds[];
+    extern __shared__ float lds_f[];
     const int lane = threadIdx.x & 63;
-    float *h1buf = lds + (threadIdx.x >> 6) * kWaveLds;
-    float *h2buf = h1buf + kHBuf;
-    float *del = h2buf + kHBuf;
+    uint8_t *lds = reinterpret_cast<uint8_t *>(lds_f) + (threadIdx.x >> 6) * MLP::kLdsBytes;
+    typename MLP::State st;
     const int64_t p_raw = a.p_begin + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const RenderK &r = a.r;
     const bool live = p_raw < a.p_end;
@@ -483,13 +515,14 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(const BwdK a) {
         gV = a.g_vis[p];
         gd = a.g_dep[p];
     }
-    float f[kNF];
-    encode<TT>(r.g, x.x, x.y, x.z, f);
-    float z[kNI], h[kH], o[2];
-#pragma unroll
-    for (int i = 0; i < kNF; ++i) z[i] = f[i];
+    // z = [features, direction] of the current tracer call; zf aliases its
+    // features (f(x), then f(x') through the bounce, then f(x) again,
+    // recomputed rather than kept live across the bounce)
+    float z[kNI], o[2];
+    float(&zf)[kNF] = *reinterpret_cast<float(*)[kNF]>(z);
+    encode<TT>(r.g, x.x, x.y, x.z, zf);
     z[kNF] = w.x; z[kNF + 1] = w.y; z[kNF + 2] = w.z;
-    mlp_fwd_mma<kNI, 2>(r.irt, z, h1buf, h1buf, lane, h, o);
+    MLP::template fwd<kNI, 2, 0>(r.irt, a.tiles, lds, z, true, st, o, lane);
     const float V = sigmoidf_(o[0]);
     const float o1p = o[1];
     const float sp = softplusf_(o1p);
@@ -500,10 +533,9 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(const BwdK a) {
     float dz[kNF];
     if constexpr (INDIRECT) {
         const float3 xb = make_float3(fmaf(t, w.x, x.x), fmaf(t, w.y, x.y), fmaf(t, w.z, x.z));
-        float fb[kNF];
-        encode<TT>(r.g, xb.x, xb.y, xb.z, fb);
+        encode<TT>(r.g, xb.x, xb.y, xb.z, zf);
         float ob[5];
-        mlp_fwd_mma<kNF, 5>(r.brdf, fb, h1buf, h1buf, lane, h, ob);
+        MLP::template fwd<kNF, 5, 1>(r.brdf, a.tiles, lds, zf, true, st, ob, lane);
         const float3 ab = make_float3(sigmoidf_(ob[0]), sigmoidf_(ob[1]), sigmoidf_(ob[2]));
         const float s3 = sigmoidf_(ob[3]);
         const float rb = 0.09f + 0.91f * s3;
@@ -513,8 +545,6 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(const BwdK a) {
         const bool diffuse = (r.s.flags & 1u) != 0;
         const uint32_t N2 = r.s.n_dirs2;
         const float invN2 = 1.0f / (float)N2;
-#pragma unroll
-        for (int i = 0; i < kNF; ++i) z[i] = fb[i];
         // one pass over the secondary directions: the forward of tracer j gives
         // V'_j for L'_o and, since d L / d V'_j needs only (1 - V) G, its
         // backward runs on the activations just computed
@@ -529,7 +559,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(const BwdK a) {
             if ((j & 3u) == 0) words = philox4x32_10((uint32_t)p, 0u, j >> 2, 1u, r.s.key0, r.s.key1);
             const float3 wj = sample_dir(pick4(words, j), j, r.s.nb2_shift, r.s.inv_na2, r.s.inv_nb2, fr);
             z[kNF] = wj.x; z[kNF + 1] = wj.y; z[kNF + 2] = wj.z;
-            mlp_fwd_mma<kNI, 2>(r.irt, z, h1buf, h2buf, lane, h, o);
+            MLP::template fwd<kNI, 2, 0>(r.irt, a.tiles, lds, z, false, st, o, lane);
             const float vj = sigmoidf_(o[0]);
             const float3 Ej = env_lookup(r.env, wj.x, wj.y, wj.z);
             const BrdfGrad bg = pi_brdf_grad(nb, nb, wj, ab, rb, mb, r.f0, diffuse);
@@ -538,7 +568,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(const BwdK a) {
             Lz = fmaf(bg.c.z * vj, Ej.z, Lz);
             const float gvj = (gLo.x * bg.c.x * Ej.x + gLo.y * bg.c.y * Ej.y + gLo.z * bg.c.z * Ej.z) * invN2;
             const float go[2] = {gvj * vj * (1.0f - vj), 0.0f};
-            mlp_bwd_stored<kNI, 2>(r.irt, a.gi, z, go, h, h1buf, h2buf, del, lane, dz);
+            MLP::template bwd<kNI, 2, 0>(r.irt, a.tiles, lds, a.gi, z, go, j == 0, st, dz, lane);
 #pragma unroll
             for (int i = 0; i < kNF; ++i) gfb[i] += dz[i];
             const float kx = gLo.x * vj * Ej.x * invN2, ky = gLo.y * vj * Ej.y * invN2, kz = gLo.z * vj * Ej.z * invN2;
@@ -552,7 +582,8 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(const BwdK a) {
         gV += G.x * (Le.x - Lx) + G.y * (Le.y - Ly) + G.z * (Le.z - Lz);
         const float gob[5] = {gax * ab.x * (1.0f - ab.x), gay * ab.y * (1.0f - ab.y), gaz * ab.z * (1.0f - ab.z),
                               gr * 0.91f * s3 * (1.0f - s3), gm * mb * (1.0f - mb)};
-        mlp_bwd_wave<kNF, 5>(r.brdf, a.gb, fb, gob, h1buf, h2buf, del, lane, dz);
+        MLP::template fwd<kNF, 5, 1>(r.brdf, a.tiles, lds, zf, false, st, ob, lane);
+        MLP::template bwd<kNF, 5, 1>(r.brdf, a.tiles, lds, a.gb, zf, gob, false, st, dz, lane);
 #pragma unroll
         for (int i = 0; i < kNF; ++i) gfb[i] += dz[i];
         // the table gradient at x' is scattered by k_scatter_records after the
@@ -565,11 +596,11 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(const BwdK a) {
         gV += G.x * Le.x + G.y * Le.y + G.z * Le.z;
     }
     // tracer at (f(x), w)
-#pragma unroll
-    for (int i = 0; i < kNF; ++i) z[i] = f[i];
+    if constexpr (INDIRECT) encode<TT>(r.g, x.x, x.y, x.z, zf);
     z[kNF] = w.x; z[kNF + 1] = w.y; z[kNF + 2] = w.z;
     const float go2[2] = {gV * V * (1.0f - V), sp < 1.0f ? gd * sigmoidf_(o1p) : 0.0f};
-    mlp_bwd_wave<kNI, 2>(r.irt, a.gi, z, go2, h1buf, h2buf, del, lane, dz);
+    MLP::template fwd<kNI, 2, 0>(r.irt, a.tiles, lds, z, INDIRECT, st, o, lane);
+    MLP::template bwd<kNI, 2, 0>(r.irt, a.tiles, lds, a.gi, z, go2, true, st, dz, lane);
     // the table gradient at x is scattered by k_scatter_records too
     float3 gx = make_float3(0.f, 0.f, 0.f);
     if (a.g_pos) gx = encode_dx<TT>(r.g, x.x, x.y, x.z, dz);
@@ -679,20 +710,28 @@ hipError_t backward_sort_bytes(int64_t records, size_t &bytes) {
 // queries with the scatter on a second stream measured slower: the two
 // kernels slowed each other down and the scatter side became the critical
 // path, 7.5 against 7.0 ms at 2^18 queries.)
-hipError_t launch_backward(const BwdK &a, bool f16, bool indirect, hipStream_t s) {
+template <typename TT, typename MLP>
+static void launch_k_backward(const BwdK &c, bool indirect, unsigned blocks, hipStream_t s) {
+    const size_t lds = (size_t)(kBwdThreads / 64) * MLP::kLdsBytes;
+    if (indirect) hipLaunchKernelGGL((k_backward<TT, true, MLP>), dim3(blocks), dim3(kBwdThreads), lds, s, c);
+    else hipLaunchKernelGGL((k_backward<TT, false, MLP>), dim3(blocks), dim3(kBwdThreads), lds, s, c);
+}
+
+hipError_t launch_backward(const BwdK &a, bool f16, bool bf16_mlp, bool indirect, hipStream_t s) {
     const int64_t n = a.r.n;
     const int R = indirect ? 2 : 1;
-    const size_t lds = (size_t)(kBwdThreads / 64) * kWaveLds * sizeof(float);
     BwdK c = a;
     c.p_begin = 0;
     c.p_end = n;
+    c.tiles = a.ws.tiles;
     const unsigned blocks = (unsigned)((n + kBwdThreads - 1) / kBwdThreads);
-    if (f16) {
-        if (indirect) hipLaunchKernelGGL((k_backward<__half, true>), dim3(blocks), dim3(kBwdThreads), lds, s, c);
-        else hipLaunchKernelGGL((k_backward<__half, false>), dim3(blocks), dim3(kBwdThreads), lds, s, c);
+    if (bf16_mlp) {
+        hipLaunchKernelGGL(k_bwd_tiles, dim3((BT_N * 64 + 255) / 256), dim3(256), 0, s, a.r.irt, a.r.brdf, a.ws.tiles);
+        launch_k_backward<__half, Bf16Mlp>(c, indirect, blocks, s);
+    } else if (f16) {
+        launch_k_backward<__half, F32Mlp>(c, indirect, blocks, s);
     } else {
-        if (indirect) hipLaunchKernelGGL((k_backward<float, true>), dim3(blocks), dim3(kBwdThreads), lds, s, c);
-        else hipLaunchKernelGGL((k_backward<float, false>), dim3(blocks), dim3(kBwdThreads), lds, s, c);
+        launch_k_backward<float, F32Mlp>(c, indirect, blocks, s);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -726,6 +765,8 @@ size_t backward_ws_layout(int64_t n, int R, size_t sort_tmp_bytes, void *base, B
     }
     const size_t o_tmp = off;
     off += al(sort_tmp_bytes);
+    const size_t o_tiles = off;
+    off += al((size_t)BT_N * 64 * sizeof(uint4));
     if (ws && base) {
         char *b = static_cast<char *>(base);
         ws->xb = reinterpret_cast<float4 *>(b + o_xb);
@@ -736,6 +777,7 @@ size_t backward_ws_layout(int64_t n, int R, size_t sort_tmp_bytes, void *base, B
         ws->id_sorted = reinterpret_cast<uint32_t *>(b + o_k[3]);
         ws->sort_tmp = b + o_tmp;
         ws->sort_tmp_bytes = sort_tmp_bytes;
+        ws->tiles = reinterpret_cast<uint4 *>(b + o_tiles);
     }
     return off;
 }

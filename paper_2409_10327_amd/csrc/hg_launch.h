@@ -47,6 +47,7 @@ struct BounceWs {
     uint32_t *key_sorted, *id_sorted;
     void *sort_tmp;
     size_t sort_tmp_bytes;
+    uint4 *tiles;      // BF16 weight tiles of the mixed MLP backward
 };
 
 struct BwdK {
@@ -58,6 +59,7 @@ struct BwdK {
     float *g_pos;
     BounceWs ws;
     int64_t p_begin, p_end;  // the queries [p_begin, p_end) of this launch
+    const uint4 *tiles;      // BF16 weight tiles (mixed MLPs), in the workspace
 };
 
 // Layout of the backward's workspace for n queries with R records each
@@ -72,7 +74,7 @@ hipError_t launch_encode_index(const GridK &g, const float *pos, int64_t n, uint
 hipError_t launch_render_f32_shade(const RenderK &a, bool indirect, hipStream_t s);
 hipError_t launch_render_f32_mma(const RenderK &a, bool indirect, bool query, hipStream_t s);
 hipError_t launch_render_mixed(const RenderK &a, bool indirect, bool query, hipStream_t s);
-hipError_t launch_backward(const BwdK &a, bool f16, bool indirect, hipStream_t s);
+hipError_t launch_backward(const BwdK &a, bool f16, bool bf16_mlp, bool indirect, hipStream_t s);
 hipError_t launch_l2_loss(const float *rgb, const float *vis, const float *dep, const float *tgt, int64_t n,
                           float *loss, float *g_rgb, float *g_vis, float *g_dep, hipStream_t s);
 size_t denoise_workspace_floats(int H, int W);

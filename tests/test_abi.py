@@ -208,10 +208,17 @@ def test_other_entry_points_validate():
     sh = hg.sampling_struct(1, 8, 7, hg.HG_HARD_VIS)   # hard visibility is forward-only
     assert L.hg_backward(C.byref(m), C.byref(env), C.byref(sh), C.byref(p), 1, C.c_void_p(FAKE), C.c_void_p(FAKE),
                          C.c_void_p(FAKE), C.c_void_p(FAKE), gb, gb, None, None, 0, None) == hg.HG_E_UNSUPPORTED
+    # BF16 MLPs with FP16 tables (the mixed backward) pass the dtype checks:
+    # without a workspace the call then stops at the workspace check
     m.brdf.dtype = m.irt.dtype = hg.HG_BF16
     m.grid.dtype = hg.HG_F16
     assert L.hg_backward(C.byref(m), C.byref(env), C.byref(s), C.byref(p), 1, C.c_void_p(FAKE), C.c_void_p(FAKE),
-                         C.c_void_p(FAKE), C.c_void_p(FAKE), gb, gb, None, None, 0, None) == hg.HG_E_UNSUPPORTED
+                         C.c_void_p(FAKE), C.c_void_p(FAKE), gb, gb, None, None, 0, None) == hg.HG_E_INVALID
+    assert "ws" in L.hg_last_error().decode()
+    # BF16 MLPs with an FP32 table are no supported pair
+    m.grid.dtype = hg.HG_F32
+    assert L.hg_backward(C.byref(m), C.byref(env), C.byref(s), C.byref(p), 1, C.c_void_p(FAKE), C.c_void_p(FAKE),
+                         C.c_void_p(FAKE), C.c_void_p(FAKE), gb, gb, None, None, 0, None) != hg.HG_OK
 
 
 def test_backward_workspace():

@@ -252,3 +252,54 @@ def test_backward_parity_spatially_sorted_batch(setup, indirect):
             e = relerr(grads[k][i].cpu().numpy(), ref[k][i])
             print(f"{k}[{i}]: rel err {e:.3g}, kappa {kappa[(k, i)]:.3g}, bar {bar:.3g}")
             assert e < bar, (k, i, e, bar)
+
+
+def _cos(a, b):
+    a, b = np.asarray(a, np.float64).ravel(), np.asarray(b, np.float64).ravel()
+    return float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+
+
+@pytest.mark.parametrize("indirect", [True, False])
+@pytest.mark.parametrize("n", [77, 1030])
+def test_backward_bf16_parity(setup, indirect, n):
+    """BF16 matrix-core backward of the mixed MLPs (FP16 tables, BF16
+    weights, activations and deltas, FP32 accumulation and gradients) against
+    the FP64 oracle on the FP32 masters.  BF16 keeps 8 significand bits, so a
+    per-sample gradient term carries ~2^-8 relative rounding, and a gradient
+    array (a sum over samples with random upstream gradients) moves by that
+    times its cancellation, and a pre-activation within BF16 rounding of zero
+    can flip its ReLU mask against FP64 (with few samples a few flips weigh
+    more): measured 4e-5 .. 0.2 norm-wise at c1 (about 8x the FP16-table
+    backward's error, as the 3 fewer significand bits give; the first layer
+    and the table at 77 samples the worst), cosines 0.983 and above.  A
+    mapping mistake (a transposed tile, a missing ReLU mask, a shifted bias
+    or direction column) would turn an array away from the oracle's instead:
+    every array, and the tracer's direction columns on their own, must keep a
+    cosine of at least 0.97 with it and a relative error of at most 0.3."""
+    print(f"case: BF16 backward indirect={indirect} n={n}", flush=True)
+    t = setup["t"]
+    r = setup["r"]
+    r.refresh_shadows()
+    pos, dirs = H.make_train_batch(n, seed=23)
+    rng = np.random.default_rng(6)
+    g_rgb = rng.standard_normal((n, 3)).astype(np.float32)
+    g_vis = rng.standard_normal(n).astype(np.float32)
+    g_dep = rng.standard_normal(n).astype(np.float32)
+    grads = hg.zero_grads(r)
+    hg.backward(r, setup["env_t"], t(pos), t(dirs), t(g_rgb), t(g_vis), t(g_dep), grads, indirect=indirect,
+                precision="mixed")
+    ref = O.backward(setup["om"], setup["oe"], O.sampling(1, 8, 7, 0), pos, dirs, g_rgb, g_vis, g_dep,
+                     indirect=indirect)
+    pairs = [("table", grads["table"].cpu().numpy(), ref["table"])]
+    for k in ("brdf", "irt"):
+        for i in range(6):
+            pairs.append((f"{k}{i}", grads[k][i].cpu().numpy(), ref[k][i]))
+    pairs.append(("irt0 direction columns", grads["irt"][0].cpu().numpy()[:, 32:], ref["irt"][0][:, 32:]))
+    for name, a, b in pairs:
+        if not indirect and name.startswith("brdf"):
+            assert np.all(a == 0) and np.all(b == 0), name
+            continue
+        e, c = relerr(a, b), _cos(a, b)
+        print(f"  {name}: rel {e:.3g} cos {c:.5f}")
+        assert np.all(np.isfinite(a)), name
+        assert c >= 0.97 and e <= 0.3, (name, e, c)
