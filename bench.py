@@ -71,12 +71,12 @@ def parse():
     return ap.parse_args()
 
 
-def measured_traffic(img, n_dirs):
-    """HBM-side bytes per launch of the headline kernel, from the committed
-    FETCH_SIZE/WRITE_SIZE summary (copy-calibrated); None if the workload
-    differs or the kernel sources changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "k_render_mma_f32_frame800_n128_traffic.txt")
-    if img != 800 or n_dirs != 128 or not os.path.exists(path):
+def profile_value(name, key):
+    """A figure from a committed rocprofv3 summary profiles/<name>.txt (its
+    `key: value` lines); None if the file is missing or the kernel sources it
+    lists changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", name + ".txt")
+    if not os.path.exists(path):
         return None
     kv = {}
     for line in open(path):
@@ -90,9 +90,31 @@ def measured_traffic(img, n_dirs):
                 h.update(fh.read())
         if h.hexdigest() != kv["source_sha256"]:
             return None
-        return float(kv["traffic_bytes_per_launch"])
+        return float(kv[key])
     except (KeyError, OSError, ValueError):
         return None
+
+
+def measured_traffic(img, n_dirs):
+    """HBM-side bytes per launch of the headline kernel, from the committed
+    FETCH_SIZE/WRITE_SIZE summary (copy-calibrated); None if the workload
+    differs or the kernel sources changed since the counters were taken."""
+    if img != 800 or n_dirs != 128:
+        return None
+    return profile_value("k_render_mma_f32_frame800_n128_traffic", "traffic_bytes_per_launch")
+
+
+def issued_backward_atomics(precision, batch):
+    """Lane atomics one backward call issues (k_backward's MLP-gradient flushes
+    plus k_scatter_records' merged table-gradient adds), counted with
+    TCP_TCC_ATOMIC_WITHOUT_RET_REQ on the 2^18-sample training batch; None for
+    another batch or stale counters."""
+    if batch != 262144:
+        return None
+    names = (("k_backward_f32_train262144", "k_scatter_records_f32_train262144") if precision == "fp32" else
+             ("k_backward_bf16_train262144", "k_scatter_records_f16_train262144"))
+    v = [profile_value(n, "issued_atomics_per_launch") for n in names]
+    return None if None in v else {"k_backward": v[0], "k_scatter_records": v[1]}
 
 
 def _rel(a, b):
@@ -451,9 +473,14 @@ def main():
                         "secondary_queries_per_s_fwd_bwd": B / (mst * 1e-3), "dtype": "f32"}
 
         def backward_roofline(precision):
-            """Time the backward alone (the step's dominant kernel) on one
-            Morton-ordered batch; roofline against the measured random FP32
-            atomic rate (the table scatter) and the matrix-core peak."""
+            """Time the backward call alone (k_backward, the record sort and
+            k_scatter_records) on one Morton-ordered batch.  Its binding
+            resource is the FP32 atomic adds, which the hardware executes past
+            the L2 at a rate that does not depend on addresses: the roofline
+            is the atomics it issues (counted by rocprofv3) over the measured
+            random-atomic rate.  The 512 table-gradient adds per sample of the
+            definition are merged in LDS before they are issued, so they are
+            reported beside it, not as the achieved rate."""
             order = morton_order(bp_t)
             sp, sd, st = bp_t[order], bd_t[order], tgt[order]
             fwd_prec = "fp32" if precision == "fp32" else "mixed"
@@ -463,17 +490,31 @@ def main():
             def bwd():
                 hg.backward(r, env_t, sp, sd, g_rgb, g_vis, g_dep, grads, precision=precision)
             msb, _, _ = time_events(bwd, max(5, args.steps), 1, torch)
-            at = ATOMICS_PER_SAMPLE * B / (msb * 1e-3)
+            issued = issued_backward_atomics(precision, B)
+            ceil = atomic_ceiling["lane_atomics_per_s"]
+            rate = None if issued is None else sum(issued.values()) / (msb * 1e-3)
+            mfma_peak = FP32_MFMA_PEAK_TFLOPS if precision == "fp32" else BF16_MFMA_PEAK_TFLOPS
             fl = BWD_FLOP_PER_SAMPLE * B / (msb * 1e-3) / 1e12
-            return msb, {"bound": "atomics", "kernel": "k_backward (query mode, indirect)", "ms": msb,
-                         "achieved": at, "peak": atomic_ceiling["lane_atomics_per_s"], "unit": "FP32 atomics/s",
-                         "frac": at / atomic_ceiling["lane_atomics_per_s"],
-                         "peak_kind": "measured random FP32 atomic adds over 64 MiB",
-                         "mfma": {"achieved": fl, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                                  "frac": fl / FP32_MFMA_PEAK_TFLOPS}}
+            return msb, {"bound": "atomics", "kernel": "backward call: k_backward + record sort + k_scatter_records",
+                         "ms": msb, "achieved": rate, "peak": ceil, "unit": "FP32 lane atomics/s",
+                         "frac": None if rate is None else rate / ceil,
+                         "peak_kind": "measured random FP32 atomic adds over 64 MiB (hgmb_atomic)",
+                         "issued_atomics_per_launch": issued,
+                         "table_adds_before_merging_per_launch": ATOMICS_PER_SAMPLE * B,
+                         "mfma": {"achieved": fl, "peak": mfma_peak, "unit": "TFLOP/s", "frac": fl / mfma_peak}}
+
+        def step_mfma(ms_step, precision):
+            # the whole training step's matrix work (forward + backward per
+            # sample) against the matrix-core peak of the MLP precision
+            peak = FP32_MFMA_PEAK_TFLOPS if precision == "fp32" else BF16_MFMA_PEAK_TFLOPS
+            fl = (FLOP_PER_QUERY + BWD_FLOP_PER_SAMPLE) * B / (ms_step * 1e-3) / 1e12
+            return {"bound": "mfma", "flop_per_sample": FLOP_PER_QUERY + BWD_FLOP_PER_SAMPLE, "achieved": fl,
+                    "peak": peak, "unit": "TFLOP/s", "frac": fl / peak}
+
         from paper_2409_10327_amd import membench as MB
         atomic_ceiling = MB.atomic(64 << 20, 1)
         _, out["train"]["roofline"] = backward_roofline("fp32")
+        out["train"]["step_roofline"] = step_mfma(mst, "fp32")
 
         # mixed-precision step: forward and backward with FP16 tables and BF16
         # MLPs on the matrix cores (FP32 accumulation, FP32 master gradients),
@@ -500,6 +541,7 @@ def main():
         out["train"]["mixed"] = {"samples_per_s": B / (mstm * 1e-3), "ms_per_step": mstm,
                                  "dtype": "bf16-mfma fwd+bwd / f16 tables / f32 masters and gradients"}
         _, out["train"]["mixed"]["roofline"] = backward_roofline("mixed")
+        out["train"]["mixed"]["step_roofline"] = step_mfma(mstm, "mixed")
         out["train"]["random_atomic_ceiling"] = atomic_ceiling
         del bp_t, bd_t, tgt
 
