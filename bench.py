@@ -107,12 +107,10 @@ def measured_traffic(img, n_dirs):
 def issued_backward_atomics(precision, batch):
     """Lane atomics one backward call issues (k_backward's MLP-gradient flushes
     plus k_scatter_records' merged table-gradient adds), counted with
-    TCP_TCC_ATOMIC_WITHOUT_RET_REQ on the 2^18-sample training batch; None for
-    another batch or stale counters."""
-    if batch != 262144:
-        return None
-    names = (("k_backward_f32_train262144", "k_scatter_records_f32_train262144") if precision == "fp32" else
-             ("k_backward_bf16_train262144", "k_scatter_records_f16_train262144"))
+    TCP_TCC_ATOMIC_WITHOUT_RET_REQ on the benchmark's training batches (2^18
+    FP32 and mixed, 2^20 mixed); None for another batch or stale counters."""
+    names = ((f"k_backward_f32_train{batch}", f"k_scatter_records_f32_train{batch}") if precision == "fp32" else
+             (f"k_backward_bf16_train{batch}", f"k_scatter_records_f16_train{batch}"))
     v = [profile_value(n, "issued_atomics_per_launch") for n in names]
     return None if None in v else {"k_backward": v[0], "k_scatter_records": v[1]}
 
@@ -472,7 +470,7 @@ def main():
         out["train"] = {"samples_per_s": B / (mst * 1e-3), "ms_per_step": mst, "batch": B,
                         "secondary_queries_per_s_fwd_bwd": B / (mst * 1e-3), "dtype": "f32"}
 
-        def backward_roofline(precision):
+        def backward_roofline(precision, B=B):
             """Time the backward call alone (k_backward, the record sort and
             k_scatter_records) on one Morton-ordered batch.  Its binding
             resource is the FP32 atomic adds, which the hardware executes past
@@ -503,7 +501,7 @@ def main():
                          "table_adds_before_merging_per_launch": ATOMICS_PER_SAMPLE * B,
                          "mfma": {"achieved": fl, "peak": mfma_peak, "unit": "TFLOP/s", "frac": fl / mfma_peak}}
 
-        def step_mfma(ms_step, precision):
+        def step_mfma(ms_step, precision, B=B):
             # the whole training step's matrix work (forward + backward per
             # sample) against the matrix-core peak of the MLP precision
             peak = FP32_MFMA_PEAK_TFLOPS if precision == "fp32" else BF16_MFMA_PEAK_TFLOPS
@@ -566,10 +564,16 @@ def main():
             tgt = torch.cat([trgb, tvis[:, None], tdep[:, None]], 1).contiguous()
             del teacher, trgb, tvis, tdep
             ms5t, _, _ = time_events(train_step_mixed, max(2, args.steps // 2), 1, torch)
+            a5 = FLOP_PER_QUERY * P * N5 / (ms5 * 1e-3) / 1e12
             out["mixed_n512_train_2e20"] = {
                 "frame_ms": ms5, "frame_queries_per_s": P * N5 / (ms5 * 1e-3), "frame_px_per_s": P / (ms5 * 1e-3),
+                "frame_roofline": {"bound": "mfma", "kernel": "k_render_mma<Bf16Path, indirect, shade>",
+                                   "achieved": a5, "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                   "frac": a5 / BF16_MFMA_PEAK_TFLOPS},
                 "train_ms": ms5t, "train_samples_per_s": B5 / (ms5t * 1e-3),
+                "train_step_roofline": step_mfma(ms5t, "mixed", B5),
                 "dtype": "bf16-mfma/f16-table/f32-acc; f32 masters"}
+            _, out["mixed_n512_train_2e20"]["train_roofline"] = backward_roofline("mixed", B5)
             del bp_t, bd_t, tgt
 
     if not args.no_cpu:

@@ -16,6 +16,23 @@
 namespace hg {
 
 constexpr int kDelStride = 68;  // del[s][k]: 16-byte aligned rows for broadcast reads
+
+// Replicated MLP-gradient accumulators (mixed backward).  Every wave adds
+// the weight gradients of its 64 samples into one of kWRep copies of
+// [tracer W0, b0, W1, b1, W2, b2 | decoder W0, b0, W1, b1, W2, b2], picked by
+// its block index, instead of into the caller's arrays: with one copy all
+// waves add into the same 13k addresses and those atomics queue behind each
+// other (the mixed backward at 2^18 queries measured 5.2 ms that way, 3.9 ms
+// with 128 copies).  k_reduce_wrep then adds the copies' sum to the caller's
+// arrays.
+constexpr int kWRep = 128;
+constexpr int kRepSize[12] = {kH * kNI, kH, kH * kH, kH, 2 * kH, 2, kH * kNF, kH, kH * kH, kH, 5 * kH, 5};
+constexpr int rep_off(int k) { return k == 0 ? 0 : rep_off(k - 1) + kRepSize[k - 1]; }
+constexpr int kRepTotal = rep_off(12);
+constexpr int kRepStride = (kRepTotal + 255) / 256 * 256;  // floats per copy
+struct GradArrays {
+    float *p[12];  // tracer W0..b2, decoder W0..b2
+};
 constexpr int kWaveLds = 2 * kHBuf + 64 * kDelStride;
 constexpr int kBwdThreads = 64;
 
@@ -301,6 +318,9 @@ __device__ __forceinline__ void mlp_bwd_stored(const MlpK &m, float *const *gp, 
 // last hidden layer.
 struct F32Mlp {
     static constexpr int kLdsBytes = kWaveLds * (int)sizeof(float);
+    // its per-layer gradient flushes overlap the arithmetic (spreading them
+    // over copies measured no faster), so they go straight to the caller
+    static constexpr bool kReplicas = false;
     struct State {
         float h[kH];
     };
@@ -501,6 +521,19 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(const BwdK a) {
     const int lane = threadIdx.x & 63;
     uint8_t *lds = reinterpret_cast<uint8_t *>(lds_f) + (threadIdx.x >> 6) * MLP::kLdsBytes;
     typename MLP::State st;
+    // where this wave's MLP weight gradients go: the caller's arrays, or one
+    // of the replicated accumulators
+    float *gi_rep[6], *gb_rep[6];
+    if constexpr (MLP::kReplicas) {
+        float *rep = a.ws.wrep + (size_t)(blockIdx.x & (kWRep - 1)) * kRepStride;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            gi_rep[k] = rep + rep_off(k);
+            gb_rep[k] = rep + rep_off(6 + k);
+        }
+    }
+    float *const *gi = MLP::kReplicas ? gi_rep : a.gi;
+    float *const *gb = MLP::kReplicas ? gb_rep : a.gb;
     const int64_t p_raw = a.p_begin + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const RenderK &r = a.r;
     const bool live = p_raw < a.p_end;
@@ -568,7 +601,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(const BwdK a) {
             Lz = fmaf(bg.c.z * vj, Ej.z, Lz);
             const float gvj = (gLo.x * bg.c.x * Ej.x + gLo.y * bg.c.y * Ej.y + gLo.z * bg.c.z * Ej.z) * invN2;
             const float go[2] = {gvj * vj * (1.0f - vj), 0.0f};
-            MLP::template bwd<kNI, 2, 0>(r.irt, a.tiles, lds, a.gi, z, go, j == 0, st, dz, lane);
+            MLP::template bwd<kNI, 2, 0>(r.irt, a.tiles, lds, gi, z, go, j == 0, st, dz, lane);
 #pragma unroll
             for (int i = 0; i < kNF; ++i) gfb[i] += dz[i];
             const float kx = gLo.x * vj * Ej.x * invN2, ky = gLo.y * vj * Ej.y * invN2, kz = gLo.z * vj * Ej.z * invN2;
@@ -583,7 +616,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(const BwdK a) {
         const float gob[5] = {gax * ab.x * (1.0f - ab.x), gay * ab.y * (1.0f - ab.y), gaz * ab.z * (1.0f - ab.z),
                               gr * 0.91f * s3 * (1.0f - s3), gm * mb * (1.0f - mb)};
         MLP::template fwd<kNF, 5, 1>(r.brdf, a.tiles, lds, zf, false, st, ob, lane);
-        MLP::template bwd<kNF, 5, 1>(r.brdf, a.tiles, lds, a.gb, zf, gob, false, st, dz, lane);
+        MLP::template bwd<kNF, 5, 1>(r.brdf, a.tiles, lds, gb, zf, gob, false, st, dz, lane);
 #pragma unroll
         for (int i = 0; i < kNF; ++i) gfb[i] += dz[i];
         // the table gradient at x' is scattered by k_scatter_records after the
@@ -600,7 +633,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(const BwdK a) {
     z[kNF] = w.x; z[kNF + 1] = w.y; z[kNF + 2] = w.z;
     const float go2[2] = {gV * V * (1.0f - V), sp < 1.0f ? gd * sigmoidf_(o1p) : 0.0f};
     MLP::template fwd<kNI, 2, 0>(r.irt, a.tiles, lds, z, INDIRECT, st, o, lane);
-    MLP::template bwd<kNI, 2, 0>(r.irt, a.tiles, lds, a.gi, z, go2, true, st, dz, lane);
+    MLP::template bwd<kNI, 2, 0>(r.irt, a.tiles, lds, gi, z, go2, true, st, dz, lane);
     // the table gradient at x is scattered by k_scatter_records too
     float3 gx = make_float3(0.f, 0.f, 0.f);
     if (a.g_pos) gx = encode_dx<TT>(r.g, x.x, x.y, x.z, dz);
@@ -698,6 +731,28 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter_records(const GridK
     }
 }
 
+__global__ __launch_bounds__(256) void k_zero_wrep(float4 *__restrict__ p, int64_t n4) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n4) p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// one thread per parameter: the sum of its kWRep copies, added to the
+// caller's gradient array (the only writer of that element in this call)
+__global__ __launch_bounds__(256) void k_reduce_wrep(const float *__restrict__ rep, GradArrays out) {
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= kRepTotal) return;
+    float s = 0.0f;
+#pragma unroll 8
+    for (int r = 0; r < kWRep; ++r) s += rep[(size_t)r * kRepStride + q];
+    int k = 0;
+#pragma unroll
+    for (int t = 1; t < 12; ++t) k = q >= rep_off(t) ? t : k;
+    int o = 0;
+#pragma unroll
+    for (int t = 0; t < 12; ++t) o = k == t ? rep_off(t) : o;
+    out.p[k][q - o] += s;
+}
+
 hipError_t backward_sort_bytes(int64_t records, size_t &bytes) {
     bytes = 0;
     return hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint32_t *)nullptr, (uint32_t *)nullptr,
@@ -727,7 +782,16 @@ hipError_t launch_backward(const BwdK &a, bool f16, bool bf16_mlp, bool indirect
     const unsigned blocks = (unsigned)((n + kBwdThreads - 1) / kBwdThreads);
     if (bf16_mlp) {
         hipLaunchKernelGGL(k_bwd_tiles, dim3((BT_N * 64 + 255) / 256), dim3(256), 0, s, a.r.irt, a.r.brdf, a.ws.tiles);
+        const int64_t n4 = (int64_t)kWRep * kRepStride / 4;
+        hipLaunchKernelGGL(k_zero_wrep, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s,
+                           reinterpret_cast<float4 *>(a.ws.wrep), n4);
         launch_k_backward<__half, Bf16Mlp>(c, indirect, blocks, s);
+        GradArrays ga;
+        for (int k = 0; k < 6; ++k) {
+            ga.p[k] = a.gi[k];
+            ga.p[6 + k] = a.gb[k];
+        }
+        hipLaunchKernelGGL(k_reduce_wrep, dim3((kRepTotal + 255) / 256), dim3(256), 0, s, a.ws.wrep, ga);
     } else if (f16) {
         launch_k_backward<__half, F32Mlp>(c, indirect, blocks, s);
     } else {
@@ -767,6 +831,8 @@ size_t backward_ws_layout(int64_t n, int R, size_t sort_tmp_bytes, void *base, B
     off += al(sort_tmp_bytes);
     const size_t o_tiles = off;
     off += al((size_t)BT_N * 64 * sizeof(uint4));
+    const size_t o_wrep = off;
+    off += al((size_t)kWRep * kRepStride * sizeof(float));
     if (ws && base) {
         char *b = static_cast<char *>(base);
         ws->xb = reinterpret_cast<float4 *>(b + o_xb);
@@ -778,6 +844,7 @@ size_t backward_ws_layout(int64_t n, int R, size_t sort_tmp_bytes, void *base, B
         ws->sort_tmp = b + o_tmp;
         ws->sort_tmp_bytes = sort_tmp_bytes;
         ws->tiles = reinterpret_cast<uint4 *>(b + o_tiles);
+        ws->wrep = reinterpret_cast<float *>(b + o_wrep);
     }
     return off;
 }

@@ -48,6 +48,7 @@ struct BounceWs {
     void *sort_tmp;
     size_t sort_tmp_bytes;
     uint4 *tiles;      // BF16 weight tiles of the mixed MLP backward
+    float *wrep;       // replicated MLP-gradient accumulators of the mixed backward
 };
 
 struct BwdK {
