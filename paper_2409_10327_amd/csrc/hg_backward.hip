@@ -650,9 +650,11 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(const BwdK a) {
 // level the wave sums its 64 x 8 corner contributions by table entry in a
 // wave-private LDS hash table (open addressing, LDS compare-and-swap on the
 // key, LDS float adds on the two features) and then issues one global
-// atomic per entry and feature: adjacent cells share corners, so this
-// merges more than summing per cell, and the global FP32 atomic add costs
-// the same per lane whatever the addresses, so their count is the cost.
+// atomic request per entry (its two features from two adjacent lanes):
+// adjacent cells share corners, so this merges more than summing per cell,
+// and the global FP32 atomic add costs the same per request whatever the
+// addresses (a request being the lanes of one instruction that fall in one
+// 64-byte line), so the number of requests is the cost.
 constexpr int kScatterThreads = 256;
 constexpr int kHashSlots = 1024;  // >= 2 x the 512 corner entries of a wave and level
 constexpr uint32_t kEmptySlot = 0xffffffffu;
@@ -716,16 +718,20 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter_records(const GridK
             }
         }
         wave_sync();
+        // lanes 2i and 2i + 1 add the two features of one entry in the same
+        // instruction: adjacent words of one line go out as one request, and
+        // the atomic rate is one of requests, not of lanes
         float *gl = g_table + 2 * ((size_t)l << g.log2T);
-        for (int q = lane; q < kHashSlots; q += 64) {
+        const float *Vf = reinterpret_cast<const float *>(V);
+        const int f = lane & 1;
+        for (int q = lane >> 1; q < kHashSlots; q += 32) {
             const uint32_t e = K[q];
-            if (e != kEmptySlot) {
-                const float2 a = V[q];
-                atomic_addf(gl + 2 * (size_t)e, a.x);
-                atomic_addf(gl + 2 * (size_t)e + 1, a.y);
-                K[q] = kEmptySlot;
-                V[q] = make_float2(0.0f, 0.0f);
-            }
+            if (e != kEmptySlot) atomic_addf(gl + 2 * (size_t)e + f, Vf[2 * q + f]);
+        }
+        wave_sync();
+        for (int q = lane; q < kHashSlots; q += 64) {
+            K[q] = kEmptySlot;
+            V[q] = make_float2(0.0f, 0.0f);
         }
         wave_sync();
     }
