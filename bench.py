@@ -105,13 +105,14 @@ def measured_traffic(img, n_dirs):
 
 
 def issued_backward_atomics(precision, batch):
-    """Lane atomics one backward call issues (k_backward's MLP-gradient flushes
-    plus k_scatter_records' merged table-gradient adds), counted with
+    """Atomic requests one backward call issues (k_backward's MLP-gradient
+    flushes plus k_scatter_records' merged table-gradient adds; a request is
+    the lanes of one instruction that fall in one 64-byte line), counted with
     TCP_TCC_ATOMIC_WITHOUT_RET_REQ on the benchmark's training batches (2^18
     FP32 and mixed, 2^20 mixed); None for another batch or stale counters."""
     names = ((f"k_backward_f32_train{batch}", f"k_scatter_records_f32_train{batch}") if precision == "fp32" else
              (f"k_backward_bf16_train{batch}", f"k_scatter_records_f16_train{batch}"))
-    v = [profile_value(n, "issued_atomics_per_launch") for n in names]
+    v = [profile_value(n, "issued_atomic_requests_per_launch") for n in names]
     return None if None in v else {"k_backward": v[0], "k_scatter_records": v[1]}
 
 
@@ -474,11 +475,12 @@ def main():
             """Time the backward call alone (k_backward, the record sort and
             k_scatter_records) on one Morton-ordered batch.  Its binding
             resource is the FP32 atomic adds, which the hardware executes past
-            the L2 at a rate that does not depend on addresses: the roofline
-            is the atomics it issues (counted by rocprofv3) over the measured
-            random-atomic rate.  The 512 table-gradient adds per sample of the
-            definition are merged in LDS before they are issued, so they are
-            reported beside it, not as the achieved rate."""
+            the L2 at a rate of requests (the lanes of one instruction in one
+            64-byte line) that does not depend on addresses: the roofline is
+            the requests it issues (counted by rocprofv3) over the measured
+            random-atomic request rate.  The 512 table-gradient adds per sample
+            of the definition are merged in LDS before they are issued, so
+            they are reported beside it, not as the achieved rate."""
             order = morton_order(bp_t)
             sp, sd, st = bp_t[order], bd_t[order], tgt[order]
             fwd_prec = "fp32" if precision == "fp32" else "mixed"
@@ -494,10 +496,11 @@ def main():
             mfma_peak = FP32_MFMA_PEAK_TFLOPS if precision == "fp32" else BF16_MFMA_PEAK_TFLOPS
             fl = BWD_FLOP_PER_SAMPLE * B / (msb * 1e-3) / 1e12
             return msb, {"bound": "atomics", "kernel": "backward call: k_backward + record sort + k_scatter_records",
-                         "ms": msb, "achieved": rate, "peak": ceil, "unit": "FP32 lane atomics/s",
+                         "ms": msb, "achieved": rate, "peak": ceil, "unit": "FP32 atomic requests/s",
                          "frac": None if rate is None else rate / ceil,
-                         "peak_kind": "measured random FP32 atomic adds over 64 MiB (hgmb_atomic)",
-                         "issued_atomics_per_launch": issued,
+                         "peak_kind": "measured random FP32 atomic adds over 64 MiB (hgmb_atomic), one lane "
+                                      "per request",
+                         "issued_atomic_requests_per_launch": issued,
                          "table_adds_before_merging_per_launch": ATOMICS_PER_SAMPLE * B,
                          "mfma": {"achieved": fl, "peak": mfma_peak, "unit": "TFLOP/s", "frac": fl / mfma_peak}}
 
@@ -541,6 +544,8 @@ def main():
         _, out["train"]["mixed"]["roofline"] = backward_roofline("mixed")
         out["train"]["mixed"]["step_roofline"] = step_mfma(mstm, "mixed")
         out["train"]["random_atomic_ceiling"] = atomic_ceiling
+        # the same rate per request when two or sixteen lanes share a line
+        out["train"]["atomic_lines"] = [MB.atomic_lines(64 << 20, g) for g in (2, 16)]
         del bp_t, bd_t, tgt
 
         if not (args.no_mixed or args.no_c5):

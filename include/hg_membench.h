@@ -7,9 +7,10 @@
  *     the access pattern of the hash-grid encoder's corner lookups (a
  *     multi-resolution hash encoding reads its tables at effectively random
  *     addresses; paper Sec. 3.2 builds its renderer on such tables);
- *   - random FP32 atomic adds into a table, alone or with groups of lanes
- *     on one address, the pattern of the backward's scatter into the table
- *     gradients (Sec. 3.3 distillation);
+ *   - random FP32 atomic adds into a table, alone, with groups of lanes on
+ *     one address, or with groups of lanes on adjacent words of one line,
+ *     the pattern of the backward's scatter into the table gradients
+ *     (Sec. 3.3 distillation);
  *   - matrix-core throughput loops (FP32 32x32x2 and BF16 16x16x32) with
  *     independent accumulator chains, the steps the MLP layers run on.
  *
@@ -62,6 +63,17 @@ int hgmb_gather_indexed(const void *table, int32_t item_bytes, const uint32_t *i
  * hgmb_gather. */
 int hgmb_atomic(float *table, int32_t log2_items, int32_t blocks, int32_t rounds, int32_t lanes_per_address,
                 uint32_t seed, hipStream_t stream);
+
+/* FP32 atomic add of 1.0 (no return value) into `table` (2^log2_items
+ * floats, 16-byte aligned): `rounds` x 4 atomics per thread over blocks x 256
+ * threads; lanes_per_line (1, 2, 4, 8 or 16) consecutive lanes of a wave add
+ * to that many adjacent words of one aligned block (inside one 64-byte
+ * line), the blocks random.  The rate per group against the rate per lane
+ * tells whether the atomic unit's cost is per lane or per request (the
+ * lanes of one instruction that fall in one line).  Same ranges as
+ * hgmb_atomic. */
+int hgmb_atomic_lines(float *table, int32_t log2_items, int32_t blocks, int32_t rounds, int32_t lanes_per_line,
+                      uint32_t seed, hipStream_t stream);
 
 /* Matrix-core loop: every wave of blocks x 256 threads issues `iters`
  * rounds of `chains` (1, 2, 4, 8 or 16) independent accumulating steps of

@@ -647,32 +647,35 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(const BwdK a) {
 
 // Table-gradient scatter, one lane per record in the order of the Morton
 // keys of the record points, so that a wave's 64 points are neighbours.  Per
-// level the wave sums its 64 x 8 corner contributions by table entry in a
-// wave-private LDS hash table (open addressing, LDS compare-and-swap on the
-// key, LDS float adds on the two features) and then issues one global
-// atomic request per entry (its two features from two adjacent lanes):
-// adjacent cells share corners, so this merges more than summing per cell,
-// and the global FP32 atomic add costs the same per request whatever the
+// level the wave sums its 64 x 8 corner contributions by 64-byte line of the
+// gradient table (8 entries of two FP32 features) in a wave-private LDS hash
+// table (open addressing on the line, LDS compare-and-swap on the key, LDS
+// float adds into the entry's two words), lists the lines it touched and
+// adds each line with one instruction of 16 lanes, i.e. one atomic request.
+// The global FP32 atomic add costs the same per request whatever the
 // addresses (a request being the lanes of one instruction that fall in one
-// 64-byte line), so the number of requests is the cost.
-constexpr int kScatterThreads = 256;
-constexpr int kHashSlots = 1024;  // >= 2 x the 512 corner entries of a wave and level
+// line), so the number of lines is the cost: a cell's two corners along x
+// share a line in 7 of 8 cases on dense and hashed levels alike (the hash's
+// x factor is 1), and neighbouring points share cells and lines; at the
+// benchmark batch about 17 requests per record remain of the 256 adds.
+constexpr int kScatterThreads = 64;  // one wave per block (35 KB of LDS)
+constexpr int kLineSlots = 512;      // >= the 64 x 8 corner entries of a wave and level, so probing ends
 constexpr uint32_t kEmptySlot = 0xffffffffu;
 template <typename TT>
 __global__ __launch_bounds__(kScatterThreads) void k_scatter_records(const GridK g, const uint32_t *__restrict__ id,
                                                                      const float4 *__restrict__ xb,
                                                                      const float *__restrict__ gf,
                                                                      float *__restrict__ g_table, int64_t n) {
-    __shared__ uint32_t hkey[kScatterThreads / 64][kHashSlots];
-    __shared__ float2 hval[kScatterThreads / 64][kHashSlots];
-    const int lane = threadIdx.x & 63;
-    uint32_t *K = hkey[threadIdx.x >> 6];
-    float2 *V = hval[threadIdx.x >> 6];
-    for (int q = lane; q < kHashSlots; q += 64) {
+    __shared__ uint32_t K[kLineSlots];        // line index (entry / 8) or empty
+    __shared__ float V[kLineSlots][16];       // the line's 8 entries x 2 features
+    __shared__ uint32_t list[kLineSlots];     // occupied (line << 9 | slot) of this level
+    const int lane = threadIdx.x;
+    for (int q = lane; q < kLineSlots; q += 64) {
         K[q] = kEmptySlot;
-        V[q] = make_float2(0.0f, 0.0f);
+#pragma unroll
+        for (int w = 0; w < 16; ++w) V[q][w] = 0.0f;
     }
-    const int64_t i = (int64_t)blockIdx.x * kScatterThreads + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * kScatterThreads + lane;
     const bool live = i < n;
     const uint32_t p = id[live ? i : n - 1];
     const float4 x = xb[p];
@@ -690,6 +693,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter_records(const GridK
     bool in[3];
     pos_to_u(g, x.x, x.y, x.z, u, in);
     wave_sync();
+    const uint64_t below = (1ull << lane) - 1ull;
 #pragma unroll 1
     for (int l = 0; l < kL; ++l) {
         if (l >= (int)g.L) break;  // wave-uniform
@@ -701,37 +705,65 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter_records(const GridK
             uint32_t idx[8];
             corner_idx(g, l, c, idx);
             const float w0[3] = {1.0f - w[0], 1.0f - w[1], 1.0f - w[2]};
+            // the first probe of the eight corners in flight together, then
+            // the collisions resolved one by one; at most 512 distinct lines
+            // in 512 slots, so every probe ends
+            uint32_t h[8], prev[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                h[k] = ((idx[k] >> 3) * 2654435761u) >> (32 - 9);
+                prev[k] = atomicCAS(&K[h[k]], kEmptySlot, idx[k] >> 3);
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const uint32_t ln = idx[k] >> 3;
+                while (prev[k] != kEmptySlot && prev[k] != ln) {
+                    h[k] = (h[k] + 1) & (kLineSlots - 1);
+                    prev[k] = atomicCAS(&K[h[k]], kEmptySlot, ln);
+                }
+            }
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 const float wt =
                     ((k & 1) ? w[0] : w0[0]) * (((k >> 1) & 1) ? w[1] : w0[1]) * (((k >> 2) & 1) ? w[2] : w0[2]);
-                const uint32_t e = idx[k];
-                uint32_t h = (e * 2654435761u) >> (32 - 10);
-                // at most 512 distinct keys in 1024 slots: the probe ends
-                while (true) {
-                    const uint32_t prev = atomicCAS(&K[h], kEmptySlot, e);
-                    if (prev == kEmptySlot || prev == e) break;
-                    h = (h + 1) & (kHashSlots - 1);
-                }
-                atomicAdd(&V[h].x, wt * gfp[2 * l]);
-                atomicAdd(&V[h].y, wt * gfp[2 * l + 1]);
+                atomicAdd(&V[h[k]][2 * (idx[k] & 7u)], wt * gfp[2 * l]);
+                atomicAdd(&V[h[k]][2 * (idx[k] & 7u) + 1], wt * gfp[2 * l + 1]);
             }
         }
         wave_sync();
-        // lanes 2i and 2i + 1 add the two features of one entry in the same
-        // instruction: adjacent words of one line go out as one request, and
-        // the atomic rate is one of requests, not of lanes
-        float *gl = g_table + 2 * ((size_t)l << g.log2T);
-        const float *Vf = reinterpret_cast<const float *>(V);
-        const int f = lane & 1;
-        for (int q = lane >> 1; q < kHashSlots; q += 32) {
-            const uint32_t e = K[q];
-            if (e != kEmptySlot) atomic_addf(gl + 2 * (size_t)e + f, Vf[2 * q + f]);
+        // list the occupied slots (a ballot per 64 slots)
+        int cnt = 0;
+#pragma unroll
+        for (int r = 0; r < kLineSlots / 64; ++r) {
+            const int q = 64 * r + lane;
+            const uint32_t ln = K[q];
+            const bool occ = ln != kEmptySlot;
+            const uint64_t m = __ballot(occ);
+            if (occ) list[cnt + __popcll(m & below)] = (ln << 9) | (uint32_t)q;
+            cnt += __popcll(m);
         }
         wave_sync();
-        for (int q = lane; q < kHashSlots; q += 64) {
-            K[q] = kEmptySlot;
-            V[q] = make_float2(0.0f, 0.0f);
+        // one instruction of 16 lanes per line: lane 16 j + w adds word w of
+        // the j-th listed line (four lines per instruction, four instructions
+        // with their LDS reads issued together)
+        float *gl = g_table + 2 * ((size_t)l << g.log2T);
+        const int wd = lane & 15;
+        for (int j0 = lane >> 4; j0 < cnt; j0 += 16) {
+            uint32_t it[4];
+            float v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) it[u] = j0 + 4 * u < cnt ? list[j0 + 4 * u] : kEmptySlot;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = it[u] != kEmptySlot ? V[it[u] & (kLineSlots - 1)][wd] : 0.0f;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (it[u] != kEmptySlot) atomic_addf(gl + 16 * (size_t)(it[u] >> 9) + wd, v[u]);
+        }
+        wave_sync();
+        for (int j = lane >> 4; j < cnt; j += 4) {
+            const uint32_t q = list[j] & (kLineSlots - 1);
+            V[q][wd] = 0.0f;
+            if (wd == 0) K[q] = kEmptySlot;
         }
         wave_sync();
     }

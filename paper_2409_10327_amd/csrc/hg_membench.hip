@@ -112,6 +112,22 @@ __global__ __launch_bounds__(kThreads) void k_atomic(float *__restrict__ table, 
     }
 }
 
+// Groups of G = 2^gs consecutive lanes add to G adjacent words of one
+// G-word-aligned block at a random place: for G <= 16 the group's words lie
+// in one 64-byte line.
+__global__ __launch_bounds__(kThreads) void k_atomic_lines(float *__restrict__ table, uint32_t log2_items,
+                                                           uint32_t rounds, uint32_t gs, uint32_t seed) {
+    const uint32_t tid = blockIdx.x * kThreads + threadIdx.x;
+    const uint32_t ngroups = (gridDim.x * kThreads) >> gs;
+    const uint32_t grp = tid >> gs, sub = tid & ((1u << gs) - 1u);
+    const uint32_t emask = (1u << (log2_items - gs)) - 1u;
+    for (uint32_t r = 0; r < rounds; ++r) {
+        const uint32_t base = (r * ngroups + grp) * 4u;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) unsafeAtomicAdd(&table[((mix32((base + u) ^ seed) & emask) << gs) + sub], 1.0f);
+    }
+}
+
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -212,6 +228,19 @@ int hgmb_atomic(float *table, int32_t log2_items, int32_t blocks, int32_t rounds
     const uint32_t mask = (uint32_t)((uint64_t(1) << log2_items) - 1);
     hipLaunchKernelGGL(k_atomic, dim3((unsigned)blocks), dim3(kThreads), 0, stream, table, mask, (uint32_t)rounds,
                        (uint32_t)shift, seed);
+    return launched();
+}
+
+int hgmb_atomic_lines(float *table, int32_t log2_items, int32_t blocks, int32_t rounds, int32_t lanes_per_line,
+                      uint32_t seed, hipStream_t stream) {
+    int shift = -1;
+    for (int s = 0; s <= 4; ++s)
+        if (lanes_per_line == (1 << s)) shift = s;
+    if (shift < 0 || !aligned16(table) || log2_items < 4 || log2_items > 29 || blocks < 1 || blocks > (1 << 20) ||
+        rounds < 1 || rounds > (1 << 16))
+        return 1;
+    hipLaunchKernelGGL(k_atomic_lines, dim3((unsigned)blocks), dim3(kThreads), 0, stream, table, (uint32_t)log2_items,
+                       (uint32_t)rounds, (uint32_t)shift, seed);
     return launched();
 }
 

@@ -11,7 +11,7 @@ import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhg_membench.so")
-EXPORTS = ["hgmb_gather", "hgmb_gather_indexed", "hgmb_atomic", "hgmb_mfma"]
+EXPORTS = ["hgmb_gather", "hgmb_gather_indexed", "hgmb_atomic", "hgmb_atomic_lines", "hgmb_mfma"]
 _lib = None
 
 
@@ -28,6 +28,8 @@ def lib():
         L.hgmb_gather_indexed.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p,
                                           C.c_void_p]
         L.hgmb_atomic.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_uint32, C.c_void_p]
+        L.hgmb_atomic_lines.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_uint32,
+                                        C.c_void_p]
         L.hgmb_mfma.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]
         _lib = L
     return _lib
@@ -93,6 +95,19 @@ def atomic(footprint_bytes: int, lanes_per_address: int, reps: int = 5, rounds: 
     n = blocks * 256 * rounds * 4
     return {"footprint_MiB": (1 << log2_items) * 4 / 2**20, "lanes_per_address": lanes_per_address, "ms": ms,
             "lane_atomics_per_s": n / (ms * 1e-3), "addresses_per_s": n / lanes_per_address / (ms * 1e-3)}
+
+
+def atomic_lines(footprint_bytes: int, lanes_per_line: int, reps: int = 5, rounds: int = 16):
+    """FP32 atomic adds where groups of lanes_per_line lanes hit adjacent
+    words of one line: lane atomics/s and groups (requests)/s."""
+    log2_items = (footprint_bytes // 4).bit_length() - 1
+    table = torch.zeros(1 << log2_items, device="cuda", dtype=torch.float32)
+    blocks = _cus() * 32
+    ms = _timed(lambda: lib().hgmb_atomic_lines(C.c_void_p(table.data_ptr()), log2_items, blocks, rounds,
+                                                lanes_per_line, 7, _stream()), reps)
+    n = blocks * 256 * rounds * 4
+    return {"footprint_MiB": (1 << log2_items) * 4 / 2**20, "lanes_per_line": lanes_per_line, "ms": ms,
+            "lane_atomics_per_s": n / (ms * 1e-3), "requests_per_s": n / lanes_per_line / (ms * 1e-3)}
 
 
 def mfma(kind: str, chains: int, waves_per_simd: int = 2, iters: int = 4096, reps: int = 3):

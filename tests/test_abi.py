@@ -264,5 +264,8 @@ def test_membench_exports_and_validation():
     assert L.hgmb_gather_indexed(f, 8, None, 0, 1, f, None) == 0     # empty stream: nothing launched
     assert L.hgmb_atomic(f, 20, 1, 1, 3, 0, None) == 1               # lanes per address not a power of two
     assert L.hgmb_atomic(f, 20, 1, 1, 128, 0, None) == 1
+    assert L.hgmb_atomic_lines(f, 20, 1, 1, 32, 0, None) == 1        # a group beyond one line
+    assert L.hgmb_atomic_lines(f, 20, 1, 1, 6, 0, None) == 1         # not a power of two
+    assert L.hgmb_atomic_lines(C.c_void_p(FAKE + 4), 20, 1, 1, 2, 0, None) == 1  # alignment
     assert L.hgmb_mfma(2, 1, 1, 1, f, None) == 1                     # kind
     assert L.hgmb_mfma(0, 1, 1, 3, f, None) == 1                     # chains
