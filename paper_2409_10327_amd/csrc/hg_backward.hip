@@ -33,7 +33,13 @@ constexpr int kRepStride = (kRepTotal + 255) / 256 * 256;  // floats per copy
 struct GradArrays {
     float *p[12];  // tracer W0..b2, decoder W0..b2
 };
-constexpr int kWaveLds = 2 * kHBuf + 64 * kDelStride;
+// Per-wave LDS of the FP32 MLP backward: two buffers, each of which holds
+// in turn an activation layout ([unit][kHS]) or delta rows
+// ([sample][kDelStride]), and the upstream-gradient rows of the output layer
+// (at most 8 per sample): 36 KB, so four waves fit in a CU.
+constexpr int kBufF = kHBuf > 64 * kDelStride ? kHBuf : 64 * kDelStride;
+constexpr int kGoStride = 8;
+constexpr int kWaveLds = 2 * kBufF + 64 * kGoStride;
 constexpr int kBwdThreads = 64;
 
 __device__ __forceinline__ void wave_sync() {
@@ -45,10 +51,10 @@ __device__ __forceinline__ void wave_sync() {
 __device__ __forceinline__ void atomic_addf(float *p, float v) { unsafeAtomicAdd(p, v); }
 
 // dW[o][col] += sum_s del[s][o] * act[col][s] over the wave's 64 samples
-// (act in the [unit][kHS] layout of the forward, del in [sample][kDelStride]);
+// (act in the [unit][kHS] layout of the forward, del in [sample][DS]);
 // lane == col owns column col.  Bias gradients db[o] = sum_s del[s][o] are
 // added by lane == o.
-template <int NOUT, int NIN>
+template <int NOUT, int NIN, int DS>
 __device__ __forceinline__ void reduce_layer(const float *act, const float *del, float *gW, float *gb, int lane) {
     constexpr int CH = NOUT < 16 ? NOUT : 16;
     if (lane < NIN) {
@@ -60,7 +66,7 @@ __device__ __forceinline__ void reduce_layer(const float *act, const float *del,
 #pragma unroll 4
             for (int s = 0; s < 64; ++s) {
                 const float a = act[lane * kHS + s];
-                const float *row = del + s * kDelStride + ob;
+                const float *row = del + s * DS + ob;
                 if constexpr (CH % 4 == 0) {
 #pragma unroll
                     for (int k = 0; k < CH; k += 4) {
@@ -82,7 +88,7 @@ __device__ __forceinline__ void reduce_layer(const float *act, const float *del,
     if (lane < NOUT) {
         float acc = 0.0f;
 #pragma unroll 8
-        for (int s = 0; s < 64; ++s) acc += del[s * kDelStride + lane];
+        for (int s = 0; s < 64; ++s) acc += del[s * DS + lane];
         atomic_addf(gb + lane, acc);
     }
 }
@@ -264,19 +270,22 @@ __device__ __forceinline__ void store_row(float *del, int lane, const float (&v)
 }
 
 // Backward of one MLP evaluation for every lane of the wave (all lanes call
-// it together), given the forward just run by mlp_fwd into h1buf / h2buf
-// with h = the last hidden layer: accumulates parameter gradients
+// it together), given the forward just run by mlp_fwd_mma with h1 in bufA
+// and h2 in bufB and h = the lane's own h2: accumulates parameter gradients
 // (gp = W0,b0,W1,b1,W2,b2) and returns d/d(input) for the first kNF inputs.
+// The delta rows, the transposed products and the restaged inputs take
+// their turns in the two buffers as those fall free (h1 is needed after its
+// weight gradient only as the lane's ReLU mask, kept as 64 bits), so a wave
+// needs two buffers rather than three.
 template <int NIN, int NOUT>
 __device__ __forceinline__ void mlp_bwd_stored(const MlpK &m, float *const *gp, const float (&z)[NIN],
-                                               const float (&gout)[NOUT], float (&h)[kH], float *h1buf, float *h2buf,
-                                               float *del, int lane, float (&dz)[kNF]) {
-    // ---- layer 2: out = W2 h2 + b2
+                                               const float (&gout)[NOUT], float (&h)[kH], float *bufA, float *bufB,
+                                               float *go, int lane, float (&dz)[kNF]) {
+    // ---- layer 2: out = W2 h2 + b2 (upstream gradient rows in go)
 #pragma unroll
-    for (int k = 0; k < NOUT; ++k) del[lane * kDelStride + k] = gout[k];
+    for (int k = 0; k < NOUT; ++k) go[lane * kGoStride + k] = gout[k];
     wave_sync();
-    reduce_layer<NOUT, kH>(h2buf, del, gp[4], gp[5], lane);
-    wave_sync();
+    reduce_layer<NOUT, kH, kGoStride>(bufB, go, gp[4], gp[5], lane);
     {
         const WPtr<float> W2(m.W2);
 #pragma unroll
@@ -287,35 +296,39 @@ __device__ __forceinline__ void mlp_bwd_stored(const MlpK &m, float *const *gp, 
             h[k] = h[k] > 0.0f ? s : 0.0f;  // h now holds d/d(pre-activation 2)
         }
     }
-    // ---- layer 1: pre2 = W1 h1 + b1
-    store_row(del, lane, h);
+    wave_sync();  // h2 (bufB) read by every lane
+    // ---- layer 1: pre2 = W1 h1 + b1; delta2 rows into bufB
+    store_row(bufB, lane, h);
     wave_sync();
-    reduce_layer_mma<kH>(h1buf, del, gp[2], gp[3], lane);
-    wave_sync();
-    // d/d(pre-activation 1) = mask(h1) * W1^T g2, through the h2 buffer (free now)
-    wt_times_del<kH>(static_cast<const float *>(m.W1), kH, del, h2buf, lane);
+    reduce_layer_mma<kH>(bufA, bufB, gp[2], gp[3], lane);
+    uint64_t m1 = 0;  // ReLU mask of the lane's own h1
+#pragma unroll
+    for (int j = 0; j < kH; ++j) m1 |= (uint64_t)(bufA[j * kHS + lane] > 0.0f) << j;
+    wave_sync();  // h1 (bufA) read by every lane
+    // d/d(pre-activation 1) = mask(h1) * W1^T delta2, transposed through bufA
+    wt_times_del<kH>(static_cast<const float *>(m.W1), kH, bufB, bufA, lane);
     wave_sync();
 #pragma unroll
-    for (int j = 0; j < kH; ++j) h[j] = h1buf[j * kHS + lane] > 0.0f ? h2buf[lane * kHS + j] : 0.0f;
-    // ---- layer 0: pre1 = W0 z + b0; z goes into the h2 buffer
+    for (int j = 0; j < kH; ++j) h[j] = ((m1 >> j) & 1u) ? bufA[lane * kHS + j] : 0.0f;
     wave_sync();
-    store_row(del, lane, h);
+    // ---- layer 0: pre1 = W0 z + b0; delta1 rows into bufB, z into bufA
+    store_row(bufB, lane, h);
 #pragma unroll
-    for (int i = 0; i < NIN; ++i) h2buf[i * kHS + lane] = z[i];
+    for (int i = 0; i < NIN; ++i) bufA[i * kHS + lane] = z[i];
     wave_sync();
-    reduce_layer_mma<NIN>(h2buf, del, gp[0], gp[1], lane);
+    reduce_layer_mma<NIN>(bufA, bufB, gp[0], gp[1], lane);
     wave_sync();
-    // d/d(features) = W0f^T g1, through the h1 buffer (free now)
-    wt_times_del<kNF>(static_cast<const float *>(m.W0), NIN, del, h1buf, lane);
+    // d/d(features) = W0f^T delta1, transposed through bufA
+    wt_times_del<kNF>(static_cast<const float *>(m.W0), NIN, bufB, bufA, lane);
     wave_sync();
 #pragma unroll
-    for (int i = 0; i < kNF; ++i) dz[i] = h1buf[lane * kHS + i];
+    for (int i = 0; i < kNF; ++i) dz[i] = bufA[lane * kHS + i];
 }
 
 // The FP32 MLP functions behind the interface the kernel body calls (the
-// BF16 ones are in hg_bwd_bf16.h): per-wave LDS = two activation buffers and
-// the delta rows; the state kept from forward to backward is the lane's own
-// last hidden layer.
+// BF16 ones are in hg_bwd_bf16.h): per-wave LDS = two buffers and the
+// upstream-gradient rows; the state kept from forward to backward is the
+// lane's own last hidden layer.
 struct F32Mlp {
     static constexpr int kLdsBytes = kWaveLds * (int)sizeof(float);
     // its per-layer gradient flushes overlap the arithmetic (spreading them
@@ -328,25 +341,15 @@ struct F32Mlp {
     static __device__ void fwd(const MlpK &m, const uint4 *, uint8_t *lds, const float (&z)[NIN], bool, State &st,
                                float (&out)[NOUT], int lane) {
         float *h1 = reinterpret_cast<float *>(lds);
-        mlp_fwd_mma<NIN, NOUT>(m, z, h1, h1 + kHBuf, lane, st.h, out);
+        mlp_fwd_mma<NIN, NOUT>(m, z, h1, h1 + kBufF, lane, st.h, out);
     }
     template <int NIN, int NOUT, int W>
     static __device__ void bwd(const MlpK &m, const uint4 *, uint8_t *lds, float *const *gp, const float (&z)[NIN],
                                const float (&gout)[NOUT], bool, State &st, float (&dz)[kNF], int lane) {
         float *h1 = reinterpret_cast<float *>(lds);
-        mlp_bwd_stored<NIN, NOUT>(m, gp, z, gout, st.h, h1, h1 + kHBuf, h1 + 2 * kHBuf, lane, dz);
+        mlp_bwd_stored<NIN, NOUT>(m, gp, z, gout, st.h, h1, h1 + kBufF, h1 + 2 * kBufF, lane, dz);
     }
 };
-
-// Forward recompute plus backward of one MLP evaluation (see mlp_bwd_stored).
-template <int NIN, int NOUT>
-__device__ __forceinline__ void mlp_bwd_wave(const MlpK &m, float *const *gp, const float (&z)[NIN],
-                                             const float (&gout)[NOUT], float *h1buf, float *h2buf, float *del, int lane,
-                                             float (&dz)[kNF]) {
-    float h[kH], o[NOUT];
-    mlp_fwd_mma<NIN, NOUT>(m, z, h1buf, h2buf, lane, h, o);  // h = h2
-    mlp_bwd_stored<NIN, NOUT>(m, gp, z, gout, h, h1buf, h2buf, del, lane, dz);
-}
 
 // Adds this lane's 16 contributions v[2k + f] (corner k, feature f) into the
 // table gradient of one level (gl = level base, idx = corner entries of the
