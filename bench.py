@@ -440,17 +440,17 @@ def main():
         step = [0]
 
         def morton_order(p):
-            # batch order along a Morton curve (10 bits per axis over the batch's
-            # box): queries of a wave then share cells down to finer levels and
-            # the backward's per-cell summation replaces more atomics
-            lo, hi = p.min(0).values, p.max(0).values
-            q = ((p - lo) / (hi - lo).clamp_min(1e-12) * 1023.0).long().clamp_(0, 1023)
+            # batch order along a Morton curve (21 bits per axis over the hash
+            # grid's domain box, no reduction over the batch): queries of a
+            # wave then share cells down to finer levels
+            q = ((p - H.BOX_LO) * ((1 << 21) / H.BOX_EXTENT)).long().clamp_(0, (1 << 21) - 1)
 
             def spread(v):
-                v = (v | (v << 16)) & 0x030000FF
-                v = (v | (v << 8)) & 0x0300F00F
-                v = (v | (v << 4)) & 0x030C30C3
-                return (v | (v << 2)) & 0x09249249
+                v = (v | (v << 32)) & 0x1F00000000FFFF
+                v = (v | (v << 16)) & 0x1F0000FF0000FF
+                v = (v | (v << 8)) & 0x100F00F00F00F00F
+                v = (v | (v << 4)) & 0x10C30C30C30C30C3
+                return (v | (v << 2)) & 0x1249249249249249
             return torch.argsort(spread(q[:, 0]) | (spread(q[:, 1]) << 1) | (spread(q[:, 2]) << 2))
 
         def train_step():
