@@ -700,14 +700,49 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter_records(const GridK
 #pragma unroll 1
     for (int l = 0; l < kL; ++l) {
         if (l >= (int)g.L) break;  // wave-uniform
-        if (live) {
-            uint32_t c[3];
-            float w[3];
+        uint32_t c[3];
+        float w[3];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) cell_of(u[d], g.resf[l], g.nm1f[l], c[d], w[d]);
-            uint32_t idx[8];
-            corner_idx(g, l, c, idx);
-            const float w0[3] = {1.0f - w[0], 1.0f - w[1], 1.0f - w[2]};
+        for (int d = 0; d < 3; ++d) cell_of(u[d], g.resf[l], g.nm1f[l], c[d], w[d]);
+        uint32_t idx[8];
+        corner_idx(g, l, c, idx);
+        const float w0[3] = {1.0f - w[0], 1.0f - w[1], 1.0f - w[2]};
+        float vx[8], vy[8];  // the lane's contributions to the two features of its eight corners
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const float wt = live ? ((k & 1) ? w[0] : w0[0]) * (((k >> 1) & 1) ? w[1] : w0[1]) *
+                                        (((k >> 2) & 1) ? w[2] : w0[2])
+                                  : 0.0f;
+            vx[k] = wt * gfp[2 * l];
+            vy[k] = wt * gfp[2 * l + 1];
+        }
+        // Lanes whose points lie in one cell of this level form runs (the
+        // records are in Morton order).  When the wave has few runs (the
+        // coarse levels), each run's sums are formed across its lanes first
+        // and only its first lane inserts them: LDS atomics of many lanes on
+        // one word are serialised.
+        // (every lane takes part in every shuffle: a lane left out of one
+        // leaves undefined values for the lanes that read from it)
+        const uint32_t p0 = __shfl_up(c[0], 1), p1 = __shfl_up(c[1], 1), p2 = __shfl_up(c[2], 1);
+        const bool head = lane == 0 || p0 != c[0] || p1 != c[1] || p2 != c[2];
+        const uint64_t heads = __ballot(head);
+        bool ins = live;
+        if (__popcll(heads) <= 32) {  // wave-uniform
+            const int seg = __popcll(heads & (below | (1ull << lane)));
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int sn = __shfl_down(seg, off);
+                const bool same = lane + off < 64 && sn == seg;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const float tx = __shfl_down(vx[k], off), ty = __shfl_down(vy[k], off);
+                    vx[k] += same ? tx : 0.0f;
+                    vy[k] += same ? ty : 0.0f;
+                }
+            }
+            ins = head;
+        }
+        if (ins) {
             // the first probe of the eight corners in flight together, then
             // the collisions resolved one by one; at most 512 distinct lines
             // in 512 slots, so every probe ends
@@ -727,10 +762,8 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter_records(const GridK
             }
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
-                const float wt =
-                    ((k & 1) ? w[0] : w0[0]) * (((k >> 1) & 1) ? w[1] : w0[1]) * (((k >> 2) & 1) ? w[2] : w0[2]);
-                atomicAdd(&V[h[k]][2 * (idx[k] & 7u)], wt * gfp[2 * l]);
-                atomicAdd(&V[h[k]][2 * (idx[k] & 7u) + 1], wt * gfp[2 * l + 1]);
+                atomicAdd(&V[h[k]][2 * (idx[k] & 7u)], vx[k]);
+                atomicAdd(&V[h[k]][2 * (idx[k] & 7u) + 1], vy[k]);
             }
         }
         wave_sync();
@@ -748,7 +781,8 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter_records(const GridK
         wave_sync();
         // one instruction of 16 lanes per line: lane 16 j + w adds word w of
         // the j-th listed line (four lines per instruction, four instructions
-        // with their LDS reads issued together)
+        // with their LDS reads issued together) and clears it for the next
+        // level
         float *gl = g_table + 2 * ((size_t)l << g.log2T);
         const int wd = lane & 15;
         for (int j0 = lane >> 4; j0 < cnt; j0 += 16) {
@@ -759,14 +793,14 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter_records(const GridK
 #pragma unroll
             for (int u = 0; u < 4; ++u) v[u] = it[u] != kEmptySlot ? V[it[u] & (kLineSlots - 1)][wd] : 0.0f;
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (it[u] != kEmptySlot) atomic_addf(gl + 16 * (size_t)(it[u] >> 9) + wd, v[u]);
-        }
-        wave_sync();
-        for (int j = lane >> 4; j < cnt; j += 4) {
-            const uint32_t q = list[j] & (kLineSlots - 1);
-            V[q][wd] = 0.0f;
-            if (wd == 0) K[q] = kEmptySlot;
+            for (int u = 0; u < 4; ++u) {
+                if (it[u] != kEmptySlot) {
+                    const uint32_t q = it[u] & (kLineSlots - 1);
+                    atomic_addf(gl + 16 * (size_t)(it[u] >> 9) + wd, v[u]);
+                    V[q][wd] = 0.0f;
+                    if (wd == 0) K[q] = kEmptySlot;
+                }
+            }
         }
         wave_sync();
     }
