@@ -20,17 +20,22 @@
 // its column, and lane l keeps N-tile l/16, which is its own query.
 // Inputs that come from other lanes (features, directions) go through LDS.
 // The tracer's first layer is split into a per-point part (W0f f + b0,
-// computed once per point and used as the accumulator input) and a
-// direction part (two K-steps in FP32; one in the mixed path, which splits
-// the direction into BF16 high and low halves).
+// the accumulator input) and a direction part (two K-steps in FP32; one in
+// the mixed path, which splits the direction into BF16 high and low
+// halves).  The FP32 path computes the per-point part once per point; the
+// mixed path recomputes it at the bounce points in every secondary tracer
+// call (registers, below).
 //
-// Occupancy.  The FP32 path runs 512-thread blocks at two waves per SIMD
-// (at most 256 registers per wave) and bounces a wave's 64 queries in two
-// halves of 32 points (bounce_lo_half); the mixed path runs 256-thread
-// blocks at one wave per SIMD with the whole-wave bounce (bounce_lo), which
-// measured faster for it.  In the FP32 path a wave raises its issue priority
-// for the tracer's matrix-core steps, so that the vector work of the SIMD's
-// other wave fills the matrix pipe's gaps rather than delaying its next step.
+// Occupancy.  Both paths run two waves per SIMD (at most 256 registers per
+// wave), so that one wave's gathers and vector work overlap the other's
+// matrix-core work.  The FP32 path runs 512-thread blocks and bounces a
+// wave's 64 queries in two halves of 32 points (bounce_lo_half); the mixed
+// path runs two 256-thread blocks per CU with the whole-wave bounce
+// (bounce_lo) and reads its tracer operands from LDS at each use instead of
+// holding them in registers.  In the FP32 path a wave raises its issue
+// priority for the tracer's matrix-core steps, so that the vector work of
+// the SIMD's other wave fills the matrix pipe's gaps rather than delaying
+// its next step.
 #include "hg_bf16.h"
 #include "hg_device.h"
 #include "hg_launch.h"
@@ -81,11 +86,14 @@ struct Bf16Path {
     enum : int {
         T_W0W = 0, T_W0F = 4, T_W1 = 8, T_W2 = 16,       // tracer
         B_W0 = 18, B_W1 = 22, B_W2A = 30, B_W2B = 32,    // decoder
-        N_TILES = 34
+        N_TILES = 34,
+        // the tracer's biases in accumulator order, four FP32 per lane
+        T_B0 = 34, T_B1 = 38, T_B2 = 42,
+        N_ALL = 43
     };
-    typedef uint4 Tile;  // 8 BF16 per lane
-    static constexpr int kTileFloats = N_TILES * 64;  // LDS array length in Tiles
-    static constexpr int kThreads = 256;              // one wave per SIMD
+    typedef uint4 Tile;  // 8 BF16 per lane (or four FP32 for a bias tile)
+    static constexpr int kTileFloats = N_ALL * 64;  // LDS array length in Tiles
+    static constexpr int kThreads = 256;  // two blocks per CU: two waves per SIMD (kernel held to 256 registers)
     static constexpr bool kHalfBounce = false;        // bounce of all 64 points at once
 
     struct Wave {
@@ -123,8 +131,15 @@ struct Bf16Path {
 
     static __device__ __forceinline__ void build_tiles(const RenderK &ka, Tile *tiles) {
         const WSrc a = wsrc(ka);
-        for (int q = threadIdx.x; q < N_TILES * 64; q += blockDim.x) {
+        for (int q = threadIdx.x; q < N_ALL * 64; q += blockDim.x) {
             const int t = q >> 6, l = q & 63, i = l & 15, g = l >> 4;
+            if (t >= T_B0) {
+                const f32x4 v = t < T_B1 ? bias_tile(ka.irt.b0, t - T_B0, g)
+                                         : (t < T_B2 ? bias_tile(ka.irt.b1, t - T_B1, g) : head_bias(ka.irt.b2, 2, 0));
+                tiles[q] = make_uint4(__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]),
+                                      __float_as_uint(v[3]));
+                continue;
+            }
             uint32_t w[4];
 #pragma unroll
             for (int p = 0; p < 4; ++p)
@@ -134,22 +149,18 @@ struct Bf16Path {
         }
     }
 
-    // hot tracer operands held in registers
+    static __device__ __forceinline__ f32x4 ftile(const Tile *tiles, int t, int lane) {
+        const uint4 u = tiles[t * 64 + lane];
+        return f32x4{__uint_as_float(u.x), __uint_as_float(u.y), __uint_as_float(u.z), __uint_as_float(u.w)};
+    }
+
+    // The tracer's operand and bias tiles are read from LDS at each use
+    // rather than held in registers across calls: that keeps the kernel
+    // within 256 registers, two waves per SIMD, so that one wave's gathers
+    // and vector work overlap the other's (LDS traffic of the reads: about
+    // 0.5 MB per wave and 64-query chunk, a small part of the LDS rate).
     struct Tracer {
-        uint4 w0w[4], w1[8], w2[2];
-        f32x4 b1[4], b2;
-        __device__ void load(const Tile *tiles, const RenderK &a, int lane) {
-            const int g = lane >> 4;
-#pragma unroll
-            for (int m = 0; m < 4; ++m) w0w[m] = tiles[(T_W0W + m) * 64 + lane];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) w1[k] = tiles[(T_W1 + k) * 64 + lane];
-            w2[0] = tiles[T_W2 * 64 + lane];
-            w2[1] = tiles[(T_W2 + 1) * 64 + lane];
-#pragma unroll
-            for (int m = 0; m < 4; ++m) b1[m] = bias_tile(a.irt.b1, m, g);
-            b2 = head_bias(a.irt.b2, 2, 0);
-        }
+        __device__ void load(const Tile *, const RenderK &, int) {}
     };
 
     static __device__ __forceinline__ void store_feat(Wave &W, int row, const float (&f)[kNF]) {
@@ -172,7 +183,8 @@ struct Bf16Path {
                                                          int lane, int g, f32x4 (&d)[4]) {
         const uint4 xb = W.x[16 * nt + (lane & 15)][g];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) d[m] = mfma_bf16(tiles[(T_W0F + m) * 64 + lane], xb, bias_tile(a.irt.b0, m, g));
+        for (int m = 0; m < 4; ++m)
+            d[m] = mfma_bf16(tiles[(T_W0F + m) * 64 + lane], xb, ftile(tiles, T_B0 + m, lane));
     }
 
     // decoder on the features of N-tile nt: oa rows 0..3 = outputs 0..3,
@@ -197,22 +209,22 @@ struct Bf16Path {
     }
 
     // tracer for N-tile nt from the point part c: returns the head tile
-    static __device__ __forceinline__ f32x4 tracer_nt(const Tracer &T, const Tile *, const Wave &W, int buf, int nt,
+    static __device__ __forceinline__ f32x4 tracer_nt(const Tracer &T, const Tile *tiles, const Wave &W, int buf, int nt,
                                                       int lane, const f32x4 (&c)[4]) {
         const uint4 ob_ = W.om[buf][16 * nt + (lane & 15)];
         f32x4 d[4];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) d[m] = mfma_bf16(T.w0w[m], ob_, c[m]);
+        for (int m = 0; m < 4; ++m) d[m] = mfma_bf16(tiles[(T_W0W + m) * 64 + lane], ob_, c[m]);
         const uint4 h0 = act_pack(d[0], d[1]), h1 = act_pack(d[2], d[3]);
         f32x4 e[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-            e[m] = mfma_bf16(T.w1[2 * m], h0, T.b1[m]);
-            e[m] = mfma_bf16(T.w1[2 * m + 1], h1, e[m]);
+            e[m] = mfma_bf16(tiles[(T_W1 + 2 * m) * 64 + lane], h0, ftile(tiles, T_B1 + m, lane));
+            e[m] = mfma_bf16(tiles[(T_W1 + 2 * m + 1) * 64 + lane], h1, e[m]);
         }
         const uint4 k0 = act_pack(e[0], e[1]), k1 = act_pack(e[2], e[3]);
-        f32x4 o = mfma_bf16(T.w2[0], k0, T.b2);
-        return mfma_bf16(T.w2[1], k1, o);
+        f32x4 o = mfma_bf16(tiles[T_W2 * 64 + lane], k0, ftile(tiles, T_B2, lane));
+        return mfma_bf16(tiles[(T_W2 + 1) * 64 + lane], k1, o);
     }
 
     // ---- whole-wave interface (four 16-column N-tiles) ----
@@ -298,6 +310,31 @@ struct Bf16Path {
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
             const f32x4 c[4] = {pp.v[0][nt], pp.v[1][nt], pp.v[2][nt], pp.v[3][nt]};
+            const f32x4 hh = tracer_nt(T, tiles, W, buf, nt, lane, c);
+            if (g == nt) {
+                o0 = hh[0];
+                o1 = hh[1];
+            }
+        }
+        return make_float2(o0, DEPTH ? o1 : 0.0f);
+    }
+
+    // Tracer at the bounce points for the secondary directions: the point
+    // part b0 + W0f x' is recomputed in each call from the features in W.x
+    // (the same products in the same order, so the same values) instead of
+    // being kept in 64 registers across the secondary loop.
+    struct NoPart {};
+    typedef NoPart BouncePart;
+    static __device__ __forceinline__ void bounce_part(const Tile *, const RenderK &, const Wave &, int, NoPart &) {}
+    template <bool DEPTH>
+    static __device__ __forceinline__ float2 tracer_bounce(const Tracer &T, const Tile *tiles, const RenderK &a,
+                                                           const Wave &W, int buf, int lane, const NoPart &) {
+        const int g = lane >> 4;
+        float o0 = 0.f, o1 = 0.f;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            f32x4 c[4];
+            point_part_nt(tiles, a, W, nt, lane, g, c);
             const f32x4 hh = tracer_nt(T, tiles, W, buf, nt, lane, c);
             if (g == nt) {
                 o0 = hh[0];
@@ -674,7 +711,7 @@ struct SecondaryBrdf {
 template <class PP, bool NHEAD>
 __device__ __forceinline__ float3 secondary_lo(const RenderK &a, const typename PP::Tile *tiles,
                                                typename PP::Wave &W, const typename PP::Tracer &T,
-                                               const typename PP::PointPart &bpt, int lane, const Frame &frb,
+                                               const typename PP::BouncePart &bpt, int lane, const Frame &frb,
                                                const SecondaryBrdf &sb, uint32_t pid, uint32_t q, bool hard) {
     const uint32_t n2 = a.s.n_dirs2;
     uint4 words2 = philox4x32_10(pid, q, 0u, 1u, a.s.key0, a.s.key1);
@@ -691,7 +728,7 @@ __device__ __forceinline__ float3 secondary_lo(const RenderK &a, const typename 
         const float3 wn = sample_dir(pick4(words2, jn), jn, a.s.nb2_shift, a.s.inv_na2, a.s.inv_nb2, frb);
         const float3 En = env_lookup(a.env, wn.x, wn.y, wn.z);
         const float3 cn = sb.eval<NHEAD>(wn);
-        const float vo = PP::template tracer<false, false>(T, tiles, W, (int)(j & 1u), lane, bpt).x;
+        const float vo = PP::template tracer_bounce<false>(T, tiles, a, W, (int)(j & 1u), lane, bpt).x;
         PP::store_dir(W, (int)((j + 1) & 1u), lane, wn);
         // hard visibility: only visible secondary rays contribute
         const float vj = hard ? (vo > 0.0f ? 1.0f : 0.0f) : sigmoidf_(vo);
@@ -721,8 +758,8 @@ __device__ __forceinline__ float3 bounce_lo(const RenderK &a, const typename PP:
     wave_sync_lds();
     PP::store_feat(W, lane, fb);
     wave_sync_lds();
-    typename PP::PointPart bpt;
-    PP::point_part(tiles, a, W, lane, bpt);
+    typename PP::BouncePart bpt;
+    PP::bounce_part(tiles, a, W, lane, bpt);
     float od[8];
     PP::decoder(tiles, a, W, lane, od);
     const float3 ab = make_float3(sigmoidf_(od[0]), sigmoidf_(od[1]), sigmoidf_(od[2]));
@@ -905,7 +942,9 @@ __device__ __forceinline__ float3 bounce_lo_half(const RenderK &a, const typenam
 // most four pixels per wave).
 // ============================================================================
 template <class PP, bool INDIRECT, bool QUERY, bool MIS>
-__global__ __launch_bounds__(PP::kThreads) void k_render_mma(const RenderK a, int64_t n_items) {
+// at least two waves per SIMD: the register budget is 256 per wave
+__global__ __launch_bounds__(PP::kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_render_mma(const RenderK a,
+                                                                                              int64_t n_items) {
     typedef typename PP::Table TT;
     constexpr int kWaves = PP::kThreads / 64;
     __shared__ typename PP::Tile tiles[PP::kTileFloats];
