@@ -232,7 +232,6 @@ hg_status render(const hg_model *model, const hg_env *env, const hg_sampling *sa
     CHECK(check_points(pts, query));
     CHECK(check_sampling(samp, !query, k.s));
     SUPPORT(prec != Prec::F16TableF32Mlp, "rendering needs (F32 table, F32 MLP) or (F16 table, BF16 MLP)");
-    SUPPORT(prec != Prec::Mixed || query || samp->n_dirs >= 16, "the mixed path needs n_dirs >= 16 in shade mode");
     REQUIRE((samp->flags & HG_MIS) == 0 || env->dist != nullptr,
             "HG_MIS needs env.dist (hg_env_build_sampling)");
     if (pts->n == 0) return HG_OK;
@@ -254,13 +253,10 @@ hg_status render(const hg_model *model, const hg_env *env, const hg_sampling *sa
     k.vis = vis;
     k.depth = depth;
     k.n = pts->n;
-    // FP32: matrix-core kernel for query mode and for shade mode with at
-    // least 16 directions per point (at most four points per wave); the
-    // vector-ALU kernel covers 1..8 directions.
-    hipError_t e;
-    if (prec == Prec::Mixed) e = hg::launch_render_mixed(k, indirect, query, stream);
-    else if (query || samp->n_dirs >= 16) e = hg::launch_render_f32_mma(k, indirect, query, stream);
-    else e = hg::launch_render_f32_shade(k, indirect, stream);
+    // the matrix-core kernel in every mode (shade mode with fewer than 16
+    // directions per point: per-lane features, up to 64 points per wave)
+    const hipError_t e = prec == Prec::Mixed ? hg::launch_render_mixed(k, indirect, query, stream)
+                                             : hg::launch_render_f32_mma(k, indirect, query, stream);
     return hip_status(e, indirect ? "hg_render_indirect" : "hg_render_direct");
 }
 

@@ -560,62 +560,12 @@ struct FacingBrdf {
 };
 
 // --------------------------------------------------------------------------
-// Three-layer ReLU MLP on the vector ALU, one sample per lane.  Weights are
-// read with wave-uniform addresses (scalar loads); W[k] is [out][in].
+// Per-lane activation storage in LDS (the backward's FP32 MLPs): column
+// `lane` of a [64][kHS] array, the odd stride letting both the per-lane rows
+// and the per-unit columns be read without bank conflicts.
 // --------------------------------------------------------------------------
-// Per-lane activation storage in LDS: column `lane` of a [64][kHS] array
-// (padded stride, so that both the per-lane rows and the per-unit columns
-// are read without bank conflicts).  Each lane reads back only what it wrote,
-// so no barrier is needed between a write and its read.
 constexpr int kHS = 65;
 constexpr int kHBuf = kH * kHS;   // floats per wave per activation buffer
-
-// out[o] = act(b[o] + sum_i W[o][i] in[i]) for o < NOUT, written to
-// hbuf[o * kHS + lane].  The loop over outputs is not unrolled: each
-// iteration reads one weight row with scalar loads.
-template <int NIN, typename WT, bool RELU>
-__device__ __forceinline__ void layer_to_lds(const void *W, const float *b, int nout, const float (&in)[NIN],
-                                             float *hbuf, int lane) {
-#pragma unroll 1
-    for (int o = 0; o < nout; ++o) {
-        const WPtr<WT> w(W);
-        const BPtr bb(b);
-        float acc = bb[o];
-#pragma unroll
-        for (int i = 0; i < NIN; ++i) acc = fmaf(w[o * NIN + i], in[i], acc);
-        hbuf[o * kHS + lane] = RELU ? fmaxf(acc, 0.0f) : acc;
-    }
-}
-
-template <int N>
-__device__ __forceinline__ void load_col(const float *hbuf, int lane, float (&h)[N]) {
-#pragma unroll
-    for (int i = 0; i < N; ++i) h[i] = hbuf[i * kHS + lane];
-}
-
-// Three-layer ReLU MLP for one sample per lane.  h1buf/h2buf receive the
-// hidden activations (they may alias when the caller does not need h1).
-// Returns the last hidden layer in h (registers) and the outputs in out.
-template <int NIN, int NOUT, typename WT>
-__device__ __forceinline__ void mlp_fwd(const MlpK &m, const float (&in)[NIN], float *h1buf, float *h2buf, int lane,
-                                        float (&h)[kH], float (&out)[NOUT], int nout = NOUT) {
-    layer_to_lds<NIN, WT, true>(m.W0, m.b0, kH, in, h1buf, lane);
-    load_col(h1buf, lane, h);
-    layer_to_lds<kH, WT, true>(m.W1, m.b1, kH, h, h2buf, lane);
-    load_col(h2buf, lane, h);
-    const WPtr<WT> W2(m.W2);
-    const BPtr b2(m.b2);
-#pragma unroll
-    for (int o = 0; o < NOUT; ++o) {
-        float acc = 0.0f;
-        if (o < nout) {  // wave-uniform: rows past the weight matrix are zero
-            acc = b2[o];
-#pragma unroll
-            for (int i = 0; i < kH; ++i) acc = fmaf(W2[o * kH + i], h[i], acc);
-        }
-        out[o] = acc;
-    }
-}
 
 // --------------------------------------------------------------------------
 // Multiple importance sampling of the primary directions (Sec. 4.1): light

@@ -72,7 +72,6 @@ hipError_t backward_sort_bytes(int64_t records, size_t &bytes);
 
 hipError_t launch_encode(const GridK &g, bool f16, const float *pos, int64_t n, float *feat, hipStream_t s);
 hipError_t launch_encode_index(const GridK &g, const float *pos, int64_t n, uint32_t *idx, float *w, hipStream_t s);
-hipError_t launch_render_f32_shade(const RenderK &a, bool indirect, hipStream_t s);
 hipError_t launch_render_f32_mma(const RenderK &a, bool indirect, bool query, hipStream_t s);
 hipError_t launch_render_mixed(const RenderK &a, bool indirect, bool query, hipStream_t s);
 hipError_t launch_backward(const BwdK &a, bool f16, bool bf16_mlp, bool indirect, hipStream_t s);

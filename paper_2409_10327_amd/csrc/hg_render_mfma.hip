@@ -269,6 +269,16 @@ struct Bf16Path {
             }
         }
     }
+    // per-lane mode: decoder outputs of the 64 lanes' own features f
+    static __device__ __forceinline__ void query_material(const Tile *tiles, const RenderK &a, Wave &W, int lane,
+                                                          const float (&f)[kNF], float (&o)[8]) {
+        wave_sync_lds();
+        store_feat(W, lane, f);
+        wave_sync_lds();
+        decoder(tiles, a, W, lane, o);
+        wave_sync_lds();
+    }
+
     // shade mode: decoder outputs and tracer point part of the pixel slots
     // (feature rows 0 .. ppw - 1) into W.mat / W.ax
     static __device__ __forceinline__ void pixel_setup(const Tile *tiles, const RenderK &a, Wave &W, int lane,
@@ -611,6 +621,30 @@ struct F32Path {
         }
     }
 
+    // per-lane mode: decoder outputs of the 64 lanes' own features f, in two
+    // passes of 32 feature rows (lanes 32 nt .. 32 nt + 31 in pass nt)
+    static __device__ __forceinline__ void query_material(const Tile *tiles, const RenderK &a, Wave &W, int lane,
+                                                          const float (&f)[kNF], float (&o)[8]) {
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            wave_sync_lds();
+            if ((lane >> 5) == nt) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    *reinterpret_cast<float4 *>(&W.x[lane & 31][4 * q]) =
+                        make_float4(f[4 * q], f[4 * q + 1], f[4 * q + 2], f[4 * q + 3]);
+            }
+            wave_sync_lds();
+            float t[8];
+            decoder(tiles, a, W, lane, t);
+            if ((lane >> 5) == nt) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) o[k] = t[k];
+            }
+        }
+        wave_sync_lds();
+    }
+
     // shade mode: decoder outputs and tracer point part of the pixel slots
     // (feature rows 0 .. ppw - 1) into W.mat / W.ax
     static __device__ __forceinline__ void pixel_setup(const Tile *tiles, const RenderK &a, Wave &W, int lane,
@@ -938,10 +972,13 @@ __device__ __forceinline__ float3 bounce_lo_half(const RenderK &a, const typenam
 
 // ============================================================================
 // The kernel.  QUERY: one query per lane with its own point and direction;
-// otherwise shade mode with G = min(N, 64) lanes per pixel (N >= 16, so at
-// most four pixels per wave).
+// otherwise shade mode with G = min(N, 64) lanes per pixel.  For N >= 16 (at
+// most four pixels per wave) the pixels' features, material and tracer point
+// part are formed once per pixel slot; PERLANE (N < 16, up to 64 pixels per
+// wave): every lane forms its own pixel's, as in query mode, and the G lanes
+// of a pixel then shade and sum as in shade mode.
 // ============================================================================
-template <class PP, bool INDIRECT, bool QUERY, bool MIS>
+template <class PP, bool INDIRECT, bool QUERY, bool MIS, bool PERLANE>
 // at least two waves per SIMD: the register budget is 256 per wave
 __global__ __launch_bounds__(PP::kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_render_mma(const RenderK a,
                                                                                               int64_t n_items) {
@@ -966,7 +1003,7 @@ __global__ __launch_bounds__(PP::kThreads) __attribute__((amdgpu_waves_per_eu(2)
 
     // Shade mode: a work unit is 4 / ppw consecutive items, whose four pixel
     // slots share one pixel setup (encode at x, decoder, tracer point part).
-    const int ipw = QUERY ? 1 : 4 / ppw;
+    const int ipw = (QUERY || PERLANE) ? 1 : 4 / ppw;
     const int64_t n_units = (n_items + ipw - 1) / ipw;
     for (int64_t unit = wave_id; unit < n_units; unit += waves_total) {
     for (int ii = 0; ii < ipw; ++ii) {
@@ -983,8 +1020,8 @@ __global__ __launch_bounds__(PP::kThreads) __attribute__((amdgpu_waves_per_eu(2)
         // ---------------- primary point ----------------
         float3 n_ = make_float3(0.f, 0.f, 1.f), v_ = n_, alb = n_;
         float rr = 0.5f, mm = 0.f;
-        float fq[kNF];  // query mode: the lane's own features at x
-        if (QUERY) {
+        float fq[kNF];  // query and per-lane modes: the lane's own features at x
+        if (QUERY || PERLANE) {
             encode<TT>(a.g, x.x, x.y, x.z, fq);
         } else if (ii == 0) {
             // lane l encodes level l % 16 of pixel slot l / 16 (pixel 4 unit + slot)
@@ -1020,12 +1057,22 @@ __global__ __launch_bounds__(PP::kThreads) __attribute__((amdgpu_waves_per_eu(2)
             wave_sync_lds();
         }
         if (!QUERY) {
-            const int myslot = sbase + (lane >> gs);
             n_ = make_float3(a.nrm[3 * p], a.nrm[3 * p + 1], a.nrm[3 * p + 2]);
             v_ = make_float3(a.wo[3 * p], a.wo[3 * p + 1], a.wo[3 * p + 2]);
-            alb = make_float3(sigmoidf_(W.mat[myslot][0]), sigmoidf_(W.mat[myslot][1]), sigmoidf_(W.mat[myslot][2]));
-            rr = 0.09f + 0.91f * sigmoidf_(W.mat[myslot][3]);
-            mm = sigmoidf_(W.mat[myslot][4]);
+            float mo[5];
+            if (PERLANE) {
+                float od[8];
+                PP::query_material(tiles, a, W, lane, fq, od);
+#pragma unroll
+                for (int k = 0; k < 5; ++k) mo[k] = od[k];
+            } else {
+                const int myslot = sbase + (lane >> gs);
+#pragma unroll
+                for (int k = 0; k < 5; ++k) mo[k] = W.mat[myslot][k];
+            }
+            alb = make_float3(sigmoidf_(mo[0]), sigmoidf_(mo[1]), sigmoidf_(mo[2]));
+            rr = 0.09f + 0.91f * sigmoidf_(mo[3]);
+            mm = sigmoidf_(mo[4]);
         }
         const Frame fr = make_frame(n_);
         const float3 vl = MIS ? ggx_view(fr, v_) : v_;
@@ -1064,7 +1111,7 @@ __global__ __launch_bounds__(PP::kThreads) __attribute__((amdgpu_waves_per_eu(2)
                 // tracer point part at x: query mode (one chunk per item) from
                 // the lanes' features, shade mode from the pixel slots
                 typename PP::PointPart c;
-                if (QUERY) PP::query_point_part(tiles, a, W, lane, fq, c);
+                if (QUERY || PERLANE) PP::query_point_part(tiles, a, W, lane, fq, c);
                 else PP::pixel_point_part(W, lane, gs, sbase, c);
                 const float2 oo = PP::template tracer<true, false>(T, tiles, W, 0, lane, c);
                 const float o0 = oo.x, o1 = oo.y;
@@ -1199,7 +1246,7 @@ __global__ __launch_bounds__(PP::kThreads) __attribute__((amdgpu_waves_per_eu(2)
 
 template <class PP>
 static hipError_t launch_mma(const RenderK &a, bool indirect, bool query, hipStream_t s) {
-    if (!query && a.s.n_dirs < 16) return hipErrorNotSupported;
+    const bool perlane = !query && a.s.n_dirs < 16;
     int n_cus = 0;
     const hipError_t ec = current_device_cus(n_cus);
     if (ec != hipSuccess) return ec;
@@ -1212,14 +1259,22 @@ static hipError_t launch_mma(const RenderK &a, bool indirect, bool query, hipStr
     const dim3 grid(blocks), block(PP::kThreads);
     const bool mis = (a.s.flags & 4u) != 0;
     if (query) {
-        if (indirect) hipLaunchKernelGGL((k_render_mma<PP, true, true, false>), grid, block, 0, s, a, items);
-        else hipLaunchKernelGGL((k_render_mma<PP, false, true, false>), grid, block, 0, s, a, items);
+        if (indirect) hipLaunchKernelGGL((k_render_mma<PP, true, true, false, false>), grid, block, 0, s, a, items);
+        else hipLaunchKernelGGL((k_render_mma<PP, false, true, false, false>), grid, block, 0, s, a, items);
+    } else if (perlane) {
+        if (mis) {
+            if (indirect) hipLaunchKernelGGL((k_render_mma<PP, true, false, true, true>), grid, block, 0, s, a, items);
+            else hipLaunchKernelGGL((k_render_mma<PP, false, false, true, true>), grid, block, 0, s, a, items);
+        } else {
+            if (indirect) hipLaunchKernelGGL((k_render_mma<PP, true, false, false, true>), grid, block, 0, s, a, items);
+            else hipLaunchKernelGGL((k_render_mma<PP, false, false, false, true>), grid, block, 0, s, a, items);
+        }
     } else if (mis) {
-        if (indirect) hipLaunchKernelGGL((k_render_mma<PP, true, false, true>), grid, block, 0, s, a, items);
-        else hipLaunchKernelGGL((k_render_mma<PP, false, false, true>), grid, block, 0, s, a, items);
+        if (indirect) hipLaunchKernelGGL((k_render_mma<PP, true, false, true, false>), grid, block, 0, s, a, items);
+        else hipLaunchKernelGGL((k_render_mma<PP, false, false, true, false>), grid, block, 0, s, a, items);
     } else {
-        if (indirect) hipLaunchKernelGGL((k_render_mma<PP, true, false, false>), grid, block, 0, s, a, items);
-        else hipLaunchKernelGGL((k_render_mma<PP, false, false, false>), grid, block, 0, s, a, items);
+        if (indirect) hipLaunchKernelGGL((k_render_mma<PP, true, false, false, false>), grid, block, 0, s, a, items);
+        else hipLaunchKernelGGL((k_render_mma<PP, false, false, false, false>), grid, block, 0, s, a, items);
     }
     return hipGetLastError();
 }

@@ -113,6 +113,22 @@ def test_shade_sample_counts_and_ragged(c1, N, npix):
     assert relerr(vis.cpu().numpy(), ovis) < TOL
 
 
+
+@pytest.mark.parametrize("N,npix", [(1, 70), (8, 33)])
+def test_shade_small_n_direct(c1, N, npix):
+    """The per-lane mode (fewer than 16 directions) without the bounce."""
+    print(f"case: direct shade N={N} npix={npix}", flush=True)
+    sl = slice(300, 300 + npix)
+    pos, nrm, wo = c1["pos"][sl], c1["nrm"][sl], c1["wo"][sl]
+    t = c1["t"]
+    rgb, vis, dep = hg.render(c1["r"], c1["env_t"], t(pos), t(nrm), t(wo), n_dirs=N, indirect=False,
+                              want_vis=True)
+    orgb, ovis, odep = O.render(c1["om"], c1["oe"], O.sampling(N, 8, 7, 0), pos, nrm, wo, indirect=False)
+    assert relerr(rgb.cpu().numpy(), orgb) < TOL
+    assert relerr(vis.cpu().numpy(), ovis) < TOL
+    assert relerr(dep.cpu().numpy(), odep) < TOL
+
+
 def test_empty_input_is_noop(c1):
     pos = torch.empty((0, 3), device=DEV)
     rgb, vis, dep = hg.render(c1["r"], c1["env_t"], pos, pos, pos, n_dirs=32)

@@ -56,9 +56,10 @@ def test_hard_query(c1, precision):
     assert e < (1e-5 if precision == "fp32" else 2e-3)
 
 
-@pytest.mark.parametrize("N,precision", [(32, "fp32"), (128, "fp32"), (128, "mixed")])
+@pytest.mark.parametrize("N,precision", [(4, "fp32"), (32, "fp32"), (128, "fp32"), (4, "mixed"), (128, "mixed")])
 def test_hard_shade(c1, N, precision):
-    """N = 128 takes the shadow-ray queue (one pixel per wave); N = 32 does not."""
+    """N = 128 takes the shadow-ray queue (one pixel per wave); N = 32 does
+    not; N = 4 takes the per-lane mode (16 pixels per wave)."""
     print(f"case: hard visibility shade N={N} {precision}", flush=True)
     t = c1["t"]
     sl = slice(0, 1024)
@@ -81,10 +82,16 @@ def test_hard_shade(c1, N, precision):
     else:
         # over 128 directions almost every pixel has some direction whose BF16
         # visibility lands within the margin of 0.5, so the mixed bar is the
-        # image-level one (PSNR against the FP64 oracle)
+        # image-level one (PSNR against the FP64 oracle).  With N = 4 a binary
+        # visibility that flips within BF16 rounding of the threshold (at the
+        # primary point, or at the bounce point, where the secondary rays are
+        # binary too) moves its pixel by up to a quarter (an eighth) of its
+        # value and nothing averages it out: about 41 dB measured, against
+        # 45 dB and more at N = 128; the bar for few directions is 38 dB.  The
+        # clear directions' visibility is still required to be exact (above).
         p = psnr(rgb, orgb)
         print(f"hard shade N={N} mixed: {clear.mean():.4f} of directions clear, PSNR {p:.1f} dB")
-        assert p >= 45.0
+        assert p >= (45.0 if N >= 16 else 38.0)
 
 
 def test_hard_is_deterministic(c1):

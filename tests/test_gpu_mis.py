@@ -74,10 +74,11 @@ def test_env_distribution(name):
     assert np.allclose(dens, odens, rtol=1e-6, atol=0)
 
 
-@pytest.mark.parametrize("N,precision", [(2, "fp32"), (8, "fp32"), (32, "fp32"), (128, "fp32"), (128, "mixed")])
+@pytest.mark.parametrize("N,precision", [(2, "fp32"), (8, "fp32"), (32, "fp32"), (128, "fp32"), (2, "mixed"),
+                                         (128, "mixed")])
 def test_mis_frame(c1, N, precision):
-    """N = 2 is the paper's one light ray + one GGX ray (vector-ALU kernel);
-    N >= 16 runs on the matrix cores."""
+    """N = 2 is the paper's one light ray + one GGX ray; fewer than 16
+    directions take the matrix-core kernel's per-lane mode."""
     print(f"case: MIS frame 64x64 N={N} {precision}", flush=True)
     t = c1["t"]
     rgb, vis, _ = hg.render(c1["r"], c1["env_t"], t(c1["pos"]), t(c1["nrm"]), t(c1["wo"]), n_dirs=N,

@@ -53,8 +53,10 @@ def test_mixed_query_c1(c1, indirect):
     assert e[0] < 2e-3 and e[1] < 5e-3 and e[2] < 5e-3
 
 
-@pytest.mark.parametrize("N,npix", [(16, 67), (32, 33), (64, 3), (256, 2)])
+@pytest.mark.parametrize("N,npix", [(1, 37), (2, 65), (8, 130), (16, 67), (32, 33), (64, 3), (256, 2)])
 def test_mixed_sample_counts_and_ragged(c1, N, npix):
+    """N < 16 takes the per-lane mode (up to 64 points per wave), N >= 16 the
+    pixel-slot mode."""
     print(f"case: mixed shade N={N} npix={npix}", flush=True)
     t = c1["t"]
     sl = slice(1000, 1000 + npix)
