@@ -310,8 +310,8 @@ def main():
 
     if not args.no_mis:
         # MIS primary directions (light-importance + GGX visible-normal rays):
-        # the paper's one + one rays per pixel (vector-ALU kernel), and the
-        # 128-direction frame on the matrix cores
+        # the paper's one + one rays per pixel (the matrix-core kernel's
+        # per-lane mode) and the 128-direction frame
         dist = hg.env_sampling(env_t)
 
         def frame_mis(n, prec):
@@ -326,7 +326,10 @@ def main():
                       "paper_1plus1_queries_per_s": 2 * P / (ms2 * 1e-3),
                       "n128_fp32_ms": ms128, "n128_fp32_queries_per_s": S / (ms128 * 1e-3)}
         if not args.no_mixed:
+            ms2m, _, _ = time_events(frame_mis(2, "mixed"), args.steps, args.warmup, torch)
             ms128m, _, _ = time_events(frame_mis(cfg.n_dirs, "mixed"), args.steps, args.warmup, torch)
+            out["mis"]["paper_1plus1_mixed_ms"] = ms2m
+            out["mis"]["paper_1plus1_mixed_fps"] = 1e3 / ms2m
             out["mis"]["n128_mixed_ms"] = ms128m
             out["mis"]["n128_mixed_queries_per_s"] = S / (ms128m * 1e-3)
         del dist
@@ -348,9 +351,11 @@ def main():
         mp32, _, _ = time_events(frame_paper(cfg.n_dirs, "fp32"), args.steps, args.warmup, torch)
         mpm, _, _ = time_events(frame_paper(cfg.n_dirs, "mixed"), args.steps, args.warmup, torch)
         mpmis, _, _ = time_events(frame_paper(2, "fp32", hg.HG_MIS), args.steps, args.warmup, torch)
+        mpmism, _, _ = time_events(frame_paper(2, "mixed", hg.HG_MIS), args.steps, args.warmup, torch)
         out["paper_shape"] = {"n128_fp32_ms": mp32, "n128_fp32_queries_per_s": S / (mp32 * 1e-3),
                               "n128_mixed_ms": mpm, "n128_mixed_queries_per_s": S / (mpm * 1e-3),
-                              "mis_1plus1_fp32_ms": mpmis, "mis_1plus1_fps": 1e3 / mpmis}
+                              "mis_1plus1_fp32_ms": mpmis, "mis_1plus1_fps": 1e3 / mpmis,
+                              "mis_1plus1_mixed_ms": mpmism, "mis_1plus1_mixed_fps": 1e3 / mpmism}
         del rp, pdist
 
     if not args.no_denoise:
