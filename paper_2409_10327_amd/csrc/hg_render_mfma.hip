@@ -32,7 +32,7 @@
 // wave's 64 queries in two halves of 32 points (bounce_lo_half); the mixed
 // path runs two 256-thread blocks per CU with the whole-wave bounce
 // (bounce_lo) and reads its tracer operands from LDS at each use instead of
-// holding them in registers.  In the FP32 path a wave raises its issue
+// holding them in registers.  In both paths a wave raises its issue
 // priority for the tracer's matrix-core steps, so that the vector work of
 // the SIMD's other wave fills the matrix pipe's gaps rather than delaying
 // its next step.
@@ -212,6 +212,11 @@ struct Bf16Path {
     static __device__ __forceinline__ f32x4 tracer_nt(const Tracer &T, const Tile *tiles, const Wave &W, int buf, int nt,
                                                       int lane, const f32x4 (&c)[4]) {
         const uint4 ob_ = W.om[buf][16 * nt + (lane & 15)];
+        // raised issue priority over the tracer's matrix-core steps, so that
+        // the SIMD's other wave fills their gaps with its vector work instead
+        // of delaying them (raising it over the decoder and the point part
+        // too starved the other wave's encoder: slower)
+        __builtin_amdgcn_s_setprio(1);
         f32x4 d[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) d[m] = mfma_bf16(tiles[(T_W0W + m) * 64 + lane], ob_, c[m]);
@@ -224,7 +229,9 @@ struct Bf16Path {
         }
         const uint4 k0 = act_pack(e[0], e[1]), k1 = act_pack(e[2], e[3]);
         f32x4 o = mfma_bf16(tiles[T_W2 * 64 + lane], k0, ftile(tiles, T_B2, lane));
-        return mfma_bf16(tiles[(T_W2 + 1) * 64 + lane], k1, o);
+        o = mfma_bf16(tiles[(T_W2 + 1) * 64 + lane], k1, o);
+        __builtin_amdgcn_s_setprio(0);
+        return o;
     }
 
     // ---- whole-wave interface (four 16-column N-tiles) ----
