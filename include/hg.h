@@ -210,7 +210,7 @@ hg_status hg_render_indirect(const hg_model *model, const hg_env *env, const hg_
  * depends on (x, and with the bounce also x') one record of 160 bytes
  * (the point, the feature gradient there, a sort key and an index, and
  * their sorted copies), plus the radix sort's temporary storage, the
- * BF16 weight tiles of the mixed backward (66 KiB) and its 128 replicated
+ * BF16 weight tiles of the mixed backward (66 KiB) and 128 replicated
  * accumulators of the MLP gradients (6.5 MiB).  0 for n <= 0, n >= 2^30 or
  * indirect not 0/1. */
 size_t hg_backward_workspace_size(int32_t indirect, int64_t n);
@@ -228,10 +228,10 @@ size_t hg_backward_workspace_size(int32_t indirect, int64_t n);
  * mixed path, the MLP products in BF16 on the matrix cores with FP32
  * accumulation (weights the BF16 shadows, activations and deltas packed to
  * BF16), the gradient arrays FP32 in every case.  Biases are FP32 in all.
- * Accumulation order of the atomics is unspecified.  The mixed backward
- * first adds each wave's MLP weight gradients into one of 128 copies in the
- * workspace (so that the waves' atomics do not all meet on one address) and
- * then adds the copies' sum to g_brdf / g_irt on the same stream.
+ * Accumulation order of the atomics is unspecified.  Each wave first adds
+ * its MLP weight gradients into one of 128 copies in the workspace (so that
+ * the waves' atomics do not all meet on one address); the copies' sum is
+ * then added to g_brdf / g_irt on the same stream.
  * ws: device workspace of at least hg_backward_workspace_size(indirect, n)
  * bytes, 256-byte aligned; its contents on entry are ignored.  The table
  * gradient is scattered after sorting the encodings' points by a Morton

@@ -17,14 +17,15 @@ namespace hg {
 
 constexpr int kDelStride = 68;  // del[s][k]: 16-byte aligned rows for broadcast reads
 
-// Replicated MLP-gradient accumulators (mixed backward).  Every wave adds
-// the weight gradients of its 64 samples into one of kWRep copies of
+// Replicated MLP-gradient accumulators.  Every wave adds the weight
+// gradients of its 64 samples into one of kWRep copies of
 // [tracer W0, b0, W1, b1, W2, b2 | decoder W0, b0, W1, b1, W2, b2], picked by
 // its block index, instead of into the caller's arrays: with one copy all
 // waves add into the same 13k addresses and those atomics queue behind each
-// other (the mixed backward at 2^18 queries measured 5.2 ms that way, 3.9 ms
-// with 128 copies).  k_reduce_wrep then adds the copies' sum to the caller's
-// arrays.
+// other (the backward at 2^18 queries, 128 copies against one: BF16 MLPs
+// 3.9 against 5.2 ms, FP32 MLPs 3.56 against 3.66 ms, with FP16 tables 3.54
+// against 3.79 ms).  k_zero_wrep clears the copies first and k_reduce_wrep
+// adds their sum to the caller's arrays afterwards.
 constexpr int kWRep = 128;
 constexpr int kRepSize[12] = {kH * kNI, kH, kH * kH, kH, 2 * kH, 2, kH * kNF, kH, kH * kH, kH, 5 * kH, 5};
 constexpr int rep_off(int k) { return k == 0 ? 0 : rep_off(k - 1) + kRepSize[k - 1]; }
@@ -331,9 +332,6 @@ __device__ __forceinline__ void mlp_bwd_stored(const MlpK &m, float *const *gp, 
 // lane's own last hidden layer.
 struct F32Mlp {
     static constexpr int kLdsBytes = kWaveLds * (int)sizeof(float);
-    // its per-layer gradient flushes overlap the arithmetic (spreading them
-    // over copies measured no faster), so they go straight to the caller
-    static constexpr bool kReplicas = false;
     struct State {
         float h[kH];
     };
@@ -524,19 +522,16 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(const BwdK a) {
     const int lane = threadIdx.x & 63;
     uint8_t *lds = reinterpret_cast<uint8_t *>(lds_f) + (threadIdx.x >> 6) * MLP::kLdsBytes;
     typename MLP::State st;
-    // where this wave's MLP weight gradients go: the caller's arrays, or one
-    // of the replicated accumulators
-    float *gi_rep[6], *gb_rep[6];
-    if constexpr (MLP::kReplicas) {
+    // this wave's MLP weight gradients go to one of the replicated accumulators
+    float *gi[6], *gb[6];
+    {
         float *rep = a.ws.wrep + (size_t)(blockIdx.x & (kWRep - 1)) * kRepStride;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            gi_rep[k] = rep + rep_off(k);
-            gb_rep[k] = rep + rep_off(6 + k);
+            gi[k] = rep + rep_off(k);
+            gb[k] = rep + rep_off(6 + k);
         }
     }
-    float *const *gi = MLP::kReplicas ? gi_rep : a.gi;
-    float *const *gb = MLP::kReplicas ? gb_rep : a.gb;
     const int64_t p_raw = a.p_begin + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const RenderK &r = a.r;
     const bool live = p_raw < a.p_end;
@@ -855,23 +850,23 @@ hipError_t launch_backward(const BwdK &a, bool f16, bool bf16_mlp, bool indirect
     c.p_end = n;
     c.tiles = a.ws.tiles;
     const unsigned blocks = (unsigned)((n + kBwdThreads - 1) / kBwdThreads);
+    const int64_t n4 = (int64_t)kWRep * kRepStride / 4;
+    hipLaunchKernelGGL(k_zero_wrep, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s,
+                       reinterpret_cast<float4 *>(a.ws.wrep), n4);
     if (bf16_mlp) {
         hipLaunchKernelGGL(k_bwd_tiles, dim3((BT_N * 64 + 255) / 256), dim3(256), 0, s, a.r.irt, a.r.brdf, a.ws.tiles);
-        const int64_t n4 = (int64_t)kWRep * kRepStride / 4;
-        hipLaunchKernelGGL(k_zero_wrep, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s,
-                           reinterpret_cast<float4 *>(a.ws.wrep), n4);
         launch_k_backward<__half, Bf16Mlp>(c, indirect, blocks, s);
-        GradArrays ga;
-        for (int k = 0; k < 6; ++k) {
-            ga.p[k] = a.gi[k];
-            ga.p[6 + k] = a.gb[k];
-        }
-        hipLaunchKernelGGL(k_reduce_wrep, dim3((kRepTotal + 255) / 256), dim3(256), 0, s, a.ws.wrep, ga);
     } else if (f16) {
         launch_k_backward<__half, F32Mlp>(c, indirect, blocks, s);
     } else {
         launch_k_backward<float, F32Mlp>(c, indirect, blocks, s);
     }
+    GradArrays ga;
+    for (int k = 0; k < 6; ++k) {
+        ga.p[k] = a.gi[k];
+        ga.p[6 + k] = a.gb[k];
+    }
+    hipLaunchKernelGGL(k_reduce_wrep, dim3((kRepTotal + 255) / 256), dim3(256), 0, s, a.ws.wrep, ga);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t rn = R * n;

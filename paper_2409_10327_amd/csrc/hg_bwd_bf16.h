@@ -171,8 +171,6 @@ __device__ __forceinline__ float wave_sum(float v) {
 
 struct Bf16Mlp {
     static constexpr int kLdsBytes = Bf16Lds::BYTES;
-    // the gradient flushes go to replicated accumulators (k_backward)
-    static constexpr bool kReplicas = true;
     typedef Bf16State State;
     // Forward of one MLP (W = 0 tracer, 1 decoder) for the wave's 64 samples;
     // new_x: the first kNF inputs (features) differ from the previous call's.
