@@ -656,8 +656,15 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(const BwdK a) {
 // share a line in 7 of 8 cases on dense and hashed levels alike (the hash's
 // x factor is 1), and neighbouring points share cells and lines; at the
 // benchmark batch about 17 requests per record remain of the 256 adds.
-constexpr int kScatterThreads = 64;  // one wave per block (35 KB of LDS)
-constexpr int kLineSlots = 512;      // >= the 64 x 8 corner entries of a wave and level, so probing ends
+// The table has 256 slots (18 KB of LDS per wave, so that two waves share
+// each SIMD): a level whose lanes form at most 32 runs inserts the run sums
+// in one pass (at most 256 entries), any other level in two passes of 32
+// lanes, each pass listed and flushed before the next.
+constexpr int kScatterThreads = 64;       // one wave per block
+constexpr int kPassLanes = 32;            // lanes inserting in one pass of a level
+constexpr int kLineSlots = kPassLanes * 8;  // >= the corner entries of one pass, so probing ends
+constexpr int kSlotBits = 8;
+static_assert((1 << kSlotBits) == kLineSlots, "slot count");
 constexpr uint32_t kEmptySlot = 0xffffffffu;
 template <typename TT>
 __global__ __launch_bounds__(kScatterThreads) void k_scatter_records(const GridK g, const uint32_t *__restrict__ id,
@@ -666,7 +673,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter_records(const GridK
                                                                      float *__restrict__ g_table, int64_t n) {
     __shared__ uint32_t K[kLineSlots];        // line index (entry / 8) or empty
     __shared__ float V[kLineSlots][16];       // the line's 8 entries x 2 features
-    __shared__ uint32_t list[kLineSlots];     // occupied (line << 9 | slot) of this level
+    __shared__ uint32_t list[kLineSlots];     // occupied (line << 9 | slot) of this pass
     const int lane = threadIdx.x;
     for (int q = lane; q < kLineSlots; q += 64) {
         K[q] = kEmptySlot;
@@ -722,7 +729,8 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter_records(const GridK
         const bool head = lane == 0 || p0 != c[0] || p1 != c[1] || p2 != c[2];
         const uint64_t heads = __ballot(head);
         bool ins = live;
-        if (__popcll(heads) <= 32) {  // wave-uniform
+        const bool few = __popcll(heads) <= 32;  // wave-uniform
+        if (few) {
             const int seg = __popcll(heads & (below | (1ull << lane)));
 #pragma unroll
             for (int off = 1; off < 64; off <<= 1) {
@@ -737,67 +745,70 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter_records(const GridK
             }
             ins = head;
         }
-        if (ins) {
-            // the first probe of the eight corners in flight together, then
-            // the collisions resolved one by one; at most 512 distinct lines
-            // in 512 slots, so every probe ends
-            uint32_t h[8], prev[8];
+#pragma unroll 1
+        for (int pass = 0; pass < (few ? 1 : 64 / kPassLanes); ++pass) {
+            if (ins && (few || lane / kPassLanes == pass)) {
+                // the first probe of the eight corners in flight together,
+                // then the collisions resolved one by one; at most 256
+                // distinct lines in 256 slots, so every probe ends
+                uint32_t h[8], prev[8];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                h[k] = ((idx[k] >> 3) * 2654435761u) >> (32 - 9);
-                prev[k] = atomicCAS(&K[h[k]], kEmptySlot, idx[k] >> 3);
-            }
+                for (int k = 0; k < 8; ++k) {
+                    h[k] = ((idx[k] >> 3) * 2654435761u) >> (32 - kSlotBits);
+                    prev[k] = atomicCAS(&K[h[k]], kEmptySlot, idx[k] >> 3);
+                }
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const uint32_t ln = idx[k] >> 3;
-                while (prev[k] != kEmptySlot && prev[k] != ln) {
-                    h[k] = (h[k] + 1) & (kLineSlots - 1);
-                    prev[k] = atomicCAS(&K[h[k]], kEmptySlot, ln);
+                for (int k = 0; k < 8; ++k) {
+                    const uint32_t ln = idx[k] >> 3;
+                    while (prev[k] != kEmptySlot && prev[k] != ln) {
+                        h[k] = (h[k] + 1) & (kLineSlots - 1);
+                        prev[k] = atomicCAS(&K[h[k]], kEmptySlot, ln);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    atomicAdd(&V[h[k]][2 * (idx[k] & 7u)], vx[k]);
+                    atomicAdd(&V[h[k]][2 * (idx[k] & 7u) + 1], vy[k]);
                 }
             }
+            wave_sync();
+            // list the occupied slots (a ballot per 64 slots)
+            int cnt = 0;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                atomicAdd(&V[h[k]][2 * (idx[k] & 7u)], vx[k]);
-                atomicAdd(&V[h[k]][2 * (idx[k] & 7u) + 1], vy[k]);
+            for (int r = 0; r < kLineSlots / 64; ++r) {
+                const int q = 64 * r + lane;
+                const uint32_t ln = K[q];
+                const bool occ = ln != kEmptySlot;
+                const uint64_t m = __ballot(occ);
+                if (occ) list[cnt + __popcll(m & below)] = (ln << 9) | (uint32_t)q;
+                cnt += __popcll(m);
             }
-        }
-        wave_sync();
-        // list the occupied slots (a ballot per 64 slots)
-        int cnt = 0;
+            wave_sync();
+            // one instruction of 16 lanes per line: lane 16 j + w adds word w
+            // of the j-th listed line (four lines per instruction, four
+            // instructions with their LDS reads issued together) and clears
+            // it for the next pass
+            float *gl = g_table + 2 * ((size_t)l << g.log2T);
+            const int wd = lane & 15;
+            for (int j0 = lane >> 4; j0 < cnt; j0 += 16) {
+                uint32_t it[4];
+                float v[4];
 #pragma unroll
-        for (int r = 0; r < kLineSlots / 64; ++r) {
-            const int q = 64 * r + lane;
-            const uint32_t ln = K[q];
-            const bool occ = ln != kEmptySlot;
-            const uint64_t m = __ballot(occ);
-            if (occ) list[cnt + __popcll(m & below)] = (ln << 9) | (uint32_t)q;
-            cnt += __popcll(m);
-        }
-        wave_sync();
-        // one instruction of 16 lanes per line: lane 16 j + w adds word w of
-        // the j-th listed line (four lines per instruction, four instructions
-        // with their LDS reads issued together) and clears it for the next
-        // level
-        float *gl = g_table + 2 * ((size_t)l << g.log2T);
-        const int wd = lane & 15;
-        for (int j0 = lane >> 4; j0 < cnt; j0 += 16) {
-            uint32_t it[4];
-            float v[4];
+                for (int u = 0; u < 4; ++u) it[u] = j0 + 4 * u < cnt ? list[j0 + 4 * u] : kEmptySlot;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) it[u] = j0 + 4 * u < cnt ? list[j0 + 4 * u] : kEmptySlot;
+                for (int u = 0; u < 4; ++u) v[u] = it[u] != kEmptySlot ? V[it[u] & (kLineSlots - 1)][wd] : 0.0f;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = it[u] != kEmptySlot ? V[it[u] & (kLineSlots - 1)][wd] : 0.0f;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (it[u] != kEmptySlot) {
-                    const uint32_t q = it[u] & (kLineSlots - 1);
-                    atomic_addf(gl + 16 * (size_t)(it[u] >> 9) + wd, v[u]);
-                    V[q][wd] = 0.0f;
-                    if (wd == 0) K[q] = kEmptySlot;
+                for (int u = 0; u < 4; ++u) {
+                    if (it[u] != kEmptySlot) {
+                        const uint32_t q = it[u] & (kLineSlots - 1);
+                        atomic_addf(gl + 16 * (size_t)(it[u] >> 9) + wd, v[u]);
+                        V[q][wd] = 0.0f;
+                        if (wd == 0) K[q] = kEmptySlot;
+                    }
                 }
             }
+            wave_sync();
         }
-        wave_sync();
     }
 }
 
