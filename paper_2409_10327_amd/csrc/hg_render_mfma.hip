@@ -79,9 +79,12 @@ __device__ __forceinline__ WSrc wsrc(const RenderK &a) {
 }
 
 // ============================================================================
-// Mixed path: BF16 operands, K = 32 per matrix-core step.
+// Mixed path: BF16 operands, K = 32 per matrix-core step.  FENCED: the
+// tracer's matrix-core steps form a scheduling region of their own, at raised
+// issue priority (the launch picks the variant per grid).
 // ============================================================================
-struct Bf16Path {
+template <bool FENCED>
+struct Bf16PathT {
     typedef __half Table;
     enum : int {
         T_W0W = 0, T_W0F = 4, T_W1 = 8, T_W2 = 16,       // tracer
@@ -212,11 +215,12 @@ struct Bf16Path {
     static __device__ __forceinline__ f32x4 tracer_nt(const Tracer &T, const Tile *tiles, const Wave &W, int buf, int nt,
                                                       int lane, const f32x4 (&c)[4]) {
         const uint4 ob_ = W.om[buf][16 * nt + (lane & 15)];
-        // raised issue priority over the tracer's matrix-core steps, so that
-        // the SIMD's other wave fills their gaps with its vector work instead
-        // of delaying them (raising it over the decoder and the point part
-        // too starved the other wave's encoder: slower)
-        __builtin_amdgcn_s_setprio(1);
+        // FENCED: raised issue priority over the tracer's matrix-core steps,
+        // so that the SIMD's other wave fills their gaps with its vector work
+        // instead of delaying them (raising it over the decoder and the point
+        // part too starved the other wave's encoder: slower); the priority
+        // changes also bound a scheduling region, which is most of the effect
+        if constexpr (FENCED) __builtin_amdgcn_s_setprio(1);
         f32x4 d[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) d[m] = mfma_bf16(tiles[(T_W0W + m) * 64 + lane], ob_, c[m]);
@@ -230,7 +234,7 @@ struct Bf16Path {
         const uint4 k0 = act_pack(e[0], e[1]), k1 = act_pack(e[2], e[3]);
         f32x4 o = mfma_bf16(tiles[T_W2 * 64 + lane], k0, ftile(tiles, T_B2, lane));
         o = mfma_bf16(tiles[(T_W2 + 1) * 64 + lane], k1, o);
-        __builtin_amdgcn_s_setprio(0);
+        if constexpr (FENCED) __builtin_amdgcn_s_setprio(0);
         return o;
     }
 
@@ -1286,8 +1290,15 @@ static hipError_t launch_mma(const RenderK &a, bool indirect, bool query, hipStr
     return hipGetLastError();
 }
 
+// The fenced tracer pays on grids whose finest resolution is moderate (finest
+// 2048: the 800x800 frame at N = 128 36.3 -> 33.6 ms) and costs on very fine
+// ones (finest 131072, the paper's grid: 35.4 -> 39.1 ms), whatever the table
+// size (2^17 .. 2^21 entries per level measured); the switch sits between the
+// two measured finest resolutions.
 hipError_t launch_render_mixed(const RenderK &a, bool indirect, bool query, hipStream_t s) {
-    return launch_mma<Bf16Path>(a, indirect, query, s);
+    const bool very_fine = a.g.L > 0 && a.g.resf[a.g.L - 1] > 16384.0f;
+    return very_fine ? launch_mma<Bf16PathT<false>>(a, indirect, query, s)
+                     : launch_mma<Bf16PathT<true>>(a, indirect, query, s);
 }
 
 hipError_t launch_render_f32_mma(const RenderK &a, bool indirect, bool query, hipStream_t s) {
