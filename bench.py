@@ -444,19 +444,13 @@ def main():
         vs_ = [torch.zeros_like(p) for p in params]
         step = [0]
 
-        def morton_order(p):
-            # batch order along a Morton curve (21 bits per axis over the hash
-            # grid's domain box, no reduction over the batch): queries of a
-            # wave then share cells down to finer levels
-            q = ((p - H.BOX_LO) * ((1 << 21) / H.BOX_EXTENT)).long().clamp_(0, (1 << 21) - 1)
+        # batch order along a Morton curve (hg_morton_order: 21 bits per axis over
+        # the hash grid's domain box, no reduction over the batch): queries of a
+        # wave then share cells down to finer levels
+        morton_ws = torch.empty(hg.lib().hg_morton_order_workspace_size(1 << 20), device=dev, dtype=torch.uint8)
 
-            def spread(v):
-                v = (v | (v << 32)) & 0x1F00000000FFFF
-                v = (v | (v << 16)) & 0x1F0000FF0000FF
-                v = (v | (v << 8)) & 0x100F00F00F00F00F
-                v = (v | (v << 4)) & 0x10C30C30C30C30C3
-                return (v | (v << 2)) & 0x1249249249249249
-            return torch.argsort(spread(q[:, 0]) | (spread(q[:, 1]) << 1) | (spread(q[:, 2]) << 2))
+        def morton_order(p):
+            return hg.morton_order(r, p, ws=morton_ws)
 
         def train_step():
             # a training loop draws a new batch each step: its ordering is part of the step

@@ -245,6 +245,30 @@ hg_status hg_backward(const hg_model *model, const hg_env *env, const hg_samplin
                       float *const g_brdf[6], float *const g_irt[6], float *g_pos,
                       void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Workspace bytes hg_morton_order needs for n points: two 8-byte keys and a
+ * 4-byte index per point, plus the radix sort's temporary storage.  0 for
+ * n <= 0 or n >= 2^31. */
+size_t hg_morton_order_workspace_size(int64_t n);
+
+/* Order of n points along a Z-order (Morton) curve over the grid's domain
+ * box: a locality aid for the random batches of the distillation step
+ * (Sec. 3.3), not part of the method.  A batch rendered and differentiated
+ * in this order gives each wave neighbouring points, whose table gathers and
+ * gradient adds share cells and cache lines.  pos [n][3] FP32 device; the
+ * cell along an axis is trunc((p - box_lo) * 2^21 / box_extent) clamped to
+ * [0, 2^21 - 1] (FP32 arithmetic; a NaN coordinate takes cell 0), the key
+ * interleaves the bits of the x, y, z cells (x lowest), and the sort is
+ * stable.  Writes perm [n] (int32): perm[i] is the index of the i-th point
+ * in key order, equal keys in ascending index.  box_lo, box_extent as in
+ * hg_grid (extent a power of two).  ws: device workspace of at least
+ * hg_morton_order_workspace_size(n) bytes, 256-byte aligned, contents on
+ * entry ignored.  Errors: HG_E_INVALID for n outside [0, 2^31 - 1], a bad
+ * box, a missing or misaligned pointer or a small workspace; HG_E_WORKSPACE
+ * if the sort would need more temporary storage than the size query
+ * reserved.  n = 0 returns HG_OK without touching the pointers. */
+hg_status hg_morton_order(const float *pos, int64_t n, float box_lo, float box_extent, int32_t *perm,
+                          void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* L2 distillation loss (squared-error reading of Sec. 3.3's losses):
  *   loss = 1/n sum_p [ |rgb_p - t_p[0:3]|^2 + (vis_p - t_p[3])^2 +
  *                      (depth_p - t_p[4])^2 ],

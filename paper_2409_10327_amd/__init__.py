@@ -64,7 +64,7 @@ class Points(C.Structure):
 
 
 EXPORTS = ["hg_encode", "hg_encode_index", "hg_render_direct", "hg_render_indirect", "hg_backward",
-           "hg_backward_workspace_size", "hg_l2_loss",
+           "hg_backward_workspace_size", "hg_morton_order", "hg_morton_order_workspace_size", "hg_l2_loss",
            "hg_adam_step", "hg_denoise", "hg_denoise_noalloc", "hg_denoise_workspace_size", "hg_env_build_sampling",
            "hg_env_sampling_size", "hg_last_error"]
 
@@ -100,6 +100,10 @@ def lib():
                                   C.c_void_p * 6, C.c_void_p * 6, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
         L.hg_backward_workspace_size.restype = C.c_size_t
         L.hg_backward_workspace_size.argtypes = [C.c_int32, C.c_int64]
+        L.hg_morton_order_workspace_size.restype = C.c_size_t
+        L.hg_morton_order_workspace_size.argtypes = [C.c_int64]
+        L.hg_morton_order.argtypes = [C.c_void_p, C.c_int64, C.c_float, C.c_float, C.c_void_p, C.c_void_p,
+                                      C.c_size_t, C.c_void_p]
         L.hg_l2_loss.argtypes = [C.c_void_p] * 4 + [C.c_int64] + [C.c_void_p] * 5
         L.hg_adam_step.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
                                    C.c_float, C.c_float, C.c_float, C.c_float, C.c_float, C.c_void_p, C.c_int32,
@@ -340,6 +344,24 @@ def backward(r: HashRenderer, env, pos, dirs, g_rgb, g_vis, g_dep, grads, n_dirs
     _check(lib().hg_backward(C.byref(m), C.byref(e), C.byref(s), C.byref(p), int(indirect), _ptr(g_rgb),
                              _ptr(g_vis), _ptr(g_dep), _ptr(grads["table"]), gb, gi, _ptr(g_pos),
                              _ptr(ws) if need else None, need, _stream(pos.device)))
+
+
+def morton_order(r: HashRenderer, pos, ws=None):
+    """int32 permutation of the points pos [n][3] along a Z-order curve over
+    the renderer's grid box (hg_morton_order); ws: optional uint8 device
+    workspace of hg_morton_order_workspace_size bytes."""
+    if pos.dim() != 2 or pos.shape[1] != 3 or pos.dtype != torch.float32 or not pos.is_contiguous():
+        raise ValueError("pos must be a contiguous float32 [n][3] tensor")
+    n = pos.shape[0]
+    perm = torch.empty(n, device=pos.device, dtype=torch.int32)
+    if n == 0:
+        return perm
+    need = lib().hg_morton_order_workspace_size(n)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, device=pos.device, dtype=torch.uint8)
+    _check(lib().hg_morton_order(_ptr(pos), n, r.box_lo, r.box_extent, _ptr(perm), _ptr(ws), need,
+                                 _stream(pos.device)))
+    return perm
 
 
 def l2_loss(rgb, vis, dep, tgt):

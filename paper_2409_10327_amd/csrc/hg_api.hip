@@ -369,6 +369,37 @@ hg_status hg_backward(const hg_model *model, const hg_env *env, const hg_samplin
                       "hg_backward");
 }
 
+// Bound on the radix sort's temporary storage that
+// hg_morton_order_workspace_size reserves (checked at call time).
+static size_t morton_sort_bound(int64_t n) { return (size_t(2) << 20) + (size_t)n * 16; }
+
+size_t hg_morton_order_workspace_size(int64_t n) {
+    if (n <= 0 || n > INT32_MAX) return 0;
+    return hg::morton_ws_layout(n, morton_sort_bound(n));
+}
+
+hg_status hg_morton_order(const float *pos, int64_t n, float box_lo, float box_extent, int32_t *perm, void *ws,
+                          size_t ws_bytes, hipStream_t stream) {
+    g_err.clear();
+    REQUIRE(n >= 0 && n <= INT32_MAX, "n = %lld outside [0, 2^31 - 1]", (long long)n);
+    REQUIRE(std::isfinite(box_lo), "box_lo is not finite");
+    int ex = 0;
+    const float mant = std::frexp(box_extent, &ex);
+    REQUIRE(box_extent > 0.0f && mant == 0.5f, "box_extent %g is not a power of two", (double)box_extent);
+    if (n == 0) return HG_OK;
+    CHECK(check_ptr(pos, "pos", 4));
+    CHECK(check_ptr(perm, "perm", 4));
+    CHECK(check_ptr(ws, "ws", 256));
+    REQUIRE(ws_bytes >= hg_morton_order_workspace_size(n), "ws_bytes %zu < hg_morton_order_workspace_size %zu",
+            ws_bytes, hg_morton_order_workspace_size(n));
+    size_t tmp = 0;
+    CHECK(hip_status(hg::morton_sort_bytes(n, tmp), "hg_morton_order: sort size"));
+    if (tmp > morton_sort_bound(n))
+        return fail(HG_E_WORKSPACE, "sort needs %zu bytes, above the reserved %zu", tmp, morton_sort_bound(n));
+    return hip_status(hg::launch_morton_order(pos, n, box_lo, box_extent, perm, ws, morton_sort_bound(n), stream),
+                      "hg_morton_order");
+}
+
 hg_status hg_l2_loss(const float *rgb, const float *vis, const float *depth, const float *tgt, int64_t n,
                      float *loss, float *g_rgb, float *g_vis, float *g_depth, hipStream_t stream) {
     g_err.clear();

@@ -19,7 +19,7 @@ def header_symbols():
 
 def test_library_exports_every_declared_symbol():
     syms = header_symbols()
-    assert len(syms) == 14, syms
+    assert len(syms) == 16, syms
     L = hg.lib()
     for s in syms:
         assert hasattr(L, s), s
@@ -192,6 +192,18 @@ def test_other_entry_points_validate():
     assert L.hg_encode(C.byref(g), None, 0, None, None) == hg.HG_OK
     assert L.hg_encode_index(C.byref(g), C.c_void_p(FAKE), 10, None, None, None) == hg.HG_E_INVALID
     assert L.hg_l2_loss(None, None, None, None, 5, C.c_void_p(FAKE), None, None, None, None) == hg.HG_E_INVALID
+    need = L.hg_morton_order_workspace_size(10)
+    assert need > 0 and L.hg_morton_order_workspace_size(0) == 0 and L.hg_morton_order_workspace_size(-1) == 0
+    assert L.hg_morton_order_workspace_size(1 << 31) == 0
+    f = C.c_void_p(FAKE)
+    assert L.hg_morton_order(None, 0, -8.0, 16.0, None, None, 0, None) == hg.HG_OK
+    assert L.hg_morton_order(f, -1, -8.0, 16.0, f, f, need, None) == hg.HG_E_INVALID
+    assert L.hg_morton_order(f, 10, -8.0, 12.0, f, f, need, None) == hg.HG_E_INVALID  # extent not 2^k
+    assert L.hg_morton_order(f, 10, float("nan"), 16.0, f, f, need, None) == hg.HG_E_INVALID
+    assert L.hg_morton_order(None, 10, -8.0, 16.0, f, f, need, None) == hg.HG_E_INVALID
+    assert L.hg_morton_order(f, 10, -8.0, 16.0, None, f, need, None) == hg.HG_E_INVALID
+    assert L.hg_morton_order(f, 10, -8.0, 16.0, f, C.c_void_p(FAKE + 16), need, None) == hg.HG_E_INVALID
+    assert L.hg_morton_order(f, 10, -8.0, 16.0, f, f, need - 1, None) == hg.HG_E_INVALID
     assert L.hg_adam_step(C.c_void_p(FAKE), C.c_void_p(FAKE), C.c_void_p(FAKE), C.c_void_p(FAKE), 10, 0,
                           1e-3, 0.9, 0.999, 1e-8, 0.0, None, 0, None) == hg.HG_E_INVALID
     assert L.hg_adam_step(C.c_void_p(FAKE), C.c_void_p(FAKE), C.c_void_p(FAKE), C.c_void_p(FAKE), 10, 1,

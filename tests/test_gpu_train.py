@@ -303,3 +303,41 @@ def test_backward_bf16_parity(setup, indirect, n):
         print(f"  {name}: rel {e:.3g} cos {c:.5f}")
         assert np.all(np.isfinite(a)), name
         assert c >= 0.97 and e <= 0.3, (name, e, c)
+
+
+def _morton63_ref(pos, lo, extent):
+    """Keys of hg_morton_order written out in numpy: the FP32 cell per axis
+    (subtract, then multiply by the power of two 2^21 / extent: both steps
+    round as on the GPU), clamped, NaN to cell 0, bits interleaved x lowest."""
+    f = (pos - np.float32(lo)) * np.float32(2.0 ** 21 / extent)
+    f = np.where(np.isnan(f), np.float32(0), f)
+    q = np.clip(f, 0, 2 ** 21 - 1).astype(np.uint64)
+    key = np.zeros(pos.shape[0], np.uint64)
+    for d in range(3):
+        for b in range(21):
+            key |= ((q[:, d] >> np.uint64(b)) & np.uint64(1)) << np.uint64(3 * b + d)
+    return key
+
+
+@pytest.mark.parametrize("n", [1, 7, 1000, 262147])
+def test_morton_order_is_stable_key_order(n):
+    rng = np.random.default_rng(n)
+    pos = rng.uniform(-1.0, 1.0, (n, 3)).astype(np.float32)
+    if n >= 7:
+        # outside the box, on its faces, non-finite, and repeated points (ties)
+        pos[0] = (-9.0, 9.0, 0.0)
+        pos[1] = (-8.0, 8.0, 7.9999995)
+        pos[2] = (np.nan, 0.5, -0.5)
+        pos[3] = (np.inf, -np.inf, 0.0)
+        pos[5] = pos[4]
+        pos[6] = pos[4]
+    r = hg.HashRenderer(H.make_model(H.config("c1")), "cuda")
+    perm = hg.morton_order(r, torch.from_numpy(pos).cuda()).cpu().numpy()
+    ref = np.argsort(_morton63_ref(pos, r.box_lo, r.box_extent), kind="stable")
+    assert perm.dtype == np.int32
+    assert np.array_equal(perm, ref.astype(np.int32))
+
+
+def test_morton_order_empty():
+    r = hg.HashRenderer(H.make_model(H.config("c1")), "cuda")
+    assert hg.morton_order(r, torch.empty((0, 3), device="cuda")).numel() == 0
