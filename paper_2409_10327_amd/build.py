@@ -15,7 +15,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhg.so")
 
-SOURCES = ["hg_api.hip", "hg_render.hip", "hg_render_mfma.hip", "hg_backward.hip", "hg_train.hip", "hg_denoise.hip", "hg_mis.hip"]
+SOURCES = ["hg_api.hip", "hg_render.hip", "hg_render_mfma.hip", "hg_backward.hip", "hg_order.hip", "hg_train.hip", "hg_denoise.hip", "hg_mis.hip"]
 # microbenchmarks of the measured ceilings (gathers, atomics, matrix cores): a library of their own
 MB_SOURCES = ["hg_membench.hip"]
 MB_LIB = os.path.join(HERE, "libhg_membench.so")

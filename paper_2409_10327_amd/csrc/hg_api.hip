@@ -12,6 +12,7 @@
 
 #include "../../include/hg.h"
 #include "hg_launch.h"
+#include "hg_order.h"
 
 namespace {
 

@@ -69,11 +69,6 @@ struct BwdK {
 size_t backward_ws_layout(int64_t n, int R, size_t sort_tmp_bytes, void *base, BounceWs *ws);
 // Temporary bytes the radix sort of `records` keys needs (a host query).
 hipError_t backward_sort_bytes(int64_t records, size_t &bytes);
-// Z-order of a batch of points (hg_morton_order)
-hipError_t morton_sort_bytes(int64_t n, size_t &bytes);
-size_t morton_ws_layout(int64_t n, size_t sort_tmp_bytes);
-hipError_t launch_morton_order(const float *pos, int64_t n, float lo, float extent, int32_t *perm, void *ws,
-                               size_t sort_tmp_bytes, hipStream_t s);
 
 hipError_t launch_encode(const GridK &g, bool f16, const float *pos, int64_t n, float *feat, hipStream_t s);
 hipError_t launch_encode_index(const GridK &g, const float *pos, int64_t n, uint32_t *idx, float *w, hipStream_t s);
