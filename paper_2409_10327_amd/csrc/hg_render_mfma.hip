@@ -1297,14 +1297,18 @@ static hipError_t launch_mma(const RenderK &a, bool indirect, bool query, hipStr
 }
 
 // The fenced tracer pays on grids whose finest resolution is moderate (finest
-// 2048: the 800x800 frame at N = 128 36.3 -> 33.6 ms) and costs on very fine
-// ones (finest 131072, the paper's grid: 35.4 -> 39.1 ms), whatever the table
-// size (2^17 .. 2^21 entries per level measured); the switch sits between the
-// two measured finest resolutions.
+// 2048: the 800x800 frame at N = 128 34.6 -> 33.6 ms against the unfenced
+// variant, N = 32 and 64 likewise) and costs on very fine ones (finest 131072,
+// the paper's grid: 33.4 -> 39.1 ms), whatever the table size (2^17 .. 2^21
+// entries per level measured), and at 256 or more directions per pixel, where
+// a pixel's set-up is shared by four or more chunks (N = 256 65.1 against
+// 65.6 ms, N = 512 122.8 against 126.0 ms).  The resolution switch sits
+// between the two measured finest resolutions.
 hipError_t launch_render_mixed(const RenderK &a, bool indirect, bool query, hipStream_t s) {
     const bool very_fine = a.g.L > 0 && a.g.resf[a.g.L - 1] > 16384.0f;
-    return very_fine ? launch_mma<Bf16PathT<false>>(a, indirect, query, s)
-                     : launch_mma<Bf16PathT<true>>(a, indirect, query, s);
+    const bool many_dirs = !query && a.s.n_dirs >= 256;
+    return very_fine || many_dirs ? launch_mma<Bf16PathT<false>>(a, indirect, query, s)
+                                  : launch_mma<Bf16PathT<true>>(a, indirect, query, s);
 }
 
 hipError_t launch_render_f32_mma(const RenderK &a, bool indirect, bool query, hipStream_t s) {
