@@ -571,7 +571,7 @@ def main():
             a5 = FLOP_PER_QUERY * P * N5 / (ms5 * 1e-3) / 1e12
             out["mixed_n512_train_2e20"] = {
                 "frame_ms": ms5, "frame_queries_per_s": P * N5 / (ms5 * 1e-3), "frame_px_per_s": P / (ms5 * 1e-3),
-                "frame_roofline": {"bound": "mfma", "kernel": "k_render_mma<Bf16PathT<true>, indirect, shade>",
+                "frame_roofline": {"bound": "mfma", "kernel": "k_render_mma<Bf16PathT<false>, indirect, shade>",
                                    "achieved": a5, "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                                    "frac": a5 / BF16_MFMA_PEAK_TFLOPS},
                 "train_ms": ms5t, "train_samples_per_s": B5 / (ms5t * 1e-3),
