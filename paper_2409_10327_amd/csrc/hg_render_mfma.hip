@@ -32,10 +32,13 @@
 // wave's 64 queries in two halves of 32 points (bounce_lo_half); the mixed
 // path runs two 256-thread blocks per CU with the whole-wave bounce
 // (bounce_lo) and reads its tracer operands from LDS at each use instead of
-// holding them in registers.  In both paths a wave raises its issue
-// priority for the tracer's matrix-core steps, so that the vector work of
-// the SIMD's other wave fills the matrix pipe's gaps rather than delaying
-// its next step.
+// holding them in registers.  The FP32 path, and the mixed one on moderate
+// grids below 256 directions per pixel, raise a wave's issue priority for
+// the tracer's matrix-core steps, so that the vector work of the SIMD's
+// other wave fills the matrix pipe's gaps rather than delaying its next
+// step; the priority changes also bound a scheduling region, which is most
+// of their effect.  The mixed path is compiled with and without that fence
+// (Bf16PathT<FENCED>) and launch_render_mixed picks the variant.
 #include "hg_bf16.h"
 #include "hg_device.h"
 #include "hg_launch.h"
@@ -81,7 +84,8 @@ __device__ __forceinline__ WSrc wsrc(const RenderK &a) {
 // ============================================================================
 // Mixed path: BF16 operands, K = 32 per matrix-core step.  FENCED: the
 // tracer's matrix-core steps form a scheduling region of their own, at raised
-// issue priority (the launch picks the variant per grid).
+// issue priority (the launch picks the variant per grid and direction
+// count).
 // ============================================================================
 template <bool FENCED>
 struct Bf16PathT {
