@@ -9,18 +9,22 @@ __global__ void k_zero1(float *p) { *p = 0.0f; }
 
 // Per-sample squared errors; the gradient is elementwise (deterministic),
 // the scalar loss is a wave reduction followed by one atomic per wave.
+// One atomic add per block into the loss (a grid of at most kLossBlocks
+// blocks, each striding over the samples): adds on one address serialise,
+// about 13 ns each, so one per wave cost 55 us at 2^18 samples.
+constexpr unsigned kLossBlocks = 512;
 __global__ __launch_bounds__(256) void k_l2_loss(const float *__restrict__ rgb, const float *__restrict__ vis,
                                                  const float *__restrict__ dep, const float *__restrict__ tgt,
                                                  int64_t n, float inv_n, float *loss, float *g_rgb, float *g_vis,
                                                  float *g_dep) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ float part[4];
     float l = 0.0f;
-    if (p < n) {
+    const float s = 2.0f * inv_n;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
         const float *t = tgt + 5 * p;
         const float e0 = rgb[3 * p] - t[0], e1 = rgb[3 * p + 1] - t[1], e2 = rgb[3 * p + 2] - t[2];
         const float ev = vis[p] - t[3], ed = dep[p] - t[4];
-        l = e0 * e0 + e1 * e1 + e2 * e2 + ev * ev + ed * ed;
-        const float s = 2.0f * inv_n;
+        l += e0 * e0 + e1 * e1 + e2 * e2 + ev * ev + ed * ed;
         g_rgb[3 * p] = s * e0;
         g_rgb[3 * p + 1] = s * e1;
         g_rgb[3 * p + 2] = s * e2;
@@ -28,14 +32,17 @@ __global__ __launch_bounds__(256) void k_l2_loss(const float *__restrict__ rgb, 
         g_dep[p] = s * ed;
     }
     for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off);
-    if ((threadIdx.x & 63) == 0) unsafeAtomicAdd(loss, l * inv_n);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = l;
+    __syncthreads();
+    if (threadIdx.x == 0) unsafeAtomicAdd(loss, (part[0] + part[1] + part[2] + part[3]) * inv_n);
 }
 
 hipError_t launch_l2_loss(const float *rgb, const float *vis, const float *dep, const float *tgt, int64_t n,
                           float *loss, float *g_rgb, float *g_vis, float *g_dep, hipStream_t s) {
     hipLaunchKernelGGL(k_zero1, dim3(1), dim3(1), 0, s, loss);
     if (n > 0) {
-        const unsigned blocks = (unsigned)((n + 255) / 256);
+        const int64_t want = (n + 255) / 256;
+        const unsigned blocks = (unsigned)(want < (int64_t)kLossBlocks ? want : (int64_t)kLossBlocks);
         hipLaunchKernelGGL(k_l2_loss, dim3(blocks), dim3(256), 0, s, rgb, vis, dep, tgt, n, 1.0f / (float)n, loss,
                            g_rgb, g_vis, g_dep);
     }

@@ -107,9 +107,9 @@ def test_gpu_gradients_vs_central_differences(setup):
     assert checked >= 48, checked
 
 
-def test_l2_loss_parity(setup):
+@pytest.mark.parametrize("n", [1, 1 << 14, 300001])  # 300001: more samples than threads of the capped grid
+def test_l2_loss_parity(setup, n):
     t = setup["t"]
-    n = 1 << 14
     rng = np.random.default_rng(2)
     rgb = rng.standard_normal((n, 3)).astype(np.float32)
     vis = rng.uniform(0, 1, n).astype(np.float32)
