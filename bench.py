@@ -457,15 +457,18 @@ def main():
             step[0] += 1
             order = morton_order(bp_t)
             sp, sd, st = bp_t[order], bd_t[order], tgt[order]
-            for g in gl:
-                g.zero_()
             rgb_, vis_, dep_ = hg.render(r, env_t, sp, dirs=sd)
             loss, g_rgb, g_vis, g_dep = hg.l2_loss(rgb_, vis_, dep_, st)
             hg.backward(r, env_t, sp, sd, g_rgb, g_vis, g_dep, grads)
-            for i, (p_, g_) in enumerate(zip(params, gl)):
-                hg.adam_step(p_, g_, ms_[i], vs_[i], step[0], lr=2e-3, weight_decay=0.0 if i == 0 else 1e-6)
+            # Adam over the 13 arrays in one launch, clearing each gradient
+            # after use for the next step's backward
+            hg.adam_step_multi(adam_fp32, step[0], lr=2e-3, zero_grad=True)
             return loss
 
+        adam_fp32 = hg.AdamGroup([(p_, g_, ms_[i], vs_[i], 0.0 if i == 0 else 1e-6, None)
+                                  for i, (p_, g_) in enumerate(zip(params, gl))])
+        for g in gl:  # cleared once; every step leaves them cleared
+            g.zero_()
         mst, _, _ = time_events(train_step, max(5, args.steps), 2, torch)
         out["train"] = {"samples_per_s": B / (mst * 1e-3), "ms_per_step": mst, "batch": B,
                         "secondary_queries_per_s_fwd_bwd": B / (mst * 1e-3), "dtype": "f32"}
@@ -527,16 +530,16 @@ def main():
             step[0] += 1
             order = morton_order(bp_t)
             sp, sd, st = bp_t[order], bd_t[order], tgt[order]
-            for g in gl:
-                g.zero_()
             rgb_, vis_, dep_ = hg.render(r, env_t, sp, dirs=sd, precision="mixed")
             loss, g_rgb, g_vis, g_dep = hg.l2_loss(rgb_, vis_, dep_, st)
             hg.backward(r, env_t, sp, sd, g_rgb, g_vis, g_dep, grads, precision="mixed")
-            for i, (p_, g_) in enumerate(zip(params, gl)):
-                hg.adam_step(p_, g_, ms_[i], vs_[i], step[0], lr=2e-3, weight_decay=0.0 if i == 0 else 1e-6,
-                             shadow=shadows[i])
+            hg.adam_step_multi(adam_mixed, step[0], lr=2e-3, zero_grad=True)
             return loss
 
+        adam_mixed = hg.AdamGroup([(p_, g_, ms_[i], vs_[i], 0.0 if i == 0 else 1e-6, shadows[i])
+                                   for i, (p_, g_) in enumerate(zip(params, gl))])
+        for g in gl:  # the backward roofline above added into them
+            g.zero_()
         mstm, _, _ = time_events(train_step_mixed, max(5, args.steps), 2, torch)
         out["train"]["mixed"] = {"samples_per_s": B / (mstm * 1e-3), "ms_per_step": mstm,
                                  "dtype": "bf16-mfma fwd+bwd / f16 tables / f32 masters and gradients"}
@@ -567,6 +570,8 @@ def main():
             trgb, tvis, tdep = hg.render(teacher, env_t, bp_t, dirs=bd_t)
             tgt = torch.cat([trgb, tvis[:, None], tdep[:, None]], 1).contiguous()
             del teacher, trgb, tvis, tdep
+            for g in gl:  # the backward roofline above added into them
+                g.zero_()
             ms5t, _, _ = time_events(train_step_mixed, max(2, args.steps // 2), 1, torch)
             a5 = FLOP_PER_QUERY * P * N5 / (ms5 * 1e-3) / 1e12
             out["mixed_n512_train_2e20"] = {

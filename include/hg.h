@@ -290,6 +290,33 @@ hg_status hg_adam_step(float *param, const float *grad, float *m, float *v, int6
                        float weight_decay, void *shadow, hg_dtype shadow_dtype,
                        hipStream_t stream);
 
+/* One tensor of hg_adam_step_multi: the arrays and size of one
+ * hg_adam_step call, its weight decay and optional shadow. */
+#define HG_ADAM_MAX_TENSORS 16
+typedef struct hg_adam_tensor {
+    float *param;
+    float *grad;
+    float *m;
+    float *v;
+    int64_t n;
+    float weight_decay;
+    hg_dtype shadow_dtype; /* HG_F16 or HG_BF16 when shadow is not NULL */
+    void *shadow;
+} hg_adam_tensor;
+
+/* The Adam step of hg_adam_step for up to HG_ADAM_MAX_TENSORS tensors (the
+ * table and the twelve MLP arrays of a model) in one launch, with the same
+ * arithmetic per element (bit-identical results).  With zero_grad = 1 each
+ * gradient is cleared after it is read, so the next hg_backward can add
+ * into it without a separate clearing pass.  tensors: HOST array of count
+ * descriptors.  Errors: HG_E_INVALID for count outside [0, 16], zero_grad
+ * not 0/1, step < 1, betas outside [0, 1), a non-finite hyper-parameter or
+ * weight decay, n outside [0, 2^36], a missing or misaligned array, a bad
+ * shadow dtype.  count = 0 returns HG_OK. */
+hg_status hg_adam_step_multi(const hg_adam_tensor *tensors, int32_t count, int32_t step, float lr,
+                             float beta1, float beta2, float eps, int32_t zero_grad,
+                             hipStream_t stream);
+
 /* Spatial variance-guided a-trous filter of a rendered frame: SVGF without
  * its temporal parts, as the paper applies it to the Monte Carlo result
  * (Sec. 4.1); the depth gradient for the edge-stopping weight is a finite

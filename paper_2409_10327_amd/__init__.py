@@ -64,7 +64,7 @@ class Points(C.Structure):
 
 
 EXPORTS = ["hg_encode", "hg_encode_index", "hg_render_direct", "hg_render_indirect", "hg_backward",
-           "hg_backward_workspace_size", "hg_morton_order", "hg_morton_order_workspace_size", "hg_l2_loss",
+           "hg_backward_workspace_size", "hg_morton_order", "hg_morton_order_workspace_size", "hg_l2_loss", "hg_adam_step_multi",
            "hg_adam_step", "hg_denoise", "hg_denoise_noalloc", "hg_denoise_workspace_size", "hg_env_build_sampling",
            "hg_env_sampling_size", "hg_last_error"]
 
@@ -105,6 +105,8 @@ def lib():
         L.hg_morton_order.argtypes = [C.c_void_p, C.c_int64, C.c_float, C.c_float, C.c_void_p, C.c_void_p,
                                       C.c_size_t, C.c_void_p]
         L.hg_l2_loss.argtypes = [C.c_void_p] * 4 + [C.c_int64] + [C.c_void_p] * 5
+        L.hg_adam_step_multi.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float,
+                                         C.c_float, C.c_int32, C.c_void_p]
         L.hg_adam_step.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
                                    C.c_float, C.c_float, C.c_float, C.c_float, C.c_float, C.c_void_p, C.c_int32,
                                    C.c_void_p]
@@ -362,6 +364,40 @@ def morton_order(r: HashRenderer, pos, ws=None):
     _check(lib().hg_morton_order(_ptr(pos), n, r.box_lo, r.box_extent, _ptr(perm), _ptr(ws), need,
                                  _stream(pos.device)))
     return perm
+
+
+class AdamTensor(C.Structure):
+    _fields_ = [("param", C.c_void_p), ("grad", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p),
+                ("n", C.c_int64), ("weight_decay", C.c_float), ("shadow_dtype", C.c_int32), ("shadow", C.c_void_p)]
+
+
+ADAM_MAX_TENSORS = 16
+
+
+class AdamGroup:
+    """The descriptors of hg_adam_step_multi for a fixed list of (param,
+    grad, m, v, weight_decay, shadow) tuples (shadow None, or an FP16 / BF16
+    tensor of param's size), built once and reused every step."""
+
+    def __init__(self, tensors):
+        if len(tensors) > ADAM_MAX_TENSORS:
+            raise ValueError(f"at most {ADAM_MAX_TENSORS} tensors per group")
+        self.tensors = list(tensors)  # keeps the tensors alive
+        self.arr = (AdamTensor * max(1, len(tensors)))()
+        self.count = len(tensors)
+        self.device = tensors[0][0].device if tensors else None
+        for i, (p, g, m_, v_, wd, sh) in enumerate(tensors):
+            dt = 0 if sh is None else (HG_F16 if sh.dtype == torch.float16 else HG_BF16)
+            self.arr[i] = AdamTensor(p.data_ptr(), g.data_ptr(), m_.data_ptr(), v_.data_ptr(), p.numel(), wd, dt,
+                                     None if sh is None else sh.data_ptr())
+
+
+def adam_step_multi(tensors, step, lr=2e-3, beta1=0.9, beta2=0.999, eps=1e-8, zero_grad=False):
+    """hg_adam_step_multi over an AdamGroup or a list of (param, grad, m, v,
+    weight_decay, shadow) tuples."""
+    grp = tensors if isinstance(tensors, AdamGroup) else AdamGroup(tensors)
+    _check(lib().hg_adam_step_multi(grp.arr, grp.count, step, lr, beta1, beta2, eps, int(bool(zero_grad)),
+                                    _stream(grp.device)))
 
 
 def l2_loss(rgb, vis, dep, tgt):

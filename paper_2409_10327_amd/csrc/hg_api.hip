@@ -13,6 +13,7 @@
 #include "../../include/hg.h"
 #include "hg_launch.h"
 #include "hg_order.h"
+#include "hg_train.h"
 
 namespace {
 
@@ -444,6 +445,60 @@ hg_status hg_adam_step(float *param, const float *grad, float *m, float *v, int6
     return hip_status(hg::launch_adam(param, grad, m, v, n, lr, beta1, beta2, eps, weight_decay, (float)bc1,
                                       (float)bc2, shadow, kind, stream),
                       "hg_adam_step");
+}
+
+static_assert(HG_ADAM_MAX_TENSORS == hg::kAdamMax, "tensor count per launch");
+
+hg_status hg_adam_step_multi(const hg_adam_tensor *tensors, int32_t count, int32_t step, float lr, float beta1,
+                             float beta2, float eps, int32_t zero_grad, hipStream_t stream) {
+    g_err.clear();
+    REQUIRE(count >= 0 && count <= HG_ADAM_MAX_TENSORS, "count = %d outside [0, %d]", count, HG_ADAM_MAX_TENSORS);
+    REQUIRE(zero_grad == 0 || zero_grad == 1, "zero_grad must be 0 or 1");
+    REQUIRE(step >= 1, "step = %d must be >= 1", step);
+    REQUIRE(std::isfinite(lr) && std::isfinite(eps), "non-finite hyper-parameter");
+    REQUIRE(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f, "betas must lie in [0, 1)");
+    if (count == 0) return HG_OK;
+    REQUIRE(tensors != nullptr, "tensors is NULL");
+    hg::AdamMultiK k{};
+    for (int t = 0; t < count; ++t) {
+        const hg_adam_tensor &x = tensors[t];
+        REQUIRE(x.n >= 0 && x.n <= (int64_t(1) << 36), "tensors[%d].n = %lld outside [0, 2^36]", t, (long long)x.n);
+        REQUIRE(std::isfinite(x.weight_decay), "tensors[%d].weight_decay is not finite", t);
+        int kind = 0;
+        if (x.shadow) {
+            REQUIRE(x.shadow_dtype == HG_F16 || x.shadow_dtype == HG_BF16,
+                    "tensors[%d]: shadow dtype must be HG_F16 or HG_BF16", t);
+            kind = x.shadow_dtype == HG_F16 ? 1 : 2;
+        }
+        if (x.n > 0) {
+            CHECK(check_ptr(x.param, "param"));
+            CHECK(check_ptr(x.grad, "grad"));
+            CHECK(check_ptr(x.m, "m"));
+            CHECK(check_ptr(x.v, "v"));
+            if (x.shadow) CHECK(check_ptr(x.shadow, "shadow", 8));
+        }
+        k.param[t] = x.param;
+        k.grad[t] = x.grad;
+        k.m[t] = x.m;
+        k.v[t] = x.v;
+        k.shadow[t] = x.shadow;
+        k.n[t] = x.n;
+        k.wd[t] = x.weight_decay;
+        k.kind[t] = kind;
+    }
+    const double bc1 = 1.0 - std::pow((double)beta1, (double)step);
+    const double bc2 = 1.0 - std::pow((double)beta2, (double)step);
+    REQUIRE(bc1 > 0.0 && bc2 > 0.0, "bias correction vanishes (beta = 0 and step too large?)");
+    k.count = count;
+    k.zero_grad = zero_grad;
+    k.lr = lr;
+    k.b1 = beta1;
+    k.b2 = beta2;
+    k.eps = eps;
+    // the same reciprocals launch_adam forms, so both entry points compute alike
+    k.inv_bc1 = 1.0f / (float)bc1;
+    k.inv_sqrt_bc2 = 1.0f / sqrtf((float)bc2);
+    return hip_status(hg::launch_adam_multi(k, stream), "hg_adam_step_multi");
 }
 
 size_t hg_env_sampling_size(int32_t H, int32_t W) {

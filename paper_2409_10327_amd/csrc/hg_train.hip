@@ -2,6 +2,7 @@
 #include <hip/hip_bf16.h>
 
 #include "hg_launch.h"
+#include "hg_train.h"
 
 namespace hg {
 
@@ -52,13 +53,13 @@ hipError_t launch_l2_loss(const float *rgb, const float *vis, const float *dep, 
 // Adam with bias correction (bc1 = 1 - b1^t, bc2 = 1 - b2^t computed on the
 // host in double); weight decay added to the gradient.  Four parameters per
 // lane with 16-byte accesses; the tail is handled element by element.
+// The update of parameters i0 .. i0 + 3 (fewer at the tail), shared by the
+// single-tensor and the multi-tensor kernels.
 template <int KIND>  // 0: no shadow, 1: FP16 shadow, 2: BF16 shadow
-__global__ __launch_bounds__(256) void k_adam(float *__restrict__ param, const float *__restrict__ grad,
-                                              float *__restrict__ m, float *__restrict__ v, int64_t n, float lr,
-                                              float b1, float b2, float eps, float wd, float inv_bc1,
-                                              float inv_sqrt_bc2, void *__restrict__ shadow) {
-    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
-    if (i0 >= n) return;
+__device__ __forceinline__ void adam_update(float *__restrict__ param, const float *__restrict__ grad,
+                                            float *__restrict__ m, float *__restrict__ v, int64_t n, int64_t i0,
+                                            float lr, float b1, float b2, float eps, float wd, float inv_bc1,
+                                            float inv_sqrt_bc2, void *__restrict__ shadow) {
     const int cnt = (int)((n - i0) < 4 ? (n - i0) : 4);
     float pp[4], gg[4], mm[4], vv[4];
     if (cnt == 4) {
@@ -99,6 +100,56 @@ __global__ __launch_bounds__(256) void k_adam(float *__restrict__ param, const f
         __hip_bfloat16 *sh = static_cast<__hip_bfloat16 *>(shadow);
         for (int k = 0; k < cnt; ++k) sh[i0 + k] = __float2bfloat16(pp[k]);
     }
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256) void k_adam(float *__restrict__ param, const float *__restrict__ grad,
+                                              float *__restrict__ m, float *__restrict__ v, int64_t n, float lr,
+                                              float b1, float b2, float eps, float wd, float inv_bc1,
+                                              float inv_sqrt_bc2, void *__restrict__ shadow) {
+    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (i0 >= n) return;
+    adam_update<KIND>(param, grad, m, v, n, i0, lr, b1, b2, eps, wd, inv_bc1, inv_sqrt_bc2, shadow);
+}
+
+// Several tensors in one launch: tensor t owns blocks block0[t] ..
+// block0[t + 1] - 1 (the block's tensor is wave-uniform); with zero_grad each
+// lane clears the gradients it has read.
+__global__ __launch_bounds__(256) void k_adam_multi(const AdamMultiK a) {
+    int t = 0;
+    for (int k = 1; k < a.count; ++k) t = blockIdx.x >= a.block0[k] ? k : t;
+    const int64_t n = a.n[t];
+    const int64_t i0 = ((int64_t)(blockIdx.x - a.block0[t]) * blockDim.x + threadIdx.x) * 4;
+    if (i0 >= n) return;
+    float *const g = a.grad[t];
+    if (a.kind[t] == 1)
+        adam_update<1>(a.param[t], g, a.m[t], a.v[t], n, i0, a.lr, a.b1, a.b2, a.eps, a.wd[t], a.inv_bc1,
+                       a.inv_sqrt_bc2, a.shadow[t]);
+    else if (a.kind[t] == 2)
+        adam_update<2>(a.param[t], g, a.m[t], a.v[t], n, i0, a.lr, a.b1, a.b2, a.eps, a.wd[t], a.inv_bc1,
+                       a.inv_sqrt_bc2, a.shadow[t]);
+    else
+        adam_update<0>(a.param[t], g, a.m[t], a.v[t], n, i0, a.lr, a.b1, a.b2, a.eps, a.wd[t], a.inv_bc1,
+                       a.inv_sqrt_bc2, a.shadow[t]);
+    if (a.zero_grad) {
+        if (n - i0 >= 4) {
+            *reinterpret_cast<float4 *>(g + i0) = make_float4(0.f, 0.f, 0.f, 0.f);
+        } else {
+            for (int64_t k = i0; k < n; ++k) g[k] = 0.0f;
+        }
+    }
+}
+
+hipError_t launch_adam_multi(AdamMultiK &a, hipStream_t s) {
+    uint32_t b = 0;
+    for (int t = 0; t < a.count; ++t) {
+        a.block0[t] = b;
+        b += (uint32_t)(((a.n[t] + 3) / 4 + 255) / 256);
+    }
+    a.block0[a.count] = b;
+    if (b == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adam_multi, dim3(b), dim3(256), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_adam(float *param, const float *grad, float *m, float *v, int64_t n, float lr, float b1,

@@ -19,7 +19,7 @@ def header_symbols():
 
 def test_library_exports_every_declared_symbol():
     syms = header_symbols()
-    assert len(syms) == 16, syms
+    assert len(syms) == 17, syms
     L = hg.lib()
     for s in syms:
         assert hasattr(L, s), s
@@ -192,6 +192,23 @@ def test_other_entry_points_validate():
     assert L.hg_encode(C.byref(g), None, 0, None, None) == hg.HG_OK
     assert L.hg_encode_index(C.byref(g), C.c_void_p(FAKE), 10, None, None, None) == hg.HG_E_INVALID
     assert L.hg_l2_loss(None, None, None, None, 5, C.c_void_p(FAKE), None, None, None, None) == hg.HG_E_INVALID
+    T = hg.AdamTensor * 2
+    good = hg.AdamTensor(FAKE, FAKE, FAKE, FAKE, 10, 0.0, 0, None)
+    assert L.hg_adam_step_multi(None, 0, 1, 1e-3, 0.9, 0.999, 1e-8, 0, None) == hg.HG_OK
+    assert L.hg_adam_step_multi(None, 2, 1, 1e-3, 0.9, 0.999, 1e-8, 0, None) == hg.HG_E_INVALID
+    assert L.hg_adam_step_multi(T(good, good), -1, 1, 1e-3, 0.9, 0.999, 1e-8, 0, None) == hg.HG_E_INVALID
+    assert L.hg_adam_step_multi(T(good, good), 17, 1, 1e-3, 0.9, 0.999, 1e-8, 0, None) == hg.HG_E_INVALID
+    assert L.hg_adam_step_multi(T(good, good), 2, 0, 1e-3, 0.9, 0.999, 1e-8, 0, None) == hg.HG_E_INVALID
+    assert L.hg_adam_step_multi(T(good, good), 2, 1, 1e-3, 0.9, 0.999, 1e-8, 2, None) == hg.HG_E_INVALID
+    assert L.hg_adam_step_multi(T(good, good), 2, 1, 1e-3, 1.0, 0.999, 1e-8, 0, None) == hg.HG_E_INVALID
+    nul = hg.AdamTensor(None, FAKE, FAKE, FAKE, 10, 0.0, 0, None)
+    assert L.hg_adam_step_multi(T(good, nul), 2, 1, 1e-3, 0.9, 0.999, 1e-8, 0, None) == hg.HG_E_INVALID
+    badsh = hg.AdamTensor(FAKE, FAKE, FAKE, FAKE, 10, 0.0, hg.HG_F32, FAKE)
+    assert L.hg_adam_step_multi(T(good, badsh), 2, 1, 1e-3, 0.9, 0.999, 1e-8, 0, None) == hg.HG_E_INVALID
+    neg = hg.AdamTensor(FAKE, FAKE, FAKE, FAKE, -1, 0.0, 0, None)
+    assert L.hg_adam_step_multi(T(good, neg), 2, 1, 1e-3, 0.9, 0.999, 1e-8, 0, None) == hg.HG_E_INVALID
+    nanwd = hg.AdamTensor(FAKE, FAKE, FAKE, FAKE, 10, float("nan"), 0, None)
+    assert L.hg_adam_step_multi(T(good, nanwd), 2, 1, 1e-3, 0.9, 0.999, 1e-8, 0, None) == hg.HG_E_INVALID
     need = L.hg_morton_order_workspace_size(10)
     assert need > 0 and L.hg_morton_order_workspace_size(0) == 0 and L.hg_morton_order_workspace_size(-1) == 0
     assert L.hg_morton_order_workspace_size(1 << 31) == 0

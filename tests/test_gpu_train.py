@@ -341,3 +341,41 @@ def test_morton_order_is_stable_key_order(n):
 def test_morton_order_empty():
     r = hg.HashRenderer(H.make_model(H.config("c1")), "cuda")
     assert hg.morton_order(r, torch.empty((0, 3), device="cuda")).numel() == 0
+
+
+@pytest.mark.parametrize("zero_grad", [False, True])
+def test_adam_multi_matches_single(zero_grad):
+    """hg_adam_step_multi against hg_adam_step tensor by tensor: parameters,
+    moments and shadows bit-identical over ragged sizes and both shadow
+    types; gradients cleared exactly when asked."""
+    rng = np.random.default_rng(11)
+    sizes = [1, 3, 4, 5, 1000, 4097, 262147]
+    kinds = [None, torch.float16, torch.bfloat16, None, torch.bfloat16, torch.float16, None]
+    def make():
+        out = []
+        for i, (n, k) in enumerate(zip(sizes, kinds)):
+            r = np.random.default_rng(100 + i)
+            p = torch.from_numpy(r.standard_normal(n).astype(np.float32)).cuda()
+            g = torch.from_numpy(r.standard_normal(n).astype(np.float32)).cuda()
+            m = torch.from_numpy(r.standard_normal(n).astype(np.float32) * 0.1).cuda()
+            v = torch.from_numpy(np.abs(r.standard_normal(n)).astype(np.float32) * 0.01).cuda()
+            sh = None if k is None else torch.empty(n, device="cuda", dtype=k)
+            out.append([p, g, m, v, 1e-6 * (i % 2), sh])
+        return out
+    a, b = make(), make()
+    for step in (1, 2):
+        for p, g, m, v, wd, sh in a:
+            hg.adam_step(p, g, m, v, step, lr=2e-3, weight_decay=wd, shadow=sh)
+        gb = [x[1].clone() for x in b]
+        hg.adam_step_multi([tuple(x) for x in b], step, lr=2e-3, zero_grad=zero_grad)
+        torch.cuda.synchronize()
+        for x, y, g0 in zip(a, b, gb):
+            for u, w in zip((x[0], x[2], x[3]), (y[0], y[2], y[3])):
+                assert torch.equal(u, w)
+            if x[5] is not None:
+                assert torch.equal(x[5].view(torch.int16), y[5].view(torch.int16))
+            if zero_grad:
+                assert torch.count_nonzero(y[1]).item() == 0
+                y[1].copy_(g0)  # the next step reuses the same gradients
+            else:
+                assert torch.equal(y[1], g0)
