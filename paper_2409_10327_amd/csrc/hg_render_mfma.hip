@@ -33,8 +33,8 @@
 // path runs two 256-thread blocks per CU with the whole-wave bounce
 // (bounce_lo) and reads its tracer operands from LDS at each use instead of
 // holding them in registers.  The FP32 path, and the mixed one on moderate
-// grids below 256 directions per pixel, raise a wave's issue priority for
-// the tracer's matrix-core steps, so that the vector work of the SIMD's
+// grids below 256 directions per pixel (its bounce tracer only), raise a
+// wave's issue priority for the tracer's matrix-core steps, so that the vector work of the SIMD's
 // other wave fills the matrix pipe's gaps rather than delaying its next
 // step; the priority changes also bound a scheduling region, which is most
 // of their effect.  The mixed path is compiled with and without that fence
@@ -83,9 +83,9 @@ __device__ __forceinline__ WSrc wsrc(const RenderK &a) {
 
 // ============================================================================
 // Mixed path: BF16 operands, K = 32 per matrix-core step.  FENCED: the
-// tracer's matrix-core steps form a scheduling region of their own, at raised
-// issue priority (the launch picks the variant per grid and direction
-// count).
+// bounce tracer's matrix-core steps form a scheduling region of their own,
+// at raised issue priority (the launch picks the variant per grid and
+// direction count).
 // ============================================================================
 template <bool FENCED>
 struct Bf16PathT {
@@ -217,6 +217,9 @@ struct Bf16PathT {
     }
 
     // tracer for N-tile nt from the point part c: returns the head tile
+    // (FENCE: the fenced variant's region and priority; the primary-point
+    // tracer runs without them, measured faster: 33.9 -> 33.5 ms at N = 128)
+    template <bool FENCE>
     static __device__ __forceinline__ f32x4 tracer_nt(const Tracer &T, const Tile *tiles, const Wave &W, int buf, int nt,
                                                       int lane, const f32x4 (&c)[4]) {
         const uint4 ob_ = W.om[buf][16 * nt + (lane & 15)];
@@ -225,7 +228,7 @@ struct Bf16PathT {
         // instead of delaying them (raising it over the decoder and the point
         // part too starved the other wave's encoder: slower); the priority
         // changes also bound a scheduling region, which is most of the effect
-        if constexpr (FENCED) __builtin_amdgcn_s_setprio(1);
+        if constexpr (FENCED && FENCE) __builtin_amdgcn_s_setprio(1);
         f32x4 d[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) d[m] = mfma_bf16(tiles[(T_W0W + m) * 64 + lane], ob_, c[m]);
@@ -239,7 +242,7 @@ struct Bf16PathT {
         const uint4 k0 = act_pack(e[0], e[1]), k1 = act_pack(e[2], e[3]);
         f32x4 o = mfma_bf16(tiles[T_W2 * 64 + lane], k0, ftile(tiles, T_B2, lane));
         o = mfma_bf16(tiles[(T_W2 + 1) * 64 + lane], k1, o);
-        if constexpr (FENCED) __builtin_amdgcn_s_setprio(0);
+        if constexpr (FENCED && FENCE) __builtin_amdgcn_s_setprio(0);
         return o;
     }
 
@@ -336,7 +339,7 @@ struct Bf16PathT {
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
             const f32x4 c[4] = {pp.v[0][nt], pp.v[1][nt], pp.v[2][nt], pp.v[3][nt]};
-            const f32x4 hh = tracer_nt(T, tiles, W, buf, nt, lane, c);
+            const f32x4 hh = tracer_nt<false>(T, tiles, W, buf, nt, lane, c);
             if (g == nt) {
                 o0 = hh[0];
                 o1 = hh[1];
@@ -361,7 +364,7 @@ struct Bf16PathT {
         for (int nt = 0; nt < 4; ++nt) {
             f32x4 c[4];
             point_part_nt(tiles, a, W, nt, lane, g, c);
-            const f32x4 hh = tracer_nt(T, tiles, W, buf, nt, lane, c);
+            const f32x4 hh = tracer_nt<true>(T, tiles, W, buf, nt, lane, c);
             if (g == nt) {
                 o0 = hh[0];
                 o1 = hh[1];
