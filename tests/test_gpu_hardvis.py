@@ -56,10 +56,12 @@ def test_hard_query(c1, precision):
     assert e < (1e-5 if precision == "fp32" else 2e-3)
 
 
-@pytest.mark.parametrize("N,precision", [(4, "fp32"), (32, "fp32"), (128, "fp32"), (4, "mixed"), (128, "mixed")])
+@pytest.mark.parametrize("N,precision", [(4, "fp32"), (32, "fp32"), (128, "fp32"), (4, "mixed"), (128, "mixed"),
+                                         (256, "mixed")])
 def test_hard_shade(c1, N, precision):
     """N = 128 takes the shadow-ray queue (one pixel per wave); N = 32 does
-    not; N = 4 takes the per-lane mode (16 pixels per wave)."""
+    not; N = 4 takes the per-lane mode (16 pixels per wave); mixed N = 256
+    runs the mixed kernel compiled without the tracer's scheduling fence."""
     print(f"case: hard visibility shade N={N} {precision}", flush=True)
     t = c1["t"]
     sl = slice(0, 1024)

@@ -75,7 +75,7 @@ def test_env_distribution(name):
 
 
 @pytest.mark.parametrize("N,precision", [(2, "fp32"), (8, "fp32"), (32, "fp32"), (128, "fp32"), (2, "mixed"),
-                                         (128, "mixed")])
+                                         (128, "mixed"), (256, "mixed")])
 def test_mis_frame(c1, N, precision):
     """N = 2 is the paper's one light ray + one GGX ray; fewer than 16
     directions take the matrix-core kernel's per-lane mode."""
